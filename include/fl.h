@@ -1,0 +1,179 @@
+/*
+ * fl.h - C ABI of the MI355X fitness-flow-graph landscape engine.
+ *
+ * The engine computes, for one discrete search space with a runtime per
+ * configuration, the landscape metric of Schoonhoven, van Werkhoven and
+ * Batenburg, "Benchmarking optimization algorithms for auto-tuning GPU
+ * kernels":
+ *   - the search space X = S_1 x ... x S_n and its valid points   (Sec. III-B)
+ *   - the Hamming (eq. 2) or adjacent neighbourhood                 (Sec. III-B)
+ *   - the fitness flow graph (FFG): an edge from every point to each
+ *     neighbour with strictly lower fitness                          (Sec. VII-B)
+ *   - PageRank centrality of the FFG by power iteration             (Sec. VII-B)
+ *   - the local minima (FFG sinks)                                   (Sec. III-B)
+ *   - the p-proportion of centrality C_p                            (Sec. VII-B, eq. 3)
+ *
+ * Conventions shared by every call:
+ *   - Every call returns fl_status.  No C++ exception crosses the ABI.  On an
+ *     error the context keeps a message, readable with fl_last_error().
+ *   - Pointers named d_* are device pointers (HIP device memory of the
+ *     context's device); every other pointer is a host pointer.
+ *   - All device work is ordered on the context's stream.  Input buffers are
+ *     borrowed for the duration of the call; output buffers are owned by the
+ *     caller.  Calls that return sizes or scores synchronise that stream.
+ *   - A context is not thread-safe: serialise calls that share one.
+ *   - Configurations are numbered in mixed radix with parameter 0 the most
+ *     significant digit: raw index I(x) = sum_i x_i * prod_{j>i} radix_j,
+ *     x_i the position of the value in the list S_i.  Valid points get node
+ *     ids 0..N-1 in ascending raw index.
+ *   - A configuration is a valid point iff its fitness is finite and > 0; the
+ *     caller marks configurations that violate a constraint or failed with
+ *     NaN or +inf.  A fitness <= 0 or -inf is an error (FL_EINVAL).
+ *   - Two fitness values are compared exactly in float32; equal neighbours
+ *     get no edge.  A local minimum is a node with no strictly better
+ *     neighbour, i.e. an FFG sink (isolated valid points included).
+ *   - PageRank is the stationary vector (sum 1) of
+ *       G = d (P + (1/N) 1 s^T) + ((1-d)/N) 1 1^T,
+ *     P[w,u] = 1/out_deg(u) per edge u->w, s the sink indicator: damping d,
+ *     uniform teleport, and the mass of a sink spread uniformly.
+ */
+#ifndef FL_H
+#define FL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FL_OK = 0,
+    FL_EINVAL = -1,     /* invalid argument or fitness value */
+    FL_ENOMEM = -2,     /* device or host allocation failed */
+    FL_EHIP = -3,       /* a HIP runtime call failed */
+    FL_ENOCONV = -4,    /* max_iter reached before the tolerance; outputs still written */
+    FL_EOVERFLOW = -5,  /* n_raw or the edge count is >= 2^31 */
+    FL_EBUSY = -6,      /* reserved for admission control */
+    FL_ENOTIMPL = -7    /* entry point not available in this build */
+} fl_status;
+
+typedef enum {
+    FL_NB_HAMMING = 0,  /* differ in exactly one parameter (Sec. III-B, eq. 2) */
+    FL_NB_ADJACENT = 1  /* ... and that parameter's value is next in its list (Sec. III-B) */
+} fl_neighbourhood;
+
+/* A search space X = S_1 x ... x S_n (Sec. III-B).  radix[i] = |S_i| >= 1,
+ * 1 <= n_params <= 32, prod radix < 2^31.  Host pointer, borrowed. */
+typedef struct {
+    int32_t n_params;
+    const int32_t *radix;
+} fl_space;
+
+/* Analysis parameters.
+ *   damping   d in (0,1); the paper leaves d open, 0.85 is the usual value.
+ *   p         proportion for C_p as a fraction (0.05 = 5 %), p >= 0 and finite.
+ *   tol_l1    stop when ||r_{k+1} - r_k||_1 < tol_l1 (0 => 2e-7).
+ *   max_iter  iteration cap (0 => 1000); reaching it gives FL_ENOCONV.
+ *   row_mapping  lanes per FFG row in the PageRank sweep: 0 = automatic,
+ *             else one of 1, 2, 4, 8, 16, 32, 64. */
+typedef struct {
+    double damping;
+    double p;
+    double tol_l1;
+    int32_t max_iter;
+    int32_t row_mapping;
+} fl_params;
+
+/* Sizes and results of one analysis. */
+typedef struct {
+    int64_t n_raw;       /* prod radix */
+    int64_t n_valid;     /* N, valid points = FFG nodes */
+    int64_t n_edges;     /* E, FFG edges */
+    int64_t n_minima;    /* M, local minima = sinks */
+    int32_t iterations;  /* PageRank iterations run */
+    int32_t row_mapping; /* lanes per row used */
+    double residual_l1;  /* ||r_k - r_{k-1}||_1 of the last iteration */
+    double f_opt;        /* minimum valid fitness */
+    double score;        /* C_p */
+    double mass_minima;  /* sum of PageRank over L(X) */
+    double mass_near;    /* sum of PageRank over L_p(X) */
+} fl_summary;
+
+/* Device time of the phases of the last fl_execute / fl_plan_create on a
+ * plan, from HIP events on the context's stream (milliseconds). */
+typedef struct {
+    double build_ms;     /* compaction, degree count, scan, CSR fill */
+    double pagerank_ms;  /* initialisation + all power iterations, host round trips included */
+    double iterate_ms;   /* device time of the iteration launches alone (sum over chunks) */
+    double score_ms;     /* output of the ranks, minima and C_p */
+    int32_t iterations;  /* iteration kernels that did work */
+    int32_t launches;    /* iteration kernels launched (extra ones exit at once) */
+} fl_timing;
+
+typedef struct fl_ctx fl_ctx;
+typedef struct fl_plan fl_plan;
+
+/* Create a context on HIP device `device`, ordering all work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The stream stays owned by the
+ * caller and must outlive the context. */
+fl_status fl_create(fl_ctx **ctx, int device, void *hip_stream);
+
+/* Release the context and every device buffer it caches.  Plans created on it
+ * must be destroyed first. */
+fl_status fl_destroy(fl_ctx *ctx);
+
+/* Message of the last failed call on ctx (owned by ctx, valid until the next
+ * call).  Never NULL. */
+const char *fl_last_error(const fl_ctx *ctx);
+
+/* Phase 1: build the FFG of a space (Sec. III-B, Sec. VII-B) - compaction of
+ * the valid points, neighbour enumeration, in/out degrees, prefix scan and
+ * CSR fill.  Independent of damping and p.
+ *   d_fitness_raw  device float32[prod radix] in raw order; borrowed.
+ *   out            receives a plan owned by the library (fl_plan_destroy).
+ *   sizes          receives n_raw, n_valid, n_edges, n_minima, f_opt.
+ * Errors: FL_EINVAL (space, neighbourhood, a fitness <= 0 or -inf, no valid
+ * point), FL_EOVERFLOW, FL_ENOMEM, FL_EHIP.  Synchronises the stream. */
+fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitness_raw,
+                         fl_neighbourhood nb, fl_plan **out, fl_summary *sizes);
+
+/* Phase 2: PageRank centrality on the plan's FFG, the local minima and C_p
+ * (Sec. VII-B, eq. 3).
+ *   d_pagerank  device double[N]: centrality of every node, sums to 1.
+ *   d_minima    device int32[M]: node ids of the local minima, ascending.
+ *   out         receives the full summary.
+ * Errors: FL_EINVAL (damping not in (0,1), p < 0 or not finite, tol_l1 < 0,
+ * max_iter < 0, bad row_mapping), FL_ENOCONV (outputs written, summary holds
+ * the residual), FL_ENOMEM, FL_EHIP.  Synchronises the stream. */
+fl_status fl_execute(fl_ctx *ctx, fl_plan *plan, const fl_params *params,
+                     double *d_pagerank, int32_t *d_minima, fl_summary *out);
+
+/* Copy the plan's FFG out (any pointer may be NULL):
+ *   d_valid_raw int32[N]   node id -> raw index
+ *   d_row_ptr   int32[N+1] CSR over in-edges: sources of node w are
+ *   d_col_idx   int32[E]     d_col_idx[d_row_ptr[w] .. d_row_ptr[w+1]), ascending
+ *   d_out_deg   int32[N]   number of strictly better neighbours
+ * Stream-ordered, does not synchronise. */
+fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *plan, int32_t *d_valid_raw,
+                         int32_t *d_row_ptr, int32_t *d_col_idx, int32_t *d_out_deg);
+
+/* Phase timings of the plan's last build and execute (see fl_timing). */
+fl_status fl_plan_timing(fl_ctx *ctx, const fl_plan *plan, fl_timing *out);
+
+/* Release a plan; its device buffers return to the context's cache. */
+fl_status fl_plan_destroy(fl_ctx *ctx, fl_plan *plan);
+
+/* One-shot analysis: fl_plan_create + fl_execute + fl_plan_export of the
+ * node map + fl_plan_destroy.  Output buffers are sized by the upper bound
+ * n_raw = prod radix: d_pagerank double[n_raw], d_minima int32[n_raw],
+ * d_valid_raw int32[n_raw] (may be NULL); only the first N / M entries are
+ * written.  Errors as fl_plan_create and fl_execute. */
+fl_status fl_analyze(fl_ctx *ctx, const fl_space *space, const float *d_fitness_raw,
+                     fl_neighbourhood nb, const fl_params *params, double *d_pagerank,
+                     int32_t *d_minima, int32_t *d_valid_raw, fl_summary *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FL_H */

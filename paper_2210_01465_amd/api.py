@@ -1,0 +1,262 @@
+"""Python binding of the C ABI (include/fl.h): argument marshalling only.
+
+Every step of the analysis runs in the HIP kernels of ``libfl.so``; torch
+provides device memory and the stream.  Function names follow the C entry
+points without the ``fl_`` prefix:
+
+    create / destroy / last_error      fl_create / fl_destroy / fl_last_error
+    plan_create                        fl_plan_create   (build the FFG)
+    execute                            fl_execute       (PageRank, minima, C_p)
+    plan_export / plan_timing          fl_plan_export / fl_plan_timing
+    plan_destroy                       fl_plan_destroy
+    analyze                            fl_analyze       (one shot)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _abi
+
+NEIGHBOURHOODS = {"hamming": _abi.FL_NB_HAMMING, "adjacent": _abi.FL_NB_ADJACENT}
+
+
+class FLError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {_abi.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+def _check(ctx, status: int, where: str, allow=()):
+    if status != _abi.FL_OK and status not in allow:
+        msg = _abi.load().fl_last_error(ctx.handle if ctx else None).decode(errors="replace")
+        raise FLError(status, where, msg)
+    return status
+
+
+def _nb(neighbourhood) -> int:
+    if isinstance(neighbourhood, str):
+        return NEIGHBOURHOODS[neighbourhood]
+    return int(neighbourhood)
+
+
+def _space(radix):
+    arr = (ctypes.c_int32 * len(radix))(*[int(r) for r in radix])
+    sp = _abi.fl_space(len(radix), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)))
+    return sp, arr
+
+
+def _n_raw(radix) -> int:
+    n = 1
+    for r in radix:
+        n *= int(r)
+    return n
+
+
+def _check_fitness(ctx: "Context", radix, fitness_raw: torch.Tensor):
+    # the kernels read prod(radix) floats: the tensor must hold exactly that
+    if not isinstance(fitness_raw, torch.Tensor):
+        raise TypeError("fitness_raw must be a torch tensor")
+    if fitness_raw.dtype != torch.float32 or not fitness_raw.is_cuda:
+        raise TypeError("fitness_raw must be a float32 tensor on the GPU")
+    if fitness_raw.device.index != ctx.device:
+        raise ValueError(f"fitness_raw is on {fitness_raw.device}, context on cuda:{ctx.device}")
+    if not fitness_raw.is_contiguous() or fitness_raw.numel() != _n_raw(radix):
+        raise ValueError(f"fitness_raw must be contiguous with prod(radix) = {_n_raw(radix)} "
+                         f"entries, got {fitness_raw.numel()}")
+
+
+class Context:
+    """An ``fl_ctx`` bound to a device and a torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        lib = _abi.load()
+        self.device = int(device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = ctypes.c_void_p()
+        rc = lib.fl_create(ctypes.byref(self.handle), self.device,
+                           ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != _abi.FL_OK:
+            raise FLError(rc, "fl_create", f"device {self.device}")
+
+    def close(self):
+        if self.handle:
+            _abi.load().fl_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+def destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def last_error(ctx: Context) -> str:
+    return _abi.load().fl_last_error(ctx.handle).decode(errors="replace")
+
+
+@dataclass
+class Plan:
+    ctx: Context
+    handle: ctypes.c_void_p
+    radix: tuple
+    sizes: dict
+
+    @property
+    def n_valid(self) -> int:
+        return int(self.sizes["n_valid"])
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.sizes["n_edges"])
+
+    @property
+    def n_minima(self) -> int:
+        return int(self.sizes["n_minima"])
+
+    def close(self):
+        if self.handle:
+            _abi.load().fl_plan_destroy(self.ctx.handle, self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_create(ctx: Context, radix, fitness_raw: torch.Tensor, neighbourhood="hamming") -> Plan:
+    """Build the FFG of one space (fl_plan_create)."""
+    _check_fitness(ctx, radix, fitness_raw)
+    sp, keep = _space(radix)
+    h = ctypes.c_void_p()
+    sizes = _abi.fl_summary()
+    rc = _abi.load().fl_plan_create(ctx.handle, ctypes.byref(sp),
+                                    ctypes.c_void_p(fitness_raw.data_ptr()), _nb(neighbourhood),
+                                    ctypes.byref(h), ctypes.byref(sizes))
+    _check(ctx, rc, "fl_plan_create")
+    del keep
+    return Plan(ctx, h, tuple(int(r) for r in radix), sizes.as_dict())
+
+
+def _params(damping, p, tol, max_iter, row_mapping):
+    return _abi.fl_params(float(damping), float(p), float(tol), int(max_iter), int(row_mapping))
+
+
+def execute(plan: Plan, damping: float = 0.85, p: float = 0.05, tol: float = 0.0,
+            max_iter: int = 0, row_mapping: int = 0, pagerank: torch.Tensor | None = None,
+            minima: torch.Tensor | None = None, allow_noconv: bool = False):
+    """PageRank, local minima and C_p on a plan (fl_execute).
+
+    Returns (pagerank float64[N], minima int32[M], summary dict).  Output
+    tensors may be passed in (sizes N and M, on the context's device)."""
+    ctx = plan.ctx
+    dev = torch.device("cuda", ctx.device)
+    if pagerank is None:
+        pagerank = torch.empty(plan.n_valid, dtype=torch.float64, device=dev)
+    if minima is None:
+        minima = torch.empty(max(plan.n_minima, 1), dtype=torch.int32, device=dev)
+    if (pagerank.dtype != torch.float64 or pagerank.numel() < plan.n_valid
+            or not pagerank.is_contiguous() or pagerank.device != dev):
+        raise ValueError("pagerank must be a contiguous float64 tensor of >= N entries")
+    if (minima.dtype != torch.int32 or minima.numel() < plan.n_minima
+            or not minima.is_contiguous() or minima.device != dev):
+        raise ValueError("minima must be a contiguous int32 tensor of >= M entries")
+    prm = _params(damping, p, tol, max_iter, row_mapping)
+    out = _abi.fl_summary()
+    rc = _abi.load().fl_execute(ctx.handle, plan.handle, ctypes.byref(prm),
+                                ctypes.c_void_p(pagerank.data_ptr()),
+                                ctypes.c_void_p(minima.data_ptr()), ctypes.byref(out))
+    _check(ctx, rc, "fl_execute", allow=(_abi.FL_ENOCONV,) if allow_noconv else ())
+    info = out.as_dict()
+    info["status"] = rc
+    return pagerank[:plan.n_valid], minima[:plan.n_minima], info
+
+
+def plan_export(plan: Plan) -> dict:
+    """The plan's FFG as device tensors (fl_plan_export)."""
+    ctx = plan.ctx
+    dev = torch.device("cuda", ctx.device)
+    N, E = plan.n_valid, plan.n_edges
+    t = {"valid_raw": torch.empty(N, dtype=torch.int32, device=dev),
+         "row_ptr": torch.empty(N + 1, dtype=torch.int32, device=dev),
+         "col_idx": torch.empty(max(E, 1), dtype=torch.int32, device=dev),
+         "out_deg": torch.empty(N, dtype=torch.int32, device=dev)}
+    rc = _abi.load().fl_plan_export(ctx.handle, plan.handle,
+                                    *[ctypes.c_void_p(t[k].data_ptr())
+                                      for k in ("valid_raw", "row_ptr", "col_idx", "out_deg")])
+    _check(ctx, rc, "fl_plan_export")
+    t["col_idx"] = t["col_idx"][:E]
+    return t
+
+
+def plan_timing(plan: Plan) -> dict:
+    out = _abi.fl_timing()
+    rc = _abi.load().fl_plan_timing(plan.ctx.handle, plan.handle, ctypes.byref(out))
+    _check(plan.ctx, rc, "fl_plan_timing")
+    return out.as_dict()
+
+
+def plan_destroy(plan: Plan) -> None:
+    plan.close()
+
+
+@dataclass
+class Result:
+    pagerank: torch.Tensor   # float64[N]
+    minima: torch.Tensor     # int32[M], ascending node ids
+    valid_raw: torch.Tensor  # int32[N], node id -> raw index
+    score: float
+    info: dict
+
+
+def analyze(radix, fitness_raw: torch.Tensor, neighbourhood="hamming", damping: float = 0.85,
+            p: float = 0.05, tol: float = 0.0, max_iter: int = 0, row_mapping: int = 0,
+            ctx: Context | None = None, allow_noconv: bool = False) -> Result:
+    """One-shot analysis of one space (fl_analyze)."""
+    own = ctx is None
+    if own:
+        ctx = Context(fitness_raw.device.index or 0)
+    try:
+        _check_fitness(ctx, radix, fitness_raw)
+        n_raw = _n_raw(radix)
+        dev = fitness_raw.device
+        pr = torch.empty(n_raw, dtype=torch.float64, device=dev)
+        mins = torch.empty(n_raw, dtype=torch.int32, device=dev)
+        vraw = torch.empty(n_raw, dtype=torch.int32, device=dev)
+        sp, keep = _space(radix)
+        prm = _params(damping, p, tol, max_iter, row_mapping)
+        out = _abi.fl_summary()
+        rc = _abi.load().fl_analyze(ctx.handle, ctypes.byref(sp),
+                                    ctypes.c_void_p(fitness_raw.data_ptr()), _nb(neighbourhood),
+                                    ctypes.byref(prm), ctypes.c_void_p(pr.data_ptr()),
+                                    ctypes.c_void_p(mins.data_ptr()),
+                                    ctypes.c_void_p(vraw.data_ptr()), ctypes.byref(out))
+        _check(ctx, rc, "fl_analyze", allow=(_abi.FL_ENOCONV,) if allow_noconv else ())
+        del keep
+        info = out.as_dict()
+        info["status"] = rc
+        N, M = int(out.n_valid), int(out.n_minima)
+        return Result(pr[:N], mins[:M], vraw[:N], float(out.score), info)
+    finally:
+        if own:
+            ctx.close()

@@ -1,0 +1,85 @@
+// fl_internal.h - types shared by the engine (fl_engine.hip) and the gfx950
+// kernels (fl_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fl {
+
+constexpr int kMaxParams = 32;
+constexpr int kBlock = 256;                       // threads per workgroup (4 waves of 64)
+constexpr int kCompactItems = 8;                  // raw configurations per thread in compaction
+constexpr int kCompactTile = kBlock * kCompactItems;
+constexpr int kXcds = 8;                          // MI355X: 8 XCDs, workgroups dealt round-robin
+
+// Mixed-radix description of a search space X = S_1 x ... x S_n, parameter 0
+// most significant: stride[i] = prod_{j>i} radix[j].  Passed by value.
+struct SpaceDesc {
+    int32_t n;
+    int32_t n_raw;
+    int32_t radix[kMaxParams];
+    int32_t stride[kMaxParams];
+};
+
+// Sizes produced on the device by the build scans, copied to the host once.
+struct BuildSizes {
+    int32_t n_valid;
+    int32_t n_bad;       // fitness <= 0 or -inf
+    float f_opt;         // minimum valid fitness
+    int32_t n_minima;
+    int64_t n_edges;
+};
+
+// Power-iteration state, device resident.  The stored iterate y_k is the
+// normalised rank vector up to the factor s = 1/sum(y_k).
+struct PrState {
+    int32_t k;           // iterations completed
+    int32_t done;        // 0 running, 1 converged, 2 iteration cap reached
+    uint32_t ticket;     // last-workgroup election, reset by the elected one
+    int32_t worked;      // iteration launches that did work
+    double s;            // 1 / sum(y_k)
+    double c;            // d*(sink mass)/N + (1-d)/N for the next iteration
+    double sigma;        // sum(y_k)
+    double resid;        // ||r_k - r_{k-1}||_1
+    double resid_prev;
+    double sink;         // sum of y_k over sinks
+    double score_num;    // sum of ranks over L_p
+    double score_den;    // sum of ranks over L
+};
+
+struct PrArgs {
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const int32_t *out_deg;
+    float *y[2];         // ping-pong iterate, slot k&1 holds y_k
+    float *x[2];         // y / out_deg (0 at sinks), same slots
+    double *partials;    // 3 * grid doubles: per-workgroup sums
+    PrState *st;
+    int32_t n;           // N
+    double d;            // damping
+    double tol;
+    int32_t max_iter;
+};
+
+// ---- launchers (fl_kernels.hip); all enqueue on `stream` ----
+hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, float *tile_min,
+                          int32_t *tile_bad, int32_t *tile_off, int32_t *remap,
+                          int32_t *valid_raw, float *fit_c, BuildSizes *sizes,
+                          hipStream_t stream);
+hipError_t launch_degree(const SpaceDesc &sp, int adjacent, const float *fit,
+                         const int32_t *valid_raw, int32_t n, int32_t *in_deg, int32_t *out_deg,
+                         int64_t *tile_e, int32_t *tile_m, int64_t *tile_eoff,
+                         int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream);
+hipError_t launch_fill(const SpaceDesc &sp, int adjacent, const float *fit,
+                       const int32_t *valid_raw, const int32_t *remap, int32_t n, int32_t n_edges,
+                       const int32_t *in_deg, const int32_t *out_deg, const int64_t *tile_eoff,
+                       const int32_t *tile_moff, int32_t *row_ptr, int32_t *col_idx,
+                       int32_t *minima, hipStream_t stream);
+hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream);
+hipError_t launch_pr_iter(const PrArgs &a, int lanes, int grid, hipStream_t stream);
+hipError_t launch_pr_output(const PrArgs &a, double *pagerank, hipStream_t stream);
+hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m,
+                        const float *fit_c, double threshold, PrState *st, hipStream_t stream);
+
+}  // namespace fl
