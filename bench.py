@@ -9,9 +9,11 @@ vector is resident in HBM before the timed region.
 
 value = FFG+PageRank edges traversed per second over the timed steps,
         sum(E * iterations) / wall time, in GTEPS.
-roofline = the PageRank iteration kernel: (20 N + 8 E) algorithmic bytes per
-        launch over its mean launch duration (HIP events on the engine's
-        stream, summed over the timed steps), against 8 TB/s HBM.
+roofline = the PageRank iteration kernel: its algorithmic bytes per launch
+        ((20 + 8 W) N + 4 E for the slot sweep with W mask words per node,
+        20 N + 8 E for the CSR sweep) over its mean launch duration (HIP
+        events on the engine's stream, summed over the timed steps), against
+        8 TB/s HBM.
 cpu_baseline = the FP64 oracle on the same space at the same tolerance,
         single-threaded on the host.
 """
@@ -79,6 +81,9 @@ def main():
     ap.add_argument("--row-mapping", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes five times "
+                         "(calibrates the HBM byte counters of a profiler)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -90,6 +95,16 @@ def main():
     import numpy as np
     import torch
     from paper_2210_01465_amd import api
+
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": 5}), flush=True)
+        return
 
     damping, p, tol = 0.85, 0.05, 2e-7
     space = workload(args.workload)
@@ -128,10 +143,15 @@ def main():
     launches = sum(t["launches"] for t in timings)
     iter_ms = sum(t["iterate_ms"] for t in timings)
     avg_launch_s = iter_ms / 1e3 / launches
-    bytes_per_launch = 20 * N + 8 * E
+    if info["row_mapping"] == -1:   # slot sweep: valid_raw, masks, y in/out, out_deg, x out; x gathers
+        bytes_per_launch = (20 + 8 * info["mask_words"]) * N + 4 * E
+        kernel = f"k_pr_iter_slots<{'true' if args.neighbourhood == 'adjacent' else 'false'}, {info['mask_words']}>"
+    else:                           # CSR sweep: row_ptr, out_deg, y in/out, x out, col_idx, x gathers
+        bytes_per_launch = 20 * N + 8 * E
+        kernel = f"k_pr_iter_csr<{info['row_mapping']}>"
     achieved = bytes_per_launch / avg_launch_s / 1e9
     traffic = measured_traffic()
-    alg_bytes = (8 * n_raw + 36 * N + 4 * E) + info["iterations"] * (20 * N + 8 * E) + 12 * M
+    alg_bytes = (8 * n_raw + 36 * N + 4 * E) + info["iterations"] * bytes_per_launch + 12 * M
     step_s = wall / args.steps
 
     out = {
@@ -154,7 +174,7 @@ def main():
                    "iterations": info["iterations"], "row_mapping": info["row_mapping"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_pr_iter",
+                     "traffic": traffic, "kernel": kernel,
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": round(avg_launch_s * 1e6, 3)},
         "phases_ms": {k: round(float(np.mean([t[k] for t in timings])), 4)

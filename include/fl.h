@@ -74,8 +74,11 @@ typedef struct {
  *   p         proportion for C_p as a fraction (0.05 = 5 %), p >= 0 and finite.
  *   tol_l1    stop when ||r_{k+1} - r_k||_1 < tol_l1 (0 => 2e-7).
  *   max_iter  iteration cap (0 => 1000); reaching it gives FL_ENOCONV.
- *   row_mapping  lanes per FFG row in the PageRank sweep: 0 = automatic,
- *             else one of 1, 2, 4, 8, 16, 32, 64. */
+ *   row_mapping  layout of the PageRank sweep: 0 = automatic; FL_ROWS_SLOTS =
+ *             one node per lane over the in-edge slot masks (needs at most 128
+ *             candidate slots per node); 1, 2, 4, 8, 16, 32 or 64 = that many
+ *             lanes per row over the CSR. */
+#define FL_ROWS_SLOTS (-1)
 typedef struct {
     double damping;
     double p;
@@ -91,7 +94,9 @@ typedef struct {
     int64_t n_edges;     /* E, FFG edges */
     int64_t n_minima;    /* M, local minima = sinks */
     int32_t iterations;  /* PageRank iterations run */
-    int32_t row_mapping; /* lanes per row used */
+    int32_t row_mapping; /* sweep layout used (FL_ROWS_SLOTS or lanes per CSR row) */
+    int32_t n_slots;     /* K, candidate neighbour slots per node */
+    int32_t mask_words;  /* 64-bit in-edge mask words per node (0: K > 128, CSR sweep only) */
     double residual_l1;  /* ||r_k - r_{k-1}||_1 of the last iteration */
     double f_opt;        /* minimum valid fitness */
     double score;        /* C_p */
@@ -143,7 +148,8 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
  *   d_minima    device int32[M]: node ids of the local minima, ascending.
  *   out         receives the full summary.
  * Errors: FL_EINVAL (damping not in (0,1), p < 0 or not finite, tol_l1 < 0,
- * max_iter < 0, bad row_mapping), FL_ENOCONV (outputs written, summary holds
+ * max_iter < 0, bad row_mapping or FL_ROWS_SLOTS on a space with more than
+ * 128 candidate slots), FL_ENOCONV (outputs written, summary holds
  * the residual), FL_ENOMEM, FL_EHIP.  Synchronises the stream. */
 fl_status fl_execute(fl_ctx *ctx, fl_plan *plan, const fl_params *params,
                      double *d_pagerank, int32_t *d_minima, fl_summary *out);

@@ -11,7 +11,10 @@ import os
 
 import torch  # noqa: F401  (load torch's HIP runtime before libfl.so)
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfl.so")
+# FL_LIBRARY selects another build of the engine (for example one compiled
+# with different -D options); by default the in-tree libfl.so is used.
+LIB_PATH = os.environ.get("FL_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                        "libfl.so")
 
 FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENOCONV, FL_EOVERFLOW, FL_EBUSY, FL_ENOTIMPL = (
     0, -1, -2, -3, -4, -5, -6, -7)
@@ -32,7 +35,8 @@ class fl_params(ctypes.Structure):
 class fl_summary(ctypes.Structure):
     _fields_ = [("n_raw", ctypes.c_int64), ("n_valid", ctypes.c_int64), ("n_edges", ctypes.c_int64),
                 ("n_minima", ctypes.c_int64), ("iterations", ctypes.c_int32),
-                ("row_mapping", ctypes.c_int32), ("residual_l1", ctypes.c_double),
+                ("row_mapping", ctypes.c_int32), ("n_slots", ctypes.c_int32),
+                ("mask_words", ctypes.c_int32), ("residual_l1", ctypes.c_double),
                 ("f_opt", ctypes.c_double), ("score", ctypes.c_double),
                 ("mass_minima", ctypes.c_double), ("mass_near", ctypes.c_double)]
 

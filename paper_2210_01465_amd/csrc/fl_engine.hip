@@ -111,9 +111,13 @@ struct fl_plan {
     int32_t *col_idx = nullptr;
     int32_t *minima = nullptr;
     float *fit_c = nullptr;
+    uint64_t *rec = nullptr;    // node records (in-edge slot bits, out_deg, raw index)
+    uint64_t *presence = nullptr;  // per wave of 64 nodes: OR of their slot bits
+    fl::SlotTable sl{};
     // power-iteration working set, allocated by the first fl_execute
     float *y[2] = {nullptr, nullptr};
     float *x[2] = {nullptr, nullptr};
+    int64_t x_cap = 0;          // entries of each x buffer
     double *partials = nullptr;
     PrState *state = nullptr;
     int pr_grid = 0;
@@ -149,7 +153,7 @@ T *pool_alloc(fl_ctx *ctx, int64_t count) {
 
 void release_plan_buffers(fl_plan *p) {
     DevicePool &pool = p->ctx->pool;
-    void *bufs[] = {p->valid_raw, p->out_deg, p->row_ptr, p->col_idx, p->minima, p->fit_c,
+    void *bufs[] = {p->valid_raw, p->out_deg, p->row_ptr, p->col_idx, p->minima, p->fit_c, p->rec, p->presence,
                     p->y[0],      p->y[1],    p->x[0],    p->x[1],    p->partials, p->state};
     for (void *b : bufs) pool.release(b);
 }
@@ -164,6 +168,53 @@ int auto_lanes(int64_t n, int64_t e) {
 }
 
 bool valid_lanes(int l) { return l == 1 || l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64; }
+
+// q / d == (q * m) >> (32 + l) for every q < 2^31, with l = ceil(log2 d) and
+// m = ceil(2^(32+l) / d) < 2^34 (Granlund and Montgomery, "Division by
+// invariant integers using multiplication", 1994, Thm. 4.2).
+void set_magic(SpaceDesc &sp) {
+    for (int k = 0; k < sp.n; ++k) {
+        const uint64_t d = (uint64_t)sp.radix[k];
+        uint32_t l = 0;
+        while ((uint64_t(1) << l) < d) ++l;
+        const uint32_t sh = 32 + l;
+        const unsigned __int128 num = (unsigned __int128)1 << sh;
+        sp.magic[k] = (uint64_t)((num + d - 1) / d);
+        sp.shift[k] = sh;
+    }
+}
+
+// Candidate slots sorted by raw-index offset: Hamming gives parameter k the
+// deltas +-1 .. +-(radix_k - 1), adjacent +-1.  A node record holds the slot
+// bits plus 40 bits of out_deg and raw index, in at most fl::kMaxWords words.
+fl::SlotTable make_slots(const SpaceDesc &sp, bool adjacent) {
+    fl::SlotTable t{};
+    int64_t total = 0;
+    for (int k = 0; k < sp.n; ++k) total += adjacent ? (sp.radix[k] > 1 ? 2 : 0) : 2 * ((int64_t)sp.radix[k] - 1);
+    t.k = (int32_t)std::min<int64_t>(total, INT32_MAX);
+    const int64_t words = (total + 40 + 63) / 64;
+    if (total > fl::kMaxSlots || words > fl::kMaxWords) {
+        t.words = 0;
+        return t;
+    }
+    t.words = (int32_t)words;
+    struct Slot { int64_t off; int delta, dim; };
+    std::vector<Slot> slots;
+    for (int k = 0; k < sp.n; ++k) {
+        const int reach = adjacent ? std::min(1, sp.radix[k] - 1) : sp.radix[k] - 1;
+        for (int dl = 1; dl <= reach; ++dl) {
+            slots.push_back({-(int64_t)dl * sp.stride[k], -dl, k});
+            slots.push_back({(int64_t)dl * sp.stride[k], dl, k});
+        }
+    }
+    std::sort(slots.begin(), slots.end(), [](const Slot &x, const Slot &y) { return x.off < y.off; });
+    for (size_t s = 0; s < slots.size(); ++s) {
+        t.off[s] = (int32_t)slots[s].off;
+        t.delta[s] = (int16_t)slots[s].delta;
+        t.dim[s] = (uint8_t)slots[s].dim;
+    }
+    return t;
+}
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.0f;
@@ -240,6 +291,7 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
     }
     for (int i = sp.n - 1; i >= 0; --i) sp.stride[i] = (i == sp.n - 1) ? 1 : sp.stride[i + 1] * sp.radix[i + 1];
     sp.n_raw = (int32_t)n_raw;
+    set_magic(sp);
     FL_HIP(hipSetDevice(ctx->device));
 
     fl_plan *p = new (std::nothrow) fl_plan;
@@ -247,6 +299,7 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
     p->ctx = ctx;
     p->sp = sp;
     p->adjacent = (nb == FL_NB_ADJACENT);
+    p->sl = make_slots(sp, p->adjacent);
     p->n_raw = n_raw;
     for (auto &e : p->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
@@ -307,12 +360,17 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
     p->out_deg = pool_alloc<int32_t>(ctx, n);
     p->row_ptr = pool_alloc<int32_t>(ctx, (int64_t)n + 1);
     p->minima = pool_alloc<int32_t>(ctx, n);
+    if (p->sl.words > 0) {
+        p->rec = pool_alloc<uint64_t>(ctx, (int64_t)n * p->sl.words);
+        p->presence = pool_alloc<uint64_t>(ctx, ((int64_t)n + 63) / 64 * p->sl.words);
+    }
     for (void *b : scratch)
         if (!b) return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
-    if (!p->out_deg || !p->row_ptr || !p->minima) return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
+    if (!p->out_deg || !p->row_ptr || !p->minima || (p->sl.words > 0 && (!p->rec || !p->presence)))
+        return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
 
-    he = fl::launch_degree(sp, p->adjacent, d_fitness_raw, p->valid_raw, n, in_deg, p->out_deg, tile_e, tile_m,
-                           tile_eoff, tile_moff, d_sizes, s);
+    he = fl::launch_degree(sp, p->sl, p->adjacent, d_fitness_raw, p->valid_raw, n, in_deg, p->out_deg, p->rec,
+                           p->presence, tile_e, tile_m, tile_eoff, tile_moff, d_sizes, s);
     if (he == hipSuccess) he = hipMemcpyAsync(ctx->h_sizes, d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (he != hipSuccess) return cleanup(fail(ctx, FL_EHIP, "degree count: %s", hipGetErrorString(he)));
@@ -323,8 +381,8 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
     p->col_idx = pool_alloc<int32_t>(ctx, e);
     if (!p->col_idx) return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
 
-    he = fl::launch_fill(sp, p->adjacent, d_fitness_raw, p->valid_raw, remap, n, (int32_t)e, in_deg, p->out_deg,
-                         tile_eoff, tile_moff, p->row_ptr, p->col_idx, p->minima, s);
+    he = fl::launch_fill(sp, p->sl, p->adjacent, d_fitness_raw, p->valid_raw, remap, p->rec, n, (int32_t)e,
+                         in_deg, p->out_deg, tile_eoff, tile_moff, p->row_ptr, p->col_idx, p->minima, s);
     if (he == hipSuccess) he = hipEventRecord(p->ev[1], s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (he != hipSuccess) return cleanup(fail(ctx, FL_EHIP, "CSR fill: %s", hipGetErrorString(he)));
@@ -336,6 +394,8 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
         sizes->n_valid = p->n;
         sizes->n_edges = p->e;
         sizes->n_minima = p->m;
+        sizes->n_slots = p->sl.k;
+        sizes->mask_words = p->sl.words;
         sizes->f_opt = (double)p->f_opt;
     }
     *out = p;
@@ -353,27 +413,43 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     if (!(prm->p >= 0.0) || !isfinite(prm->p)) return fail(ctx, FL_EINVAL, "p must be finite and >= 0");
     if (!(prm->tol_l1 >= 0.0) || !isfinite(prm->tol_l1)) return fail(ctx, FL_EINVAL, "tol_l1 must be finite and >= 0");
     if (prm->max_iter < 0) return fail(ctx, FL_EINVAL, "max_iter must be >= 0");
-    if (prm->row_mapping != 0 && !valid_lanes(prm->row_mapping))
-        return fail(ctx, FL_EINVAL, "row_mapping must be 0 or a power of two <= 64");
+    if (prm->row_mapping != 0 && prm->row_mapping != FL_ROWS_SLOTS && !valid_lanes(prm->row_mapping))
+        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS or a power of two <= 64");
+    if (prm->row_mapping == FL_ROWS_SLOTS && p->sl.words == 0)
+        return fail(ctx, FL_EINVAL, "the slot sweep needs at most %d candidate slots (space has %d)",
+                    fl::kMaxSlots, p->sl.k);
     const double tol = prm->tol_l1 > 0.0 ? prm->tol_l1 : 2e-7;
     const int32_t max_iter = prm->max_iter > 0 ? prm->max_iter : 1000;
-    const int lanes = prm->row_mapping ? prm->row_mapping : auto_lanes(p->n, p->e);
+    int lanes = prm->row_mapping;
+    if (lanes == 0) lanes = p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e);
+    const int kind = lanes == FL_ROWS_SLOTS ? fl::kSweepSlots : fl::kSweepCsr;
     FL_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
 
-    // persistent grid: a multiple of the XCD count, at most 8 workgroups per CU
-    const int64_t rows_per_wg = fl::kBlock / lanes;
+    PrArgs a{};
+    a.kind = kind;
+    a.adjacent = p->adjacent;
+    // persistent grid: every workgroup resident at once (occupancy query), a
+    // multiple of the XCD count so each XCD gets the same number of them
+    int per_cu = 0;
+    FL_HIP(fl::pr_iter_blocks_per_cu(a, p->sp, p->sl, lanes, &per_cu));
+    const int64_t resident = std::max<int64_t>(fl::kXcds, (int64_t)std::max(per_cu, 1) * ctx->num_cus / fl::kXcds * fl::kXcds);
+    const int64_t rows_per_wg = kind == fl::kSweepSlots ? fl::kBlock : fl::kBlock / lanes;
     const int64_t groups = (p->n + rows_per_wg - 1) / rows_per_wg;
-    int grid = (int)std::min<int64_t>(groups, (int64_t)ctx->num_cus * 8);
-    grid = std::max(fl::kXcds, (grid + fl::kXcds - 1) / fl::kXcds * fl::kXcds);
+    const int grid = (int)std::min<int64_t>(resident, (groups + fl::kXcds - 1) / fl::kXcds * fl::kXcds);
+    const int64_t x_need = kind == fl::kSweepSlots ? p->n_raw : p->n;
     if (!p->state) {
-        for (int j = 0; j < 2; ++j) {
-            p->y[j] = pool_alloc<float>(ctx, p->n);
-            p->x[j] = pool_alloc<float>(ctx, p->n);
-        }
+        for (int j = 0; j < 2; ++j) p->y[j] = pool_alloc<float>(ctx, p->n);
         p->state = pool_alloc<PrState>(ctx, 1);
-        if (!p->y[0] || !p->y[1] || !p->x[0] || !p->x[1] || !p->state)
-            return fail(ctx, FL_ENOMEM, "device allocation failed");
+        if (!p->y[0] || !p->y[1] || !p->state) return fail(ctx, FL_ENOMEM, "device allocation failed");
+    }
+    if (x_need > p->x_cap) {
+        for (int j = 0; j < 2; ++j) {
+            ctx->pool.release(p->x[j]);
+            p->x[j] = pool_alloc<float>(ctx, x_need);
+        }
+        if (!p->x[0] || !p->x[1]) return fail(ctx, FL_ENOMEM, "device allocation failed");
+        p->x_cap = x_need;
     }
     // the init and iteration kernels each write 3 partial sums per workgroup
     const int init_grid = (int)std::min<int64_t>((p->n + fl::kBlock - 1) / fl::kBlock, (int64_t)ctx->num_cus * 4);
@@ -384,10 +460,13 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
         if (!p->partials) return fail(ctx, FL_ENOMEM, "device allocation failed");
         p->pr_grid = need;
     }
-    PrArgs a{};
     a.row_ptr = p->row_ptr;
     a.col_idx = p->col_idx;
     a.out_deg = p->out_deg;
+    a.valid_raw = p->valid_raw;
+    a.rec = p->rec;
+    a.presence = p->presence;
+    a.x_bytes = (kind == fl::kSweepSlots && 4 * p->n_raw < (int64_t(1) << 31)) ? (int32_t)(4 * p->n_raw) : 0;
     a.y[0] = p->y[0];
     a.y[1] = p->y[1];
     a.x[0] = p->x[0];
@@ -412,7 +491,7 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     PrState *hs = ctx->h_state;
     for (;;) {
         FL_HIP(hipEventRecord(p->ev[5], s));
-        for (int j = 0; j < chunk; ++j) FL_HIP(fl::launch_pr_iter(a, lanes, grid, s));
+        for (int j = 0; j < chunk; ++j) FL_HIP(fl::launch_pr_iter(a, p->sp, p->sl, lanes, grid, s));
         FL_HIP(hipEventRecord(p->ev[6], s));
         launches += chunk;
         FL_HIP(hipMemcpyAsync(hs, p->state, sizeof(PrState), hipMemcpyDeviceToHost, s));
@@ -450,6 +529,8 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
         out->n_minima = p->m;
         out->iterations = hs->k;
         out->row_mapping = lanes;
+        out->n_slots = p->sl.k;
+        out->mask_words = p->sl.words;
         out->residual_l1 = hs->resid;
         out->f_opt = (double)p->f_opt;
         out->mass_minima = hs->score_den;

@@ -8,18 +8,44 @@
 namespace fl {
 
 constexpr int kMaxParams = 32;
+constexpr int kMaxSlots = 256;                    // candidate slots a node record can hold
+constexpr int kMaxWords = 5;                      // 64-bit words per node record
 constexpr int kBlock = 256;                       // threads per workgroup (4 waves of 64)
 constexpr int kCompactItems = 8;                  // raw configurations per thread in compaction
 constexpr int kCompactTile = kBlock * kCompactItems;
 constexpr int kXcds = 8;                          // MI355X: 8 XCDs, workgroups dealt round-robin
+constexpr int kBatch = 16;                        // candidate slots whose loads are issued together
 
 // Mixed-radix description of a search space X = S_1 x ... x S_n, parameter 0
-// most significant: stride[i] = prod_{j>i} radix[j].  Passed by value.
+// most significant: stride[i] = prod_{j>i} radix[j].  Digits are peeled off
+// from the least significant end with q / radix = (q * magic) >> shift, exact
+// for every q < 2^31 (Granlund-Montgomery with a 33-bit multiplier).
 struct SpaceDesc {
     int32_t n;
     int32_t n_raw;
     int32_t radix[kMaxParams];
     int32_t stride[kMaxParams];
+    uint64_t magic[kMaxParams];
+    uint32_t shift[kMaxParams];
+};
+
+// Candidate neighbour slots, numbered independently of the node: slot s moves
+// parameter dim[s] by delta[s] list positions, i.e. to raw index i + off[s]
+// with off[s] = delta[s] * stride[dim[s]].  Hamming (eq. 2) gives parameter k
+// the 2(radix_k - 1) deltas +-1 .. +-(radix_k - 1); adjacent gives +-1.  A
+// slot exists for a node iff 0 <= x_k + delta < radix_k.  Slots are sorted by
+// off, so ascending slot order is ascending neighbour raw index (= node id).
+//
+// Node record (words x 64 bits): bits [0, k) flag the slots that are in-edges
+// of the node; in the last word, bits 24..31 hold out_deg and bits 32..63 the
+// raw index.  words = 0 when k + 40 > 64 * kMaxWords (then only the generic
+// kernels and the CSR sweep are used).
+struct SlotTable {
+    int32_t k;
+    int32_t words;
+    int32_t off[kMaxSlots];
+    int16_t delta[kMaxSlots];
+    uint8_t dim[kMaxSlots];
 };
 
 // Sizes produced on the device by the build scans, copied to the host once.
@@ -48,18 +74,30 @@ struct PrState {
     double score_den;    // sum of ranks over L
 };
 
+// Row formats of the PageRank sweep.
+enum SweepKind : int32_t {
+    kSweepCsr = 0,   // pull over the CSR, L lanes per row, x indexed by node id
+    kSweepSlots = 1  // pull over the in-edge slot masks, x indexed by raw index
+};
+
 struct PrArgs {
     const int32_t *row_ptr;
     const int32_t *col_idx;
     const int32_t *out_deg;
-    float *y[2];         // ping-pong iterate, slot k&1 holds y_k
-    float *x[2];         // y / out_deg (0 at sinks), same slots
-    double *partials;    // 3 * grid doubles: per-workgroup sums
+    const int32_t *valid_raw;
+    const uint64_t *rec;    // node records (SlotTable), slot sweep only
+    const uint64_t *presence;  // per wave of 64 nodes: OR of their in-edge slot bits
+    float *y[2];            // ping-pong iterate (node ids), slot k&1 holds y_k
+    float *x[2];            // y / out_deg (0 at sinks): node ids (CSR) or raw indices (slots)
+    double *partials;       // 3 * grid doubles: per-workgroup sums
     PrState *st;
-    int32_t n;           // N
-    double d;            // damping
+    int32_t n;              // N
+    int32_t kind;           // SweepKind
+    double d;               // damping
     double tol;
     int32_t max_iter;
+    int32_t adjacent;
+    int32_t x_bytes;        // bytes of each x buffer when < 2^31 (slot sweep uses buffer loads), else 0
 };
 
 // ---- launchers (fl_kernels.hip); all enqueue on `stream` ----
@@ -67,17 +105,21 @@ hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, fl
                           int32_t *tile_bad, int32_t *tile_off, int32_t *remap,
                           int32_t *valid_raw, float *fit_c, BuildSizes *sizes,
                           hipStream_t stream);
-hipError_t launch_degree(const SpaceDesc &sp, int adjacent, const float *fit,
+hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                          const int32_t *valid_raw, int32_t n, int32_t *in_deg, int32_t *out_deg,
-                         int64_t *tile_e, int32_t *tile_m, int64_t *tile_eoff,
-                         int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream);
-hipError_t launch_fill(const SpaceDesc &sp, int adjacent, const float *fit,
-                       const int32_t *valid_raw, const int32_t *remap, int32_t n, int32_t n_edges,
-                       const int32_t *in_deg, const int32_t *out_deg, const int64_t *tile_eoff,
-                       const int32_t *tile_moff, int32_t *row_ptr, int32_t *col_idx,
-                       int32_t *minima, hipStream_t stream);
+                         uint64_t *rec, uint64_t *presence, int64_t *tile_e, int32_t *tile_m,
+                         int64_t *tile_eoff, int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream);
+hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
+                       const int32_t *valid_raw, const int32_t *remap, const uint64_t *rec,
+                       int32_t n, int32_t n_edges, const int32_t *in_deg, const int32_t *out_deg,
+                       const int64_t *tile_eoff, const int32_t *tile_moff, int32_t *row_ptr,
+                       int32_t *col_idx, int32_t *minima, hipStream_t stream);
 hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream);
-hipError_t launch_pr_iter(const PrArgs &a, int lanes, int grid, hipStream_t stream);
+hipError_t launch_pr_iter(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
+                          int grid, hipStream_t stream);
+// Workgroups of the sweep kernel for this layout that fit on one CU at once.
+hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
+                                 int *blocks);
 hipError_t launch_pr_output(const PrArgs &a, double *pagerank, hipStream_t stream);
 hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m,
                         const float *fit_c, double threshold, PrState *st, hipStream_t stream);

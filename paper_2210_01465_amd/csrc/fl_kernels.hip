@@ -9,10 +9,13 @@
 //   power iteration PageRank centrality of the FFG                    (Sec. VII-B)
 //   score           p-proportion of centrality C_p                   (Sec. VII-B, eq. 3)
 //
-// All of it is integer or memory-bound work: no dense contraction exists on
-// this path, so nothing here uses MFMA.  The kernels are written for 64-wide
-// waves and 256-thread workgroups; the iteration kernel maps contiguous row
-// ranges to each XCD so that the x gathers of one row range stay in one L2.
+// No step is a dense contraction, so nothing here uses MFMA: every kernel is
+// bound by memory traffic.  The space is mixed-radix, so the neighbours of a
+// node sit at fixed offsets in raw-index space.  The node kernels therefore
+// run one node per lane with the 64 lanes of a wave on consecutive valid
+// points, and walk the candidate slots in the same order in every lane: each
+// slot becomes one near-contiguous gather for the whole wave, and the loads of
+// kBatch slots are issued back to back before any of them is used.
 #include <math.h>
 
 #include "fl_internal.h"
@@ -119,6 +122,79 @@ __device__ T scan_tiles(const T *in, T *out, int n_tiles) {
 }
 
 // ---------------------------------------------------------------------------
+// Mixed-radix digits and candidate slots.
+
+// Digits of raw index i, least significant first, into the calling thread's
+// column of the workgroup's digit table: dig[k * kBlock] = x_k.
+__device__ __forceinline__ void store_digits(const SpaceDesc &sp, uint32_t i, uint32_t *dig) {
+    uint32_t q = i;
+    for (int k = sp.n - 1; k >= 0; --k) {
+        const uint32_t qn = (uint32_t)(((uint64_t)q * sp.magic[k]) >> sp.shift[k]);
+        dig[k * kBlock] = q - qn * (uint32_t)sp.radix[k];
+        q = qn;
+    }
+}
+
+// Node records: W 64-bit words; in-edge bits first, then out_deg in bits
+// 24..31 and the raw index in bits 32..63 of the last word.
+template <int W>
+struct Record {
+    uint64_t w[W];
+    __device__ __forceinline__ uint32_t word32(int b) const {  // b compile-time after unrolling
+        return (b & 1) ? (uint32_t)(w[b >> 1] >> 32) : (uint32_t)w[b >> 1];
+    }
+    __device__ __forceinline__ int32_t raw() const { return (int32_t)(w[W - 1] >> 32); }
+    __device__ __forceinline__ int32_t out_deg() const { return (int32_t)((w[W - 1] >> 24) & 0xffu); }
+};
+
+// Slot bits of batch b (slots 32b .. 32b+31) that name real slots: the last
+// record word also carries out_deg and the raw index above slot k.
+__device__ __forceinline__ uint32_t batch_mask(int b, int k) {
+    const int left = k - 32 * b;
+    return left >= 32 ? ~0u : (left <= 0 ? 0u : (1u << left) - 1u);
+}
+
+template <int W>
+__device__ __forceinline__ Record<W> load_record(const uint64_t *__restrict__ rec, int32_t v) {
+    Record<W> r;
+    const uint64_t *p = rec + (int64_t)v * W;
+    if (W % 2 == 0) {
+#pragma unroll
+        for (int q = 0; q < W; q += 2) {
+            const ulonglong2 t = *reinterpret_cast<const ulonglong2 *>(p + q);
+            r.w[q] = t.x;
+            r.w[q + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < W; ++q) r.w[q] = p[q];
+    }
+    return r;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= (uint32_t)__shfl_xor((int)x, o, 64);
+    return x;
+}
+
+// Number of set bits of the record's in-edge mask below slot s (compile-time
+// word index after unrolling).
+template <int W>
+__device__ __forceinline__ int bits_below(const Record<W> &r, int s) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        const int lo = q * 64;
+        if (s >= lo + 64)
+            c += __popcll(r.w[q]);
+        else if (s > lo)
+            c += __popcll(r.w[q] & ((1ull << (s - lo)) - 1ull));
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
 // Compaction: valid points in ascending raw order (Sec. III-B; failed and
 // constraint-violating configurations are excluded, Sec. V), f_opt.
 
@@ -204,21 +280,89 @@ __global__ __launch_bounds__(kBlock) void k_compact_write(const float *__restric
 }
 
 // ---------------------------------------------------------------------------
-// FFG degrees (Sec. VII-B): for node v with raw index i and digits x, every
-// candidate neighbour is c = i + (a - x_k) * stride_k (eq. 2: one parameter
+// FFG degrees (Sec. VII-B): for node v with raw index i and digits x, the
+// candidate neighbours are c = i + (a - x_k) * stride_k (eq. 2: one parameter
 // changed; adjacent: a = x_k +- 1 inside the list).  in_deg counts valid
 // neighbours with strictly higher fitness (edges into v), out_deg those with
-// strictly lower fitness (edges out of v).  One thread per node: the wave's
-// 64 nodes are consecutive valid points, so each candidate slot is a
-// near-contiguous gather.
+// strictly lower fitness (edges out of v).  The slot kernel also records the
+// in-edges as a bit mask over the node's candidate slots.
 
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable sl,
+                                                         const float *__restrict__ fit,
+                                                         const int32_t *__restrict__ valid_raw, int32_t n,
+                                                         int32_t *__restrict__ in_deg,
+                                                         int32_t *__restrict__ out_deg,
+                                                         uint64_t *__restrict__ rec,
+                                                         uint64_t *__restrict__ presence,
+                                                         int64_t *__restrict__ tile_e,
+                                                         int32_t *__restrict__ tile_m) {
+    extern __shared__ uint32_t s_dig[];
+    uint32_t *dig = s_dig + threadIdx.x;
+    const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+    int32_t din = 0, dout = 0;
+    uint64_t m[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) m[q] = 0ull;
+    if (v < n) {
+        const uint32_t i = (uint32_t)valid_raw[v];
+        const float fv = fit[i];
+        store_digits(sp, i, dig);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            for (int s0 = q * 64; s0 < q * 64 + 64 && s0 < sl.k; s0 += kBatch) {
+                float fc[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int s = s0 + u;
+                    fc[u] = NAN;
+                    if (s < sl.k) {
+                        const int k = sl.dim[s];
+                        const int32_t a = (int32_t)dig[k * kBlock] + sl.delta[s];
+                        if (a >= 0 && a < sp.radix[k]) fc[u] = fit[(int32_t)i + sl.off[s]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const bool in = (fc[u] > fv) & (fc[u] < INFINITY);
+                    din += in;
+                    dout += (fc[u] < fv);
+                    if (in) m[q] |= 1ull << ((s0 + u) & 63);
+                }
+            }
+        }
+        in_deg[v] = din;
+        out_deg[v] = dout;
+        const uint64_t tail = ((uint64_t)i << 32) | ((uint64_t)(uint32_t)dout << 24);
+        uint64_t *p = rec + (int64_t)v * W;
+#pragma unroll
+        for (int q = 0; q < W; ++q) p[q] = m[q] | (q == W - 1 ? tail : 0ull);
+    }
+    // slots any node of this wave has as an in-edge (read by the sweep's scalar unit)
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        uint32_t lo = (uint32_t)m[q], hi = (uint32_t)(m[q] >> 32);
+        lo = wave_or(lo);
+        hi = wave_or(hi);
+        if ((threadIdx.x & 63) == 0 && v < n) presence[(int64_t)(v >> 6) * W + q] = ((uint64_t)hi << 32) | lo;
+    }
+    const int64_t te = block_sum((int64_t)din);
+    const int32_t tm = block_sum((int32_t)(v < n && dout == 0));
+    if (threadIdx.x == 0) {
+        tile_e[blockIdx.x] = te;
+        tile_m[blockIdx.x] = tm;
+    }
+}
+
+// Generic count for spaces with more than kMaxSlots candidate slots: walks the
+// parameters and their values directly.
 template <bool ADJ>
-__global__ __launch_bounds__(kBlock) void k_degree(SpaceDesc sp, const float *__restrict__ fit,
-                                                   const int32_t *__restrict__ valid_raw, int32_t n,
-                                                   int32_t *__restrict__ in_deg,
-                                                   int32_t *__restrict__ out_deg,
-                                                   int64_t *__restrict__ tile_e,
-                                                   int32_t *__restrict__ tile_m) {
+__global__ __launch_bounds__(kBlock) void k_degree_generic(SpaceDesc sp, const float *__restrict__ fit,
+                                                           const int32_t *__restrict__ valid_raw, int32_t n,
+                                                           int32_t *__restrict__ in_deg,
+                                                           int32_t *__restrict__ out_deg,
+                                                           int64_t *__restrict__ tile_e,
+                                                           int32_t *__restrict__ tile_m) {
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
     int32_t din = 0, dout = 0;
     if (v < n) {
@@ -229,22 +373,23 @@ __global__ __launch_bounds__(kBlock) void k_degree(SpaceDesc sp, const float *__
             const uint32_t xk = (i / st) % r;
             const uint32_t row = i - xk * st;
             if (ADJ) {
-                if (xk > 0) {
-                    const float fc = fit[row + (xk - 1) * st];
-                    din += (fc > fv) & (fc < INFINITY);
-                    dout += (fc < fv);
-                }
-                if (xk + 1 < r) {
-                    const float fc = fit[row + (xk + 1) * st];
-                    din += (fc > fv) & (fc < INFINITY);
-                    dout += (fc < fv);
-                }
+                const float lo = xk > 0 ? fit[row + (xk - 1) * st] : NAN;
+                const float hi = xk + 1 < r ? fit[row + (xk + 1) * st] : NAN;
+                din += ((lo > fv) & (lo < INFINITY)) + ((hi > fv) & (hi < INFINITY));
+                dout += (lo < fv) + (hi < fv);
             } else {
-                for (uint32_t a = 0; a < r; ++a) {
-                    if (a == xk) continue;
-                    const float fc = fit[row + a * st];
-                    din += (fc > fv) & (fc < INFINITY);
-                    dout += (fc < fv);
+                for (uint32_t a0 = 0; a0 < r; a0 += 8) {
+                    float fc[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const uint32_t a = a0 + u;
+                        fc[u] = (a < r && a != xk) ? fit[row + a * st] : NAN;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        din += (fc[u] > fv) & (fc[u] < INFINITY);
+                        dout += (fc[u] < fv);
+                    }
                 }
             }
         }
@@ -272,57 +417,110 @@ __global__ __launch_bounds__(kBlock) void k_degree_scan(const int64_t *__restric
     }
 }
 
+// ---------------------------------------------------------------------------
 // CSR fill: row_ptr by a workgroup scan of in_deg plus the tile offset, the
 // minima (sinks) by a scan of the sink flags, then the sources of every
 // in-edge in ascending raw (= node id) order.  Ascending order of
 // c = i + (a - x_k) * stride_k is: below i, parameters 0..n-1 with a rising
 // from 0 to x_k - 1; above i, parameters n-1..0 with a rising from x_k + 1.
 
-template <bool ADJ>
-__device__ __forceinline__ void fill_slot(const float *__restrict__ fit, const int32_t *__restrict__ remap,
-                                          uint32_t c, float fv, int32_t *__restrict__ col_idx,
-                                          int32_t &pos, int32_t end) {
-    const float fc = fit[c];
-    if ((fc > fv) & (fc < INFINITY)) {
-        if (pos < end) col_idx[pos] = remap[c];
-        ++pos;
+// Shared prologue: row_ptr and minima for the workgroup's nodes.
+__device__ __forceinline__ void fill_rows(int32_t v, int32_t n, int32_t n_edges, int32_t din, int32_t sink,
+                                          const int64_t *tile_eoff, const int32_t *tile_moff,
+                                          int32_t *row_ptr, int32_t *minima, int32_t &e_off) {
+    int32_t tot;
+    e_off = (int32_t)tile_eoff[blockIdx.x] + block_excl_scan(din, &tot);
+    const int32_t m_off = tile_moff[blockIdx.x] + block_excl_scan(sink, &tot);
+    if (v < n) {
+        row_ptr[v] = e_off;
+        if (v == n - 1) row_ptr[n] = n_edges;
+        if (sink) minima[m_off] = v;
     }
 }
 
-template <bool ADJ>
-__global__ __launch_bounds__(kBlock) void k_fill(SpaceDesc sp, const float *__restrict__ fit,
-                                                 const int32_t *__restrict__ valid_raw,
-                                                 const int32_t *__restrict__ remap, int32_t n,
-                                                 int32_t n_edges, const int32_t *__restrict__ in_deg,
-                                                 const int32_t *__restrict__ out_deg,
-                                                 const int64_t *__restrict__ tile_eoff,
-                                                 const int32_t *__restrict__ tile_moff,
-                                                 int32_t *__restrict__ row_ptr,
-                                                 int32_t *__restrict__ col_idx,
-                                                 int32_t *__restrict__ minima) {
+// Slot version: the in-edges come from the node records of the degree pass.
+// Slots are sorted by raw-index offset, so the position of an in-edge in its
+// row is the number of in-edge bits below its slot.  Every lane walks the
+// slots in the same order, so the remap gathers of one slot are
+// near-contiguous across the wave.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_fill_slots(SlotTable sl, const int32_t *__restrict__ remap,
+                                                       const uint64_t *__restrict__ rec, int32_t n,
+                                                       int32_t n_edges, const int32_t *__restrict__ in_deg,
+                                                       const int32_t *__restrict__ out_deg,
+                                                       const int64_t *__restrict__ tile_eoff,
+                                                       const int32_t *__restrict__ tile_moff,
+                                                       int32_t *__restrict__ row_ptr,
+                                                       int32_t *__restrict__ col_idx,
+                                                       int32_t *__restrict__ minima) {
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
     const int32_t din = v < n ? in_deg[v] : 0;
     const int32_t sink = (v < n && out_deg[v] == 0) ? 1 : 0;
-    int32_t tot;
-    const int32_t e_off = (int32_t)tile_eoff[blockIdx.x] + block_excl_scan(din, &tot);
-    const int32_t m_off = tile_moff[blockIdx.x] + block_excl_scan(sink, &tot);
-    if (v >= n) return;
-    row_ptr[v] = e_off;
-    if (v == n - 1) row_ptr[n] = n_edges;
-    if (sink) minima[m_off] = v;
-    if (din == 0) return;
+    int32_t e_off;
+    fill_rows(v, n, n_edges, din, sink, tile_eoff, tile_moff, row_ptr, minima, e_off);
+    if (v >= n || din == 0) return;
+    const Record<W> r = load_record<W>(rec, v);
+    const int32_t i = r.raw();
+    const int32_t end = e_off + din;
+#pragma unroll
+    for (int b = 0; b < 2 * W; ++b) {
+        if (32 * b >= sl.k) break;
+        const uint32_t bits = r.word32(b) & batch_mask(b, sl.k);
+        if (bits == 0u) continue;
+        int32_t src[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int s = 32 * b + u;
+            src[u] = ((bits >> u) & 1u) ? remap[i + sl.off[s]] : -1;
+        }
+        int32_t pos = e_off + bits_below<W>(r, 32 * b);
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            if ((bits >> u) & 1u) {
+                if (pos < end) col_idx[pos] = src[u];
+                ++pos;
+            }
+        }
+    }
+}
+
+// Generic version for spaces with more than kMaxSlots candidate slots.
+template <bool ADJ>
+__global__ __launch_bounds__(kBlock) void k_fill_generic(SpaceDesc sp, const float *__restrict__ fit,
+                                                         const int32_t *__restrict__ valid_raw,
+                                                         const int32_t *__restrict__ remap, int32_t n,
+                                                         int32_t n_edges, const int32_t *__restrict__ in_deg,
+                                                         const int32_t *__restrict__ out_deg,
+                                                         const int64_t *__restrict__ tile_eoff,
+                                                         const int32_t *__restrict__ tile_moff,
+                                                         int32_t *__restrict__ row_ptr,
+                                                         int32_t *__restrict__ col_idx,
+                                                         int32_t *__restrict__ minima) {
+    const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+    const int32_t din = v < n ? in_deg[v] : 0;
+    const int32_t sink = (v < n && out_deg[v] == 0) ? 1 : 0;
+    int32_t e_off;
+    fill_rows(v, n, n_edges, din, sink, tile_eoff, tile_moff, row_ptr, minima, e_off);
+    if (v >= n || din == 0) return;
     const uint32_t i = (uint32_t)valid_raw[v];
     const float fv = fit[i];
     const int32_t end = e_off + din;
     int32_t pos = e_off;
+    auto take = [&](uint32_t c) {
+        const float fc = fit[c];
+        if ((fc > fv) & (fc < INFINITY)) {
+            if (pos < end) col_idx[pos] = remap[c];
+            ++pos;
+        }
+    };
     for (int k = 0; k < sp.n; ++k) {  // below i
         const uint32_t r = (uint32_t)sp.radix[k], st = (uint32_t)sp.stride[k];
         const uint32_t xk = (i / st) % r;
         const uint32_t row = i - xk * st;
         if (ADJ) {
-            if (xk > 0) fill_slot<ADJ>(fit, remap, row + (xk - 1) * st, fv, col_idx, pos, end);
+            if (xk > 0) take(row + (xk - 1) * st);
         } else {
-            for (uint32_t a = 0; a < xk; ++a) fill_slot<ADJ>(fit, remap, row + a * st, fv, col_idx, pos, end);
+            for (uint32_t a = 0; a < xk; ++a) take(row + a * st);
         }
     }
     for (int k = sp.n - 1; k >= 0; --k) {  // above i
@@ -330,9 +528,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(SpaceDesc sp, const float *__re
         const uint32_t xk = (i / st) % r;
         const uint32_t row = i - xk * st;
         if (ADJ) {
-            if (xk + 1 < r) fill_slot<ADJ>(fit, remap, row + (xk + 1) * st, fv, col_idx, pos, end);
+            if (xk + 1 < r) take(row + (xk + 1) * st);
         } else {
-            for (uint32_t a = xk + 1; a < r; ++a) fill_slot<ADJ>(fit, remap, row + a * st, fv, col_idx, pos, end);
+            for (uint32_t a = xk + 1; a < r; ++a) take(row + a * st);
         }
     }
 }
@@ -347,25 +545,50 @@ __global__ __launch_bounds__(kBlock) void k_fill(SpaceDesc sp, const float *__re
 // workgroup writes FP64 partial sums; the last one to finish (ticket) reduces
 // them in a fixed order and sets s, c and the stop flag for the next launch.
 
+// How the workgroups of a sweep hand their partial sums to the one that
+// finishes the step:
+//   0  each workgroup's ticket increment is an agent-scope acquire-release RMW;
+//   1  the increment only releases, and just the elected workgroup acquires;
+//   2  no ticket: a one-workgroup kernel finishes the step after the sweep.
+#ifndef FL_SYNC_MODE
+#define FL_SYNC_MODE 2
+#endif
+
 __device__ bool elect_last(uint32_t *ticket) {
     __shared__ bool last;
     __syncthreads();
     if (threadIdx.x == 0) {
+#if FL_SYNC_MODE == 0
         const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+#else
+        const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+#endif
         last = (t == gridDim.x - 1);
     }
     __syncthreads();
-    if (last) __threadfence();
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return last;
 }
 
-__device__ void pr_finish(const PrArgs &a, bool first) {
-    const int g = gridDim.x;
+// Reduce the g workgroups' partial sums in a fixed order and set up the next
+// step (s, c, residual, stop flag).  Runs in one workgroup.
+__device__ void pr_finish(const PrArgs &a, int g, bool first) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int b = threadIdx.x; b < g; b += kBlock) {
-        s0 += __hip_atomic_load(&a.partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s1 += __hip_atomic_load(&a.partials[g + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s2 += __hip_atomic_load(&a.partials[2 * g + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int b0 = 0; b0 < g; b0 += kBlock * 8) {
+        double v0[8], v1[8], v2[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * kBlock + threadIdx.x;
+            v0[u] = b < g ? __hip_atomic_load(&a.partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+            v1[u] = b < g ? __hip_atomic_load(&a.partials[g + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+            v2[u] = b < g ? __hip_atomic_load(&a.partials[2 * g + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            s0 += v0[u];
+            s1 += v1[u];
+            s2 += v2[u];
+        }
     }
     s0 = block_sum(s0);
     s1 = block_sum(s1);
@@ -392,34 +615,77 @@ __device__ void pr_finish(const PrArgs &a, bool first) {
     }
 }
 
+__device__ __forceinline__ void pr_block_end(const PrArgs &a, double ps, double pr, double pk, bool first) {
+    ps = block_sum(ps);
+    pr = block_sum(pr);
+    pk = block_sum(pk);
+    const int g = gridDim.x;
+    if (threadIdx.x == 0) {
+        a.partials[blockIdx.x] = ps;
+        a.partials[g + blockIdx.x] = pr;
+        a.partials[2 * g + blockIdx.x] = pk;
+    }
+#if FL_SYNC_MODE != 2
+    if (elect_last(&a.st->ticket)) pr_finish(a, g, first);
+#else
+    (void)first;
+#endif
+}
+
+// Finishing kernel of sync mode 2 (one workgroup): skipped, like the sweep
+// it follows, once the stop flag is set.
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_pr_finish(PrArgs a, int g) {
+    if (!FIRST && a.st->done) return;
+    pr_finish(a, g, FIRST);
+}
+
 __global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
     const float y0 = (float)(1.0 / (double)a.n);
     double ps = 0.0, pk = 0.0;
     for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += gridDim.x * kBlock) {
         const int32_t deg = a.out_deg[v];
+        const int32_t xi = a.kind == kSweepSlots ? a.valid_raw[v] : v;
         a.y[0][v] = y0;
-        a.x[0][v] = deg > 0 ? y0 / (float)deg : 0.0f;
+        a.x[0][xi] = deg > 0 ? y0 / (float)deg : 0.0f;
         ps += (double)y0;
         if (deg == 0) pk += (double)y0;
     }
-    ps = block_sum(ps);
-    pk = block_sum(pk);
-    const int g = gridDim.x;
-    if (threadIdx.x == 0) {
-        a.partials[blockIdx.x] = ps;
-        a.partials[g + blockIdx.x] = 0.0;
-        a.partials[2 * g + blockIdx.x] = pk;
-    }
-    if (elect_last(&a.st->ticket)) pr_finish(a, true);
+    pr_block_end(a, ps, 0.0, pk, true);
 }
 
-// L lanes per row: the lanes of a row read consecutive col_idx entries and
-// reduce with cross-lane shuffles.  The grid is persistent (a multiple of 8
-// workgroups); workgroup b is dealt to XCD b % 8 and gets logical id
-// (b % 8) * (G/8) + b / 8, and logical ids own contiguous runs of rows, so
-// every XCD sweeps one contiguous eighth of the rows.
+// Tile t of the persistent grid, in "front" order: XCD j = b % 8 owns the
+// contiguous j-th eighth of the tiles, and its workgroups take consecutive
+// tiles in turn, so at any time an XCD sweeps a narrow band of nodes and the
+// x values that band gathers stay in its L2.
+struct TileWalk {
+    int32_t first, end, step;
+    __device__ TileWalk(int32_t n_tiles) {
+        const int g = gridDim.x;
+        const int xcd = blockIdx.x % kXcds;
+        const int32_t per = (n_tiles + kXcds - 1) / kXcds;
+        first = per * xcd + blockIdx.x / kXcds;
+        end = min(per * (xcd + 1), n_tiles);
+        step = g / kXcds;
+    }
+};
+
+__device__ __forceinline__ void pr_node_update(const PrArgs &a, int32_t v, int32_t xi, float acc, double sd,
+                                               double c, double s, const float *y_in, float *y_out,
+                                               float *x_out, double &ps, double &pr, double &pk) {
+    const float yf = (float)(sd * (double)acc + c);
+    const int32_t deg = a.out_deg[v];
+    y_out[v] = yf;
+    x_out[xi] = deg > 0 ? yf / (float)deg : 0.0f;
+    ps += (double)yf;
+    pr += fabs((double)yf - s * (double)y_in[v]);
+    if (deg == 0) pk += (double)yf;
+}
+
+// CSR sweep, L lanes per row: the lanes of a row read consecutive col_idx
+// entries (four rounds of loads in flight) and reduce with shuffles.
 template <int L>
-__global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
+__global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
     const PrState *st = a.st;
     if (st->done) return;
     const int32_t k = st->k;
@@ -431,46 +697,111 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
     const int32_t *__restrict__ col_idx = a.col_idx;
     const double s = st->s, c = st->c;
     const double sd = s * a.d;
-
-    const int g = gridDim.x;
-    const int lb = (blockIdx.x % kXcds) * (g / kXcds) + blockIdx.x / kXcds;
     constexpr int kRows = kBlock / L;
-    const int32_t n_groups = (a.n + kRows - 1) / kRows;
-    const int32_t chunk = (n_groups + g - 1) / g;
-    const int32_t g0 = lb * chunk;
-    const int32_t g1 = min(g0 + chunk, n_groups);
     const int lane = threadIdx.x % L;
     const int sub = threadIdx.x / L;
-
+    const TileWalk w((a.n + kRows - 1) / kRows);
     double ps = 0.0, pr = 0.0, pk = 0.0;
-    for (int32_t grp = g0; grp < g1; ++grp) {
-        const int32_t v = grp * kRows + sub;
+    for (int32_t t = w.first; t < w.end; t += w.step) {
+        const int32_t v = t * kRows + sub;
         float acc = 0.0f;
         if (v < a.n) {
             const int32_t e1 = row_ptr[v + 1];
-            for (int32_t e = row_ptr[v] + lane; e < e1; e += L) acc += x_in[col_idx[e]];
+            for (int32_t e = row_ptr[v] + lane; e < e1; e += 4 * L) {
+                int32_t cix[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) cix[u] = e + u * L < e1 ? col_idx[e + u * L] : -1;
+                float xv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) xv[u] = cix[u] >= 0 ? x_in[cix[u]] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc += xv[u];
+            }
         }
 #pragma unroll
         for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lane == 0 && v < a.n) {
+        if (lane == 0 && v < a.n) pr_node_update(a, v, v, acc, sd, c, s, y_in, y_out, x_out, ps, pr, pk);
+    }
+    pr_block_end(a, ps, pr, pk, false);
+}
+
+// Slot sweep: one node per lane, 64 consecutive nodes per wave.  For every
+// candidate slot whose in-edge bit is set, gather x at raw index i + off[s]
+// (x lives in raw-index space, so neither col_idx nor an index remap is read).
+// A slot no lane of the wave needs is skipped with a scalar branch; the other
+// lanes' loads of that slot get an out-of-range buffer offset and return 0,
+// so the 32 loads of a batch issue back to back with no per-lane branching.
+// Slots run in ascending raw-index order, the order of the CSR rows, so the
+// FP32 sum equals the one-lane-per-row CSR sweep's bit for bit.
+template <int W, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a, SlotTable sl) {
+    const PrState *st = a.st;
+    if (st->done) return;
+    const int32_t k = st->k;
+    const float *__restrict__ y_in = a.y[k & 1];
+    const float *__restrict__ x_in = a.x[k & 1];
+    float *__restrict__ y_out = a.y[(k + 1) & 1];
+    float *__restrict__ x_out = a.x[(k + 1) & 1];
+    const double s = st->s, c = st->c;
+    const double sd = s * a.d;
+    const __amdgpu_buffer_rsrc_t xr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)x_in, (short)0, a.x_bytes, 0x00020000);
+    const TileWalk w((a.n + kBlock - 1) / kBlock);
+    double ps = 0.0, pr = 0.0, pk = 0.0;
+    for (int32_t t = w.first; t < w.end; t += w.step) {
+        const int32_t v = t * kBlock + threadIdx.x;
+        const bool active = v < a.n;
+        Record<W> r;
+        if (active) {
+            r = load_record<W>(a.rec, v);
+        } else {
+#pragma unroll
+            for (int q = 0; q < W; ++q) r.w[q] = 0ull;
+        }
+        const int32_t i = r.raw();
+        const uint32_t i4 = 4u * (uint32_t)i;
+        // this wave's slot presence, loaded through the scalar unit; a wave
+        // past the last node (in the last tile) has no entry and skips
+        const int32_t first = __builtin_amdgcn_readfirstlane(t * kBlock + (int32_t)(threadIdx.x & ~63u));
+        const uint64_t *pw = a.presence + (int64_t)(first >> 6) * W;
+        float acc = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 2 * W; ++b) {
+            if (32 * b >= sl.k || first >= a.n) break;
+            const uint32_t bits = r.word32(b) & batch_mask(b, sl.k);
+            const uint64_t pq = pw[b >> 1];
+            const uint32_t any = (b & 1) ? (uint32_t)(pq >> 32) : (uint32_t)pq;
+            if (any == 0u) continue;
+            const uint32_t nbits = ~bits;
+            float val[32];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) {
+                val[u] = 0.0f;
+                if ((any >> u) & 1u) {
+                    if (BUF) {
+                        // out-of-range offset (the load returns 0) where this lane's bit is clear
+                        const uint32_t byte = ((nbits << (31 - u)) & 0x80000000u) |
+                                              (i4 + 4u * (uint32_t)sl.off[32 * b + u]);
+                        val[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, byte, 0, 0));
+                    } else {
+                        val[u] = ((bits >> u) & 1u) ? x_in[i + sl.off[32 * b + u]] : 0.0f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 32; ++u) acc += val[u];
+        }
+        if (active) {
             const float yf = (float)(sd * (double)acc + c);
-            const int32_t deg = a.out_deg[v];
+            const int32_t deg = r.out_deg();
             y_out[v] = yf;
-            x_out[v] = deg > 0 ? yf / (float)deg : 0.0f;
+            x_out[i] = deg > 0 ? yf / (float)deg : 0.0f;
             ps += (double)yf;
             pr += fabs((double)yf - s * (double)y_in[v]);
             if (deg == 0) pk += (double)yf;
         }
     }
-    ps = block_sum(ps);
-    pr = block_sum(pr);
-    pk = block_sum(pk);
-    if (threadIdx.x == 0) {
-        a.partials[blockIdx.x] = ps;
-        a.partials[g + blockIdx.x] = pr;
-        a.partials[2 * g + blockIdx.x] = pk;
-    }
-    if (elect_last(&a.st->ticket)) pr_finish(a, false);
+    pr_block_end(a, ps, pr, pk, false);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pr_output(PrArgs a, double *__restrict__ pagerank) {
@@ -502,6 +833,39 @@ __global__ __launch_bounds__(kBlock) void k_score(const double *__restrict__ pag
     }
 }
 
+size_t digit_lds(const SpaceDesc &sp) { return sizeof(uint32_t) * kBlock * (size_t)sp.n; }
+
+// The slot sweep kernel for W record words, with out-of-range buffer loads
+// when the x vector's byte size leaves room for the out-of-range offset.
+template <int W>
+const void *slot_sweep_fn(const PrArgs &a) {
+    return a.x_bytes > 0 ? (const void *)k_pr_iter_slots<W, true> : (const void *)k_pr_iter_slots<W, false>;
+}
+
+const void *slot_sweep_kernel(const PrArgs &a, int words) {
+    switch (words) {
+        case 1: return slot_sweep_fn<1>(a);
+        case 2: return slot_sweep_fn<2>(a);
+        case 3: return slot_sweep_fn<3>(a);
+        case 4: return slot_sweep_fn<4>(a);
+        case 5: return slot_sweep_fn<5>(a);
+        default: return nullptr;
+    }
+}
+
+const void *csr_sweep_kernel(int lanes) {
+    switch (lanes) {
+        case 1: return (const void *)k_pr_iter_csr<1>;
+        case 2: return (const void *)k_pr_iter_csr<2>;
+        case 4: return (const void *)k_pr_iter_csr<4>;
+        case 8: return (const void *)k_pr_iter_csr<8>;
+        case 16: return (const void *)k_pr_iter_csr<16>;
+        case 32: return (const void *)k_pr_iter_csr<32>;
+        case 64: return (const void *)k_pr_iter_csr<64>;
+        default: return nullptr;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -521,60 +885,98 @@ hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, fl
     return hipGetLastError();
 }
 
-hipError_t launch_degree(const SpaceDesc &sp, int adjacent, const float *fit,
+hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                          const int32_t *valid_raw, int32_t n, int32_t *in_deg, int32_t *out_deg,
-                         int64_t *tile_e, int32_t *tile_m, int64_t *tile_eoff,
-                         int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream) {
+                         uint64_t *rec, uint64_t *presence, int64_t *tile_e, int32_t *tile_m,
+                         int64_t *tile_eoff, int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream) {
     const int32_t tiles = (n + kBlock - 1) / kBlock;
-    if (adjacent)
-        hipLaunchKernelGGL(k_degree<true>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
-                           n, in_deg, out_deg, tile_e, tile_m);
-    else
-        hipLaunchKernelGGL(k_degree<false>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
-                           n, in_deg, out_deg, tile_e, tile_m);
+    const size_t lds = digit_lds(sp);
+    switch (sl.words) {
+        case 1: hipLaunchKernelGGL(k_degree_slots<1>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
+        case 2: hipLaunchKernelGGL(k_degree_slots<2>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
+        case 3: hipLaunchKernelGGL(k_degree_slots<3>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
+        case 4: hipLaunchKernelGGL(k_degree_slots<4>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
+        case 5: hipLaunchKernelGGL(k_degree_slots<5>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
+        case 0:
+            if (adjacent)
+                hipLaunchKernelGGL(k_degree_generic<true>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
+                                   n, in_deg, out_deg, tile_e, tile_m);
+            else
+                hipLaunchKernelGGL(k_degree_generic<false>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
+                                   n, in_deg, out_deg, tile_e, tile_m);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL(k_degree_scan, dim3(1), dim3(kBlock), 0, stream, tile_e, tile_m, tiles,
                        tile_eoff, tile_moff, sizes);
     return hipGetLastError();
 }
 
-hipError_t launch_fill(const SpaceDesc &sp, int adjacent, const float *fit,
-                       const int32_t *valid_raw, const int32_t *remap, int32_t n, int32_t n_edges,
-                       const int32_t *in_deg, const int32_t *out_deg, const int64_t *tile_eoff,
-                       const int32_t *tile_moff, int32_t *row_ptr, int32_t *col_idx,
-                       int32_t *minima, hipStream_t stream) {
+hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
+                       const int32_t *valid_raw, const int32_t *remap, const uint64_t *rec,
+                       int32_t n, int32_t n_edges, const int32_t *in_deg, const int32_t *out_deg,
+                       const int64_t *tile_eoff, const int32_t *tile_moff, int32_t *row_ptr,
+                       int32_t *col_idx, int32_t *minima, hipStream_t stream) {
     const int32_t tiles = (n + kBlock - 1) / kBlock;
-    if (adjacent)
-        hipLaunchKernelGGL(k_fill<true>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
-                           remap, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr,
-                           col_idx, minima);
-    else
-        hipLaunchKernelGGL(k_fill<false>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
-                           remap, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr,
-                           col_idx, minima);
-    return hipGetLastError();
-}
-
-hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL(k_pr_init, dim3(grid), dim3(kBlock), 0, stream, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_pr_iter(const PrArgs &a, int lanes, int grid, hipStream_t stream) {
-    switch (lanes) {
-        case 1: hipLaunchKernelGGL(k_pr_iter<1>, dim3(grid), dim3(kBlock), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL(k_pr_iter<2>, dim3(grid), dim3(kBlock), 0, stream, a); break;
-        case 4: hipLaunchKernelGGL(k_pr_iter<4>, dim3(grid), dim3(kBlock), 0, stream, a); break;
-        case 8: hipLaunchKernelGGL(k_pr_iter<8>, dim3(grid), dim3(kBlock), 0, stream, a); break;
-        case 16: hipLaunchKernelGGL(k_pr_iter<16>, dim3(grid), dim3(kBlock), 0, stream, a); break;
-        case 32: hipLaunchKernelGGL(k_pr_iter<32>, dim3(grid), dim3(kBlock), 0, stream, a); break;
-        case 64: hipLaunchKernelGGL(k_pr_iter<64>, dim3(grid), dim3(kBlock), 0, stream, a); break;
+    switch (sl.words) {
+        case 1: hipLaunchKernelGGL(k_fill_slots<1>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
+        case 2: hipLaunchKernelGGL(k_fill_slots<2>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
+        case 3: hipLaunchKernelGGL(k_fill_slots<3>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
+        case 4: hipLaunchKernelGGL(k_fill_slots<4>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
+        case 5: hipLaunchKernelGGL(k_fill_slots<5>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
+        case 0:
+            if (adjacent)
+                hipLaunchKernelGGL(k_fill_generic<true>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw, remap,
+                                   n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima);
+            else
+                hipLaunchKernelGGL(k_fill_generic<false>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw, remap,
+                                   n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(k_pr_init, dim3(grid), dim3(kBlock), 0, stream, a);
+#if FL_SYNC_MODE == 2
+    hipLaunchKernelGGL(k_pr_finish<true>, dim3(1), dim3(kBlock), 0, stream, a, grid);
+#endif
+    return hipGetLastError();
+}
+
+hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
+                                 int *blocks) {
+    (void)sp;
+    const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(lanes);
+    if (!fn) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
+}
+
+hipError_t launch_pr_iter(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
+                          int grid, hipStream_t stream) {
+    (void)sp;
+    if (a.kind == kSweepSlots) {
+        const void *fn = slot_sweep_kernel(a, sl.words);
+        if (!fn) return hipErrorInvalidValue;
+        void *args[] = {(void *)&a, (void *)&sl};
+        hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+        if (e != hipSuccess) return e;
+    } else {
+        const void *fn = csr_sweep_kernel(lanes);
+        if (!fn) return hipErrorInvalidValue;
+        void *args[] = {(void *)&a};
+        hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+        if (e != hipSuccess) return e;
+    }
+#if FL_SYNC_MODE == 2
+    hipLaunchKernelGGL(k_pr_finish<false>, dim3(1), dim3(kBlock), 0, stream, a, grid);
+#endif
+    return hipGetLastError();
+}
+
 hipError_t launch_pr_output(const PrArgs &a, double *pagerank, hipStream_t stream) {
-    const int grid = (int)std::min<int64_t>(((int64_t)a.n + kBlock - 1) / kBlock, 4096);
+    const int grid = (int)(((int64_t)a.n + kBlock - 1) / kBlock < 4096 ? ((int64_t)a.n + kBlock - 1) / kBlock : 4096);
     hipLaunchKernelGGL(k_pr_output, dim3(grid), dim3(kBlock), 0, stream, a, pagerank);
     return hipGetLastError();
 }

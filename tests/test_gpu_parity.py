@@ -38,6 +38,10 @@ def say(msg):
     print(f"[case] {msg}", flush=True)
 
 
+def _space(name, radix, f):
+    return synth.Space(name, tuple(radix), np.asarray(f, dtype=np.float32).reshape(-1))
+
+
 def run_gpu(ctx, space, nb, damping=0.85, p=0.05, row_mapping=0, tol=0.0, max_iter=0,
             allow_noconv=False):
     import torch
@@ -97,15 +101,30 @@ def test_fuzz_parity(ctx, seed):
         check_parity(ctx, s, nb, damping=(0.5, 0.85, 0.9)[seed % 3], p=(0.0, 0.05, 0.15)[seed % 3])
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+ROWS_SLOTS = -1
+
+
+@pytest.mark.parametrize("lanes", [ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64])
 def test_every_row_mapping(ctx, lanes):
-    check_parity(ctx, synth.tiny(3), "hamming", row_mapping=lanes)
-    check_parity(ctx, synth.fuzz_space(5, max_params=6, max_radix=8), "hamming",
-                 row_mapping=lanes)
+    """Every sweep layout: the slot sweep and the CSR sweep with 1..64 lanes."""
+    for nb in ("hamming", "adjacent"):
+        check_parity(ctx, synth.tiny(3), nb, row_mapping=lanes)
+        check_parity(ctx, synth.fuzz_space(5, max_params=6, max_radix=8), nb, row_mapping=lanes)
+    check_parity(ctx, synth.mid(), "hamming", row_mapping=lanes)
 
 
-def _space(name, radix, f):
-    return synth.Space(name, tuple(radix), np.asarray(f, dtype=np.float32).reshape(-1))
+def test_mask_widths(ctx):
+    """K = 64 and 65 (one / two mask words), 128 (full) and 129 (generic
+    kernels, CSR sweep only)."""
+    rng = np.random.default_rng(5)
+    for radix in ((33, 33), (34, 33), (65, 65), (65, 66), (129,), (130,)):
+        n_raw = int(np.prod(radix))
+        f = np.where(rng.random(n_raw) < 0.1, np.nan, rng.random(n_raw) + 0.5)
+        s = _space(f"K{sum(r - 1 for r in radix)}", radix, f)
+        for nb in ("hamming", "adjacent"):
+            check_parity(ctx, s, nb)
+
+
 
 
 def test_edge_cases(ctx):
@@ -197,7 +216,8 @@ def test_error_paths(ctx):
     plan = api.plan_create(ctx, (8,), ones)
     try:
         for kw in ({"damping": 0.0}, {"damping": 1.0}, {"damping": float("nan")},
-                   {"p": -0.1}, {"p": float("inf")}, {"row_mapping": 3}, {"max_iter": -1}):
+                   {"p": -0.1}, {"p": float("inf")}, {"row_mapping": 3}, {"row_mapping": -2},
+                   {"max_iter": -1}):
             args = {"damping": 0.85, "p": 0.05}
             args.update(kw)
             with pytest.raises(api.FLError) as e:
@@ -205,6 +225,13 @@ def test_error_paths(ctx):
             assert e.value.status == _abi.FL_EINVAL, kw
     finally:
         plan.close()
+    wide = api.plan_create(ctx, (200,), torch.arange(1, 201, dtype=torch.float32, device="cuda"))
+    try:
+        with pytest.raises(api.FLError) as e:
+            api.execute(wide, row_mapping=ROWS_SLOTS)
+        assert e.value.status == _abi.FL_EINVAL
+    finally:
+        wide.close()
 
 
 def test_overflow_rejected_before_any_launch(ctx):
