@@ -71,6 +71,38 @@ def cpu_baseline(space, nb, damping, p, tol):
                          f"at tol {tol:g}: {a.iterations} FP64 iterations in {t:.2f} s"}
 
 
+def batched_leg(ctx, damping, p, tol, repeats: int = 3):
+    """234 spaces (26 shapes x 9 landscapes, N from 414 to 196k): one
+    fl_analyze_batch over all of them against the same analyses run one at a
+    time through fl_plan_create + fl_execute."""
+    import torch
+    from paper_2210_01465_amd import api, synth
+    spaces = synth.batched()
+    fits = [torch.from_numpy(s.fitness_raw).cuda() for s in spaces]
+    radices = [s.radix for s in spaces]
+    api.analyze_batch(radices, fits, "hamming", damping, p, tol, ctx=ctx)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        res = api.analyze_batch(radices, fits, "hamming", damping, p, tol, ctx=ctx)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / repeats
+    edges = sum(r.info["n_edges"] * r.info["iterations"] for r in res)
+    nodes = sum(r.info["n_valid"] for r in res)
+    t0 = time.perf_counter()
+    for s, f in zip(spaces, fits):
+        plan = api.plan_create(ctx, s.radix, f, "hamming")
+        api.execute(plan, damping, p, tol=tol, row_mapping=-1)
+        plan.close()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    return {"spaces": len(spaces), "n_valid_total": nodes, "ms_batched": round(t_batch * 1e3, 3),
+            "ms_one_at_a_time": round(t_plain * 1e3, 3), "speedup": round(t_plain / t_batch, 3),
+            "gteps_batched": round(edges / t_batch / 1e9, 3),
+            "gteps_one_at_a_time": round(edges / t_plain / 1e9, 3),
+            "all_ok": all(r.info["status"] == 0 for r in res)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +113,8 @@ def main():
     ap.add_argument("--row-mapping", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched leg (234 spaces in one fl_analyze_batch vs one at a time)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times "
                          "(calibrates the HBM byte counters of a profiler)")
@@ -182,6 +216,10 @@ def main():
         "analysis_pct_hbm_alg": round(alg_bytes / step_s / (HBM_PEAK_GBS * 1e9), 4),
         "score": info["score"],
     }
+
+    if not args.no_batched:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(ctx, damping, p, tol)
 
     ref = None
     if not args.no_cpu_baseline:

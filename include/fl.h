@@ -95,8 +95,10 @@ typedef struct {
     int64_t n_minima;    /* M, local minima = sinks */
     int32_t iterations;  /* PageRank iterations run */
     int32_t row_mapping; /* sweep layout used (FL_ROWS_SLOTS or lanes per CSR row) */
-    int32_t n_slots;     /* K, candidate neighbour slots per node */
-    int32_t mask_words;  /* 64-bit in-edge mask words per node (0: K > 128, CSR sweep only) */
+    int32_t n_slots;     /* candidate neighbour slots per node (2 per neighbour offset) */
+    int32_t mask_words;  /* 64-bit words of a node record (0: too many slots, CSR sweep only) */
+    int32_t status;      /* fl_status of this analysis (batched calls) */
+    int32_t reserved;
     double residual_l1;  /* ||r_k - r_{k-1}||_1 of the last iteration */
     double f_opt;        /* minimum valid fitness */
     double score;        /* C_p */
@@ -177,6 +179,59 @@ fl_status fl_plan_destroy(fl_ctx *ctx, fl_plan *plan);
 fl_status fl_analyze(fl_ctx *ctx, const fl_space *space, const float *d_fitness_raw,
                      fl_neighbourhood nb, const fl_params *params, double *d_pagerank,
                      int32_t *d_minima, int32_t *d_valid_raw, fl_summary *out);
+
+/* ---- Batches: many spaces in one segmented PageRank (continuous batching) ----
+ *
+ * A batch runs the power iteration of many plans together: every sweep is one
+ * segmented launch over the tiles of all running members (one launch per
+ * node-record width), followed by one launch that finishes the step of every
+ * member.  Each member keeps its own damping, tolerance, iteration count and
+ * stop flag, and its results equal those of fl_execute with the slot sweep
+ * (row_mapping FL_ROWS_SLOTS) bit for bit, whatever else runs in the batch.
+ * Members join (fl_batch_add) and leave (fl_batch_collect) between steps.
+ * A plan must stay alive while it is a member and may belong to one batch
+ * at a time. */
+typedef struct fl_batch fl_batch;
+
+fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out);
+
+/* Release the batch (not its plans).  Synchronises the stream. */
+fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *batch);
+
+/* Add a plan as a member; it starts at the next fl_batch_step.  The outputs
+ * (d_pagerank double[N], d_minima int32[M]) are caller-owned device buffers
+ * written when the member finishes; `tag` is returned by fl_batch_collect.
+ * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0 or
+ * FL_ROWS_SLOTS, or a space the slot sweep cannot take: use fl_execute),
+ * FL_ENOMEM, FL_EHIP. */
+fl_status fl_batch_add(fl_ctx *ctx, fl_batch *batch, fl_plan *plan, const fl_params *params,
+                       double *d_pagerank, int32_t *d_minima, int64_t tag);
+
+/* Run up to `sweeps` power-iteration sweeps (Sec. VII-B) for every running
+ * member; members that converge or reach max_iter finish: their ranks,
+ * minima and C_p (Sec. VII-B, eq. 3) are written.  *n_running receives the
+ * number of members not yet finished.  Synchronises the stream. */
+fl_status fl_batch_step(fl_ctx *ctx, fl_batch *batch, int32_t sweeps, int32_t *n_running);
+
+/* Remove up to `max` finished members: their tags and summaries (status
+ * FL_OK or FL_ENOCONV in out[j].status).  *n_out receives the count. */
+fl_status fl_batch_collect(fl_ctx *ctx, fl_batch *batch, int32_t max, int64_t *tags, fl_summary *out,
+                           int32_t *n_out);
+
+/* Sweeps run and device time of the sweep launches (HIP events) so far. */
+fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *batch, int64_t *sweeps, double *sweep_ms);
+
+/* One-shot batched analysis of n_spaces spaces: the FFGs are built with one
+ * synchronisation per build stage, then PageRank runs as one batch (spaces
+ * the slot sweep cannot take run through fl_execute).  All array arguments
+ * have n_spaces entries; d_pagerank[j] / d_minima[j] are sized as for
+ * fl_execute (n_raw upper bound is always enough).  out[j].status holds each
+ * space's status; the call returns the first error, or FL_ENOCONV if some
+ * space did not converge. */
+fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces,
+                           const float *const *d_fitness_raw, const fl_neighbourhood *nb,
+                           const fl_params *params, double *const *d_pagerank, int32_t *const *d_minima,
+                           fl_summary *out);
 
 #ifdef __cplusplus
 }

@@ -36,7 +36,8 @@ class fl_summary(ctypes.Structure):
     _fields_ = [("n_raw", ctypes.c_int64), ("n_valid", ctypes.c_int64), ("n_edges", ctypes.c_int64),
                 ("n_minima", ctypes.c_int64), ("iterations", ctypes.c_int32),
                 ("row_mapping", ctypes.c_int32), ("n_slots", ctypes.c_int32),
-                ("mask_words", ctypes.c_int32), ("residual_l1", ctypes.c_double),
+                ("mask_words", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("residual_l1", ctypes.c_double),
                 ("f_opt", ctypes.c_double), ("score", ctypes.c_double),
                 ("mass_minima", ctypes.c_double), ("mass_near", ctypes.c_double)]
 
@@ -70,6 +71,16 @@ PROTOTYPES = {
     "fl_analyze": (ctypes.c_int, [_P, ctypes.POINTER(fl_space), _P, ctypes.c_int,
                                   ctypes.POINTER(fl_params), _P, _P, _P,
                                   ctypes.POINTER(fl_summary)]),
+    "fl_batch_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "fl_batch_destroy": (ctypes.c_int, [_P, _P]),
+    "fl_batch_add": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(fl_params), _P, _P, ctypes.c_int64]),
+    "fl_batch_step": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "fl_batch_collect": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(fl_summary), ctypes.POINTER(ctypes.c_int32)]),
+    "fl_batch_timing": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "fl_analyze_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(fl_space), _P, _P,
+                                        ctypes.POINTER(fl_params), _P, _P, ctypes.POINTER(fl_summary)]),
 }
 
 _lib = None

@@ -10,6 +10,8 @@ points without the ``fl_`` prefix:
     plan_export / plan_timing          fl_plan_export / fl_plan_timing
     plan_destroy                       fl_plan_destroy
     analyze                            fl_analyze       (one shot)
+    Batch / batch_create               fl_batch_create / _add / _step / _collect / _timing / _destroy
+    analyze_batch                      fl_analyze_batch (many spaces, one shot)
 """
 from __future__ import annotations
 
@@ -257,6 +259,129 @@ def analyze(radix, fitness_raw: torch.Tensor, neighbourhood="hamming", damping: 
         info["status"] = rc
         N, M = int(out.n_valid), int(out.n_minima)
         return Result(pr[:N], mins[:M], vraw[:N], float(out.score), info)
+    finally:
+        if own:
+            ctx.close()
+
+
+class Batch:
+    """An ``fl_batch``: plans swept together (fl_batch_* entry points).
+
+    ``add`` attaches a plan with its parameters and output tensors, ``step``
+    runs sweeps for all running members, ``collect`` returns the finished
+    ones as ``(tag, pagerank, minima, summary)``.
+    """
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.handle = ctypes.c_void_p()
+        _check(ctx, _abi.load().fl_batch_create(ctx.handle, ctypes.byref(self.handle)), "fl_batch_create")
+        self._outputs = {}
+
+    def add(self, plan: Plan, damping: float = 0.85, p: float = 0.05, tol: float = 0.0,
+            max_iter: int = 0, tag: int | None = None) -> int:
+        dev = torch.device("cuda", self.ctx.device)
+        pr = torch.empty(plan.n_valid, dtype=torch.float64, device=dev)
+        mins = torch.empty(max(plan.n_minima, 1), dtype=torch.int32, device=dev)
+        tag = len(self._outputs) if tag is None else int(tag)
+        prm = _params(damping, p, tol, max_iter, 0)
+        rc = _abi.load().fl_batch_add(self.ctx.handle, self.handle, plan.handle, ctypes.byref(prm),
+                                      ctypes.c_void_p(pr.data_ptr()), ctypes.c_void_p(mins.data_ptr()), tag)
+        _check(self.ctx, rc, "fl_batch_add")
+        self._outputs[tag] = (plan, pr, mins)
+        return tag
+
+    def step(self, sweeps: int = 8) -> int:
+        running = ctypes.c_int32()
+        rc = _abi.load().fl_batch_step(self.ctx.handle, self.handle, int(sweeps), ctypes.byref(running))
+        _check(self.ctx, rc, "fl_batch_step")
+        return int(running.value)
+
+    def collect(self, max_items: int = 1024) -> list:
+        tags = (ctypes.c_int64 * max_items)()
+        sums = (_abi.fl_summary * max_items)()
+        n = ctypes.c_int32()
+        rc = _abi.load().fl_batch_collect(self.ctx.handle, self.handle, max_items, tags, sums, ctypes.byref(n))
+        _check(self.ctx, rc, "fl_batch_collect")
+        out = []
+        for j in range(n.value):
+            plan, pr, mins = self._outputs.pop(int(tags[j]))
+            info = sums[j].as_dict()
+            out.append((int(tags[j]), pr, mins[:plan.n_minima], info))
+        return out
+
+    def timing(self) -> dict:
+        sweeps = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(self.ctx, _abi.load().fl_batch_timing(self.ctx.handle, self.handle, ctypes.byref(sweeps),
+                                                      ctypes.byref(ms)), "fl_batch_timing")
+        return {"sweeps": int(sweeps.value), "sweep_ms": float(ms.value)}
+
+    def close(self):
+        if self.handle:
+            _abi.load().fl_batch_destroy(self.ctx.handle, self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_create(ctx: Context) -> Batch:
+    return Batch(ctx)
+
+
+def analyze_batch(spaces, fitness, neighbourhood="hamming", damping=0.85, p: float = 0.05,
+                  tol: float = 0.0, max_iter: int = 0, ctx: Context | None = None) -> list:
+    """fl_analyze_batch over many spaces.  ``spaces`` is a list of radix
+    tuples, ``fitness`` a matching list of device float32 tensors; the other
+    arguments may be scalars or per-space lists.  Returns a list of Result."""
+    n = len(spaces)
+    if len(fitness) != n:
+        raise ValueError("spaces and fitness differ in length")
+    own = ctx is None
+    if own:
+        ctx = Context(fitness[0].device.index or 0 if n else 0)
+
+    def per(x):
+        return list(x) if isinstance(x, (list, tuple)) else [x] * n
+    nbs, ds, ps, tols, its = per(neighbourhood), per(damping), per(p), per(tol), per(max_iter)
+    try:
+        keep = []
+        sp_arr = (_abi.fl_space * max(n, 1))()
+        fit_ptrs = (ctypes.c_void_p * max(n, 1))()
+        nb_arr = (ctypes.c_int * max(n, 1))()
+        prm_arr = (_abi.fl_params * max(n, 1))()
+        pr_ptrs = (ctypes.c_void_p * max(n, 1))()
+        min_ptrs = (ctypes.c_void_p * max(n, 1))()
+        outs = (_abi.fl_summary * max(n, 1))()
+        bufs = []
+        for j in range(n):
+            _check_fitness(ctx, spaces[j], fitness[j])
+            sp, arr = _space(spaces[j])
+            keep.append(arr)
+            sp_arr[j] = sp
+            fit_ptrs[j] = fitness[j].data_ptr()
+            nb_arr[j] = _nb(nbs[j])
+            prm_arr[j] = _params(ds[j], ps[j], tols[j], its[j], 0)
+            n_raw = _n_raw(spaces[j])
+            pr = torch.empty(n_raw, dtype=torch.float64, device=fitness[j].device)
+            mins = torch.empty(n_raw, dtype=torch.int32, device=fitness[j].device)
+            bufs.append((pr, mins))
+            pr_ptrs[j] = pr.data_ptr()
+            min_ptrs[j] = mins.data_ptr()
+        rc = _abi.load().fl_analyze_batch(ctx.handle, n, sp_arr, fit_ptrs, nb_arr, prm_arr, pr_ptrs,
+                                          min_ptrs, outs)
+        _check(ctx, rc, "fl_analyze_batch", allow=(_abi.FL_ENOCONV, _abi.FL_EINVAL, _abi.FL_EOVERFLOW))
+        results = []
+        for j in range(n):
+            info = outs[j].as_dict()
+            N, M = int(info["n_valid"]), int(info["n_minima"])
+            pr, mins = bufs[j]
+            results.append(Result(pr[:N], mins[:M], None, float(info["score"]), info))
+        return results
     finally:
         if own:
             ctx.close()

@@ -121,6 +121,7 @@ struct fl_plan {
     double *partials = nullptr;
     PrState *state = nullptr;
     int pr_grid = 0;
+    int32_t *d_off = nullptr;   // slot offsets in device memory (read by the slot sweep)
     // timing
     hipEvent_t ev[7] = {};  // build 0-1, pagerank 2-3, score 4, iteration chunk 5-6
     bool have_events = false;
@@ -153,8 +154,9 @@ T *pool_alloc(fl_ctx *ctx, int64_t count) {
 
 void release_plan_buffers(fl_plan *p) {
     DevicePool &pool = p->ctx->pool;
-    void *bufs[] = {p->valid_raw, p->out_deg, p->row_ptr, p->col_idx, p->minima, p->fit_c, p->rec, p->presence,
-                    p->y[0],      p->y[1],    p->x[0],    p->x[1],    p->partials, p->state};
+    void *bufs[] = {p->valid_raw, p->out_deg, p->row_ptr, p->col_idx, p->minima,  p->fit_c,
+                    p->rec,       p->presence, p->y[0], p->y[1],      p->x[0],     p->x[1],
+                    p->partials,  p->state,   p->d_off};
     for (void *b : bufs) pool.release(b);
 }
 
@@ -225,6 +227,358 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+
+// ---------------------------------------------------------------------------
+// Plan building in resumable stages, so that many spaces can be built with one
+// host synchronisation per stage (fl_analyze_batch) as well as one at a time.
+
+struct Build {
+    fl_plan *p = nullptr;
+    fl_status status = FL_OK;
+    std::string err;
+    BuildSizes *h_sizes = nullptr;  // pinned slot for this build's sizes
+    const float *fit = nullptr;
+    int32_t *remap = nullptr, *tile_cnt = nullptr, *tile_bad = nullptr, *tile_off = nullptr;
+    float *tile_min = nullptr;
+    BuildSizes *d_sizes = nullptr;
+    int32_t *in_deg = nullptr, *tile_m = nullptr, *tile_moff = nullptr;
+    int64_t *tile_e = nullptr, *tile_eoff = nullptr;
+};
+
+void build_fail(Build &b, fl_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    b.status = st;
+    b.err = buf;
+}
+
+void build_release_scratch(fl_ctx *ctx, Build &b) {
+    void *bufs[] = {b.remap, b.tile_cnt, b.tile_bad, b.tile_off, b.tile_min, b.d_sizes,
+                    b.in_deg, b.tile_m, b.tile_moff, b.tile_e, b.tile_eoff};
+    for (void *x : bufs) ctx->pool.release(x);
+    b.remap = b.tile_cnt = b.tile_bad = b.tile_off = b.in_deg = b.tile_m = b.tile_moff = nullptr;
+    b.tile_min = nullptr;
+    b.d_sizes = nullptr;
+    b.tile_e = b.tile_eoff = nullptr;
+}
+
+void build_abort(fl_ctx *ctx, Build &b) {
+    build_release_scratch(ctx, b);
+    if (b.p) {
+        release_plan_buffers(b.p);
+        if (b.p->have_events)
+            for (auto &e : b.p->ev) (void)hipEventDestroy(e);
+        delete b.p;
+        b.p = nullptr;
+    }
+}
+
+// Stage 1: validate, allocate, launch the compaction (Sec. III-B, Sec. V).
+void build_begin(fl_ctx *ctx, Build &b, const fl_space *space, const float *fit, fl_neighbourhood nb) {
+    if (!space || !fit) return build_fail(b, FL_EINVAL, "null argument");
+    if (space->n_params < 1 || space->n_params > fl::kMaxParams || !space->radix)
+        return build_fail(b, FL_EINVAL, "n_params must be in [1, %d]", fl::kMaxParams);
+    if (nb != FL_NB_HAMMING && nb != FL_NB_ADJACENT)
+        return build_fail(b, FL_EINVAL, "unknown neighbourhood %d", (int)nb);
+    SpaceDesc sp{};
+    sp.n = space->n_params;
+    int64_t n_raw = 1;
+    for (int i = 0; i < sp.n; ++i) {
+        if (space->radix[i] < 1) return build_fail(b, FL_EINVAL, "radix[%d] = %d < 1", i, space->radix[i]);
+        sp.radix[i] = space->radix[i];
+        n_raw *= space->radix[i];
+        if (n_raw >= (int64_t(1) << 31)) return build_fail(b, FL_EOVERFLOW, "prod radix >= 2^31");
+    }
+    for (int i = sp.n - 1; i >= 0; --i) sp.stride[i] = (i == sp.n - 1) ? 1 : sp.stride[i + 1] * sp.radix[i + 1];
+    sp.n_raw = (int32_t)n_raw;
+    set_magic(sp);
+
+    fl_plan *p = new (std::nothrow) fl_plan;
+    if (!p) return build_fail(b, FL_ENOMEM, "out of host memory");
+    b.p = p;
+    b.fit = fit;
+    p->ctx = ctx;
+    p->sp = sp;
+    p->adjacent = (nb == FL_NB_ADJACENT);
+    p->sl = make_slots(sp, p->adjacent);
+    p->n_raw = n_raw;
+    for (auto &e : p->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            return build_fail(b, FL_EHIP, "hipEventCreate failed");
+        }
+    }
+    p->have_events = true;
+
+    const int64_t c_tiles = (n_raw + fl::kCompactTile - 1) / fl::kCompactTile;
+    b.remap = pool_alloc<int32_t>(ctx, n_raw);
+    b.tile_cnt = pool_alloc<int32_t>(ctx, c_tiles);
+    b.tile_bad = pool_alloc<int32_t>(ctx, c_tiles);
+    b.tile_off = pool_alloc<int32_t>(ctx, c_tiles);
+    b.tile_min = pool_alloc<float>(ctx, c_tiles);
+    b.d_sizes = pool_alloc<BuildSizes>(ctx, 1);
+    p->valid_raw = pool_alloc<int32_t>(ctx, n_raw);
+    p->fit_c = pool_alloc<float>(ctx, n_raw);
+    if (!b.remap || !b.tile_cnt || !b.tile_bad || !b.tile_off || !b.tile_min || !b.d_sizes || !p->valid_raw ||
+        !p->fit_c)
+        return build_fail(b, FL_ENOMEM, "device allocation failed");
+    hipStream_t s = ctx->stream;
+    hipError_t he = hipEventRecord(p->ev[0], s);
+    if (he == hipSuccess)
+        he = fl::launch_compact(fit, sp.n_raw, b.tile_cnt, b.tile_min, b.tile_bad, b.tile_off, b.remap,
+                                p->valid_raw, p->fit_c, b.d_sizes, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(b.h_sizes, b.d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
+    if (he != hipSuccess) build_fail(b, FL_EHIP, "compaction: %s", hipGetErrorString(he));
+}
+
+// Stage 2 (sizes of stage 1 on the host): degree count + scans (Sec. VII-B).
+void build_degree(fl_ctx *ctx, Build &b) {
+    if (b.status != FL_OK) return;
+    fl_plan *p = b.p;
+    if (b.h_sizes->n_bad > 0)
+        return build_fail(b, FL_EINVAL, "%d fitness values are <= 0 or -inf", b.h_sizes->n_bad);
+    const int32_t n = b.h_sizes->n_valid;
+    if (n == 0) return build_fail(b, FL_EINVAL, "no valid configuration (all NaN / +inf)");
+    p->n = n;
+    p->f_opt = b.h_sizes->f_opt;
+    const int64_t n_tiles = (n + fl::kBlock - 1) / fl::kBlock;
+    b.in_deg = pool_alloc<int32_t>(ctx, n);
+    b.tile_e = pool_alloc<int64_t>(ctx, n_tiles);
+    b.tile_eoff = pool_alloc<int64_t>(ctx, n_tiles);
+    b.tile_m = pool_alloc<int32_t>(ctx, n_tiles);
+    b.tile_moff = pool_alloc<int32_t>(ctx, n_tiles);
+    p->out_deg = pool_alloc<int32_t>(ctx, n);
+    p->row_ptr = pool_alloc<int32_t>(ctx, (int64_t)n + 1);
+    p->minima = pool_alloc<int32_t>(ctx, n);
+    if (p->sl.words > 0) {
+        p->rec = pool_alloc<uint64_t>(ctx, (int64_t)n * p->sl.words);
+        p->presence = pool_alloc<uint64_t>(ctx, ((int64_t)n + 63) / 64 * p->sl.words);
+        p->d_off = pool_alloc<int32_t>(ctx, std::max(p->sl.k, 1));
+    }
+    if (!b.in_deg || !b.tile_e || !b.tile_eoff || !b.tile_m || !b.tile_moff || !p->out_deg || !p->row_ptr ||
+        !p->minima || (p->sl.words > 0 && (!p->rec || !p->presence || !p->d_off)))
+        return build_fail(b, FL_ENOMEM, "device allocation failed");
+    hipStream_t s = ctx->stream;
+    hipError_t he = hipSuccess;
+    if (p->sl.words > 0 && p->sl.k > 0)
+        he = hipMemcpyAsync(p->d_off, p->sl.off, sizeof(int32_t) * p->sl.k, hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = fl::launch_degree(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, n, b.in_deg, p->out_deg,
+                                      p->rec, p->presence, b.tile_e, b.tile_m, b.tile_eoff, b.tile_moff,
+                                      b.d_sizes, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(b.h_sizes, b.d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
+    if (he != hipSuccess) build_fail(b, FL_EHIP, "degree count: %s", hipGetErrorString(he));
+}
+
+// Stage 3 (edge count on the host): CSR fill and minima (Sec. III-B, VII-B).
+void build_fill(fl_ctx *ctx, Build &b) {
+    if (b.status != FL_OK) return;
+    fl_plan *p = b.p;
+    const int64_t e = b.h_sizes->n_edges;
+    if (e >= (int64_t(1) << 31)) return build_fail(b, FL_EOVERFLOW, "edge count %lld >= 2^31", (long long)e);
+    p->e = e;
+    p->m = b.h_sizes->n_minima;
+    p->col_idx = pool_alloc<int32_t>(ctx, e);
+    if (!p->col_idx) return build_fail(b, FL_ENOMEM, "device allocation failed");
+    hipStream_t s = ctx->stream;
+    hipError_t he = fl::launch_fill(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, b.remap, p->rec, (int32_t)p->n,
+                                    (int32_t)e, b.in_deg, p->out_deg, b.tile_eoff, b.tile_moff, p->row_ptr,
+                                    p->col_idx, p->minima, s);
+    if (he == hipSuccess) he = hipEventRecord(p->ev[1], s);
+    if (he != hipSuccess) build_fail(b, FL_EHIP, "CSR fill: %s", hipGetErrorString(he));
+}
+
+// Stage 4 (after the stream has drained): release scratch, record timing.
+void build_end(fl_ctx *ctx, Build &b) {
+    build_release_scratch(ctx, b);
+    if (b.status != FL_OK) return;
+    b.p->timing.build_ms = elapsed(b.p->ev[0], b.p->ev[1]);
+}
+
+void fill_sizes(const fl_plan *p, fl_summary *sizes) {
+    memset(sizes, 0, sizeof *sizes);
+    sizes->n_raw = p->n_raw;
+    sizes->n_valid = p->n;
+    sizes->n_edges = p->e;
+    sizes->n_minima = p->m;
+    sizes->n_slots = p->sl.k;
+    sizes->mask_words = p->sl.words;
+    sizes->f_opt = (double)p->f_opt;
+}
+
+// Analysis parameters with the defaults applied.
+struct Resolved {
+    double d, p, tol;
+    int32_t max_iter;
+    int lanes;  // FL_ROWS_SLOTS or CSR lanes
+};
+
+fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Resolved &r) {
+    const double d = prm->damping;
+    if (!(d > 0.0 && d < 1.0)) return fail(ctx, FL_EINVAL, "damping must be in (0,1)");
+    if (!(prm->p >= 0.0) || !isfinite(prm->p)) return fail(ctx, FL_EINVAL, "p must be finite and >= 0");
+    if (!(prm->tol_l1 >= 0.0) || !isfinite(prm->tol_l1)) return fail(ctx, FL_EINVAL, "tol_l1 must be finite and >= 0");
+    if (prm->max_iter < 0) return fail(ctx, FL_EINVAL, "max_iter must be >= 0");
+    if (prm->row_mapping != 0 && prm->row_mapping != FL_ROWS_SLOTS && !valid_lanes(prm->row_mapping))
+        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS or a power of two <= 64");
+    if (prm->row_mapping == FL_ROWS_SLOTS && p->sl.words == 0)
+        return fail(ctx, FL_EINVAL, "the slot sweep needs at most %d candidate slots (space has %d)",
+                    fl::kMaxSlots, p->sl.k);
+    r.d = d;
+    r.p = prm->p;
+    r.tol = prm->tol_l1 > 0.0 ? prm->tol_l1 : 2e-7;
+    r.max_iter = prm->max_iter > 0 ? prm->max_iter : 1000;
+    r.lanes = prm->row_mapping ? prm->row_mapping : (p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e));
+    return FL_OK;
+}
+
+// y, x (x in raw-index space for the slot sweep) and the state of a plan.
+fl_status ensure_pr_buffers(fl_ctx *ctx, fl_plan *p, bool slots) {
+    if (!p->state) {
+        for (int j = 0; j < 2; ++j) p->y[j] = pool_alloc<float>(ctx, p->n);
+        p->state = pool_alloc<PrState>(ctx, 1);
+        if (!p->y[0] || !p->y[1] || !p->state) return fail(ctx, FL_ENOMEM, "device allocation failed");
+    }
+    const int64_t x_need = slots ? p->n_raw : p->n;
+    if (x_need > p->x_cap) {
+        for (int j = 0; j < 2; ++j) {
+            ctx->pool.release(p->x[j]);
+            p->x[j] = pool_alloc<float>(ctx, x_need);
+        }
+        if (!p->x[0] || !p->x[1]) return fail(ctx, FL_ENOMEM, "device allocation failed");
+        p->x_cap = x_need;
+    }
+    return FL_OK;
+}
+
+int32_t tiles_of(const fl_plan *p) { return (int32_t)((p->n + fl::kBlock - 1) / fl::kBlock); }
+
+fl_status ensure_partials(fl_ctx *ctx, fl_plan *p, int64_t triples) {
+    if (triples <= p->pr_grid) return FL_OK;
+    ctx->pool.release(p->partials);
+    p->partials = pool_alloc<double>(ctx, 3 * triples);
+    if (!p->partials) {
+        p->pr_grid = 0;
+        return fail(ctx, FL_ENOMEM, "device allocation failed");
+    }
+    p->pr_grid = (int)triples;
+    return FL_OK;
+}
+
+int32_t x_bytes_of(const fl_plan *p) {
+    return 4 * p->n_raw < (int64_t(1) << 31) ? (int32_t)(4 * p->n_raw) : 0;
+}
+
+void fill_summary(const fl_plan *p, const PrState &hs, int lanes, fl_status status, fl_summary *out) {
+    fill_sizes(p, out);
+    out->iterations = hs.k;
+    out->row_mapping = lanes;
+    out->status = status;
+    out->residual_l1 = hs.resid;
+    out->mass_minima = hs.score_den;
+    out->mass_near = hs.score_num;
+    out->score = hs.score_den > 0.0 ? hs.score_num / hs.score_den : 0.0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batches: members swept together by the segmented kernels, joining and
+// leaving at step boundaries (continuous batching).
+
+struct fl_batch {
+    struct Member {
+        fl_plan *plan = nullptr;
+        Resolved prm{};
+        double *out_pr = nullptr;
+        int32_t *out_min = nullptr;
+        int64_t tag = 0;
+        int slot = -1;    // row of the device member table
+        int phase = 0;    // 0 waiting for initialisation, 1 running, 2 finished
+        fl_summary sum{};
+    };
+    fl_ctx *ctx = nullptr;
+    std::vector<Member> members;
+    std::vector<int> free_slots;
+    int capacity = 0;
+    fl::BatchMember *d_members = nullptr, *h_members = nullptr;
+    fl::TileRef *d_tiles = nullptr, *h_tiles = nullptr;  // regions: init | sweep | output
+    int64_t tile_cap = 0;
+    int32_t *d_ids = nullptr, *h_ids = nullptr;  // regions: init | running | finishing
+    PrState *d_states = nullptr, *h_states = nullptr;
+    int sweep_per_cu[fl::kMaxWords + 1] = {};
+    int64_t sweeps = 0;
+    double sweep_ms = 0.0;
+    hipEvent_t ev[2] = {};
+};
+
+namespace {
+
+void batch_free_tables(fl_batch *b) {
+    fl_ctx *ctx = b->ctx;
+    ctx->pool.release(b->d_members);
+    ctx->pool.release(b->d_tiles);
+    ctx->pool.release(b->d_ids);
+    ctx->pool.release(b->d_states);
+    if (b->h_members) (void)hipHostFree(b->h_members);
+    if (b->h_tiles) (void)hipHostFree(b->h_tiles);
+    if (b->h_ids) (void)hipHostFree(b->h_ids);
+    if (b->h_states) (void)hipHostFree(b->h_states);
+    b->d_members = b->h_members = nullptr;
+    b->d_tiles = b->h_tiles = nullptr;
+    b->d_ids = b->h_ids = nullptr;
+    b->d_states = b->h_states = nullptr;
+}
+
+// Member table, id lists and state snapshots for `cap` members and `tiles`
+// tiles (three regions each).  Only called between steps.
+fl_status batch_reserve(fl_batch *b, int cap, int64_t tiles) {
+    fl_ctx *ctx = b->ctx;
+    if (cap <= b->capacity && tiles <= b->tile_cap) return FL_OK;
+    const int new_cap = std::max(cap, std::max(16, 2 * b->capacity));
+    const int64_t new_tiles = std::max<int64_t>(tiles, std::max<int64_t>(1024, 2 * b->tile_cap));
+    fl::BatchMember *dm = pool_alloc<fl::BatchMember>(ctx, new_cap);
+    fl::TileRef *dt = pool_alloc<fl::TileRef>(ctx, 3 * new_tiles);
+    int32_t *di = pool_alloc<int32_t>(ctx, 3 * (int64_t)new_cap);
+    PrState *ds = pool_alloc<PrState>(ctx, new_cap);
+    fl::BatchMember *hm = nullptr;
+    fl::TileRef *ht = nullptr;
+    int32_t *hi = nullptr;
+    PrState *hs = nullptr;
+    if (!dm || !dt || !di || !ds ||
+        hipHostMalloc((void **)&hm, sizeof(fl::BatchMember) * new_cap, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ht, sizeof(fl::TileRef) * 3 * new_tiles, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&hi, sizeof(int32_t) * 3 * new_cap, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&hs, sizeof(PrState) * new_cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->pool.release(dm);
+        ctx->pool.release(dt);
+        ctx->pool.release(di);
+        ctx->pool.release(ds);
+        if (hm) (void)hipHostFree(hm);
+        if (ht) (void)hipHostFree(ht);
+        if (hi) (void)hipHostFree(hi);
+        if (hs) (void)hipHostFree(hs);
+        return fail(ctx, FL_ENOMEM, "batch tables: allocation failed");
+    }
+    if (b->h_members) memcpy(hm, b->h_members, sizeof(fl::BatchMember) * b->capacity);
+    batch_free_tables(b);
+    b->d_members = dm;
+    b->h_members = hm;
+    b->d_tiles = dt;
+    b->h_tiles = ht;
+    b->d_ids = di;
+    b->h_ids = hi;
+    b->d_states = ds;
+    b->h_states = hs;
+    for (int j = b->capacity; j < new_cap; ++j) b->free_slots.push_back(j);
+    b->capacity = new_cap;
+    b->tile_cap = new_tiles;
+    return FL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -274,132 +628,30 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
                          fl_neighbourhood nb, fl_plan **out, fl_summary *sizes) {
     if (!ctx) return FL_EINVAL;
     ctx->err.clear();
-    if (!out || !space || !d_fitness_raw) return fail(ctx, FL_EINVAL, "null argument");
+    if (!out) return fail(ctx, FL_EINVAL, "null argument");
     *out = nullptr;
-    if (space->n_params < 1 || space->n_params > fl::kMaxParams || !space->radix)
-        return fail(ctx, FL_EINVAL, "n_params must be in [1, %d]", fl::kMaxParams);
-    if (nb != FL_NB_HAMMING && nb != FL_NB_ADJACENT)
-        return fail(ctx, FL_EINVAL, "unknown neighbourhood %d", (int)nb);
-    SpaceDesc sp{};
-    sp.n = space->n_params;
-    int64_t n_raw = 1;
-    for (int i = 0; i < sp.n; ++i) {
-        if (space->radix[i] < 1) return fail(ctx, FL_EINVAL, "radix[%d] = %d < 1", i, space->radix[i]);
-        sp.radix[i] = space->radix[i];
-        n_raw *= space->radix[i];
-        if (n_raw >= (int64_t(1) << 31)) return fail(ctx, FL_EOVERFLOW, "prod radix >= 2^31");
-    }
-    for (int i = sp.n - 1; i >= 0; --i) sp.stride[i] = (i == sp.n - 1) ? 1 : sp.stride[i + 1] * sp.radix[i + 1];
-    sp.n_raw = (int32_t)n_raw;
-    set_magic(sp);
     FL_HIP(hipSetDevice(ctx->device));
-
-    fl_plan *p = new (std::nothrow) fl_plan;
-    if (!p) return fail(ctx, FL_ENOMEM, "out of host memory");
-    p->ctx = ctx;
-    p->sp = sp;
-    p->adjacent = (nb == FL_NB_ADJACENT);
-    p->sl = make_slots(sp, p->adjacent);
-    p->n_raw = n_raw;
-    for (auto &e : p->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            (void)hipGetLastError();
-            delete p;
-            return fail(ctx, FL_EHIP, "hipEventCreate failed");
-        }
-    }
-    p->have_events = true;
-    hipStream_t s = ctx->stream;
-
-    // scratch that lives only during the build
-    const int64_t c_tiles = (n_raw + fl::kCompactTile - 1) / fl::kCompactTile;
-    int32_t *remap = pool_alloc<int32_t>(ctx, n_raw);
-    int32_t *tile_cnt = pool_alloc<int32_t>(ctx, c_tiles);
-    int32_t *tile_bad = pool_alloc<int32_t>(ctx, c_tiles);
-    int32_t *tile_off = pool_alloc<int32_t>(ctx, c_tiles);
-    float *tile_min = pool_alloc<float>(ctx, c_tiles);
-    BuildSizes *d_sizes = pool_alloc<BuildSizes>(ctx, 1);
-    p->valid_raw = pool_alloc<int32_t>(ctx, n_raw);
-    p->fit_c = pool_alloc<float>(ctx, n_raw);
-    std::vector<void *> scratch = {remap, tile_cnt, tile_bad, tile_off, tile_min, d_sizes};
-    auto cleanup = [&](fl_status st) {
-        (void)hipStreamSynchronize(s);
-        for (void *b : scratch) ctx->pool.release(b);
-        if (st != FL_OK) {
-            release_plan_buffers(p);
-            for (auto &e : p->ev) (void)hipEventDestroy(e);
-            delete p;
-        }
-        return st;
+    Build b;
+    b.h_sizes = ctx->h_sizes;
+    auto sync = [&]() {
+        if (b.status != FL_OK) return;
+        hipError_t he = hipStreamSynchronize(ctx->stream);
+        if (he != hipSuccess) build_fail(b, FL_EHIP, "%s", hipGetErrorString(he));
     };
-    for (void *b : scratch)
-        if (!b) return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
-    if (!p->valid_raw || !p->fit_c) return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
-
-    hipError_t he = hipEventRecord(p->ev[0], s);
-    if (he == hipSuccess)
-        he = fl::launch_compact(d_fitness_raw, sp.n_raw, tile_cnt, tile_min, tile_bad, tile_off, remap,
-                                p->valid_raw, p->fit_c, d_sizes, s);
-    if (he == hipSuccess) he = hipMemcpyAsync(ctx->h_sizes, d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
-    if (he == hipSuccess) he = hipStreamSynchronize(s);
-    if (he != hipSuccess) return cleanup(fail(ctx, FL_EHIP, "compaction: %s", hipGetErrorString(he)));
-    if (ctx->h_sizes->n_bad > 0)
-        return cleanup(fail(ctx, FL_EINVAL, "%d fitness values are <= 0 or -inf", ctx->h_sizes->n_bad));
-    const int32_t n = ctx->h_sizes->n_valid;
-    if (n == 0) return cleanup(fail(ctx, FL_EINVAL, "no valid configuration (all NaN / +inf)"));
-    p->n = n;
-    p->f_opt = ctx->h_sizes->f_opt;
-
-    const int64_t n_tiles = (n + fl::kBlock - 1) / fl::kBlock;
-    int32_t *in_deg = pool_alloc<int32_t>(ctx, n);
-    int64_t *tile_e = pool_alloc<int64_t>(ctx, n_tiles);
-    int64_t *tile_eoff = pool_alloc<int64_t>(ctx, n_tiles);
-    int32_t *tile_m = pool_alloc<int32_t>(ctx, n_tiles);
-    int32_t *tile_moff = pool_alloc<int32_t>(ctx, n_tiles);
-    scratch.insert(scratch.end(), {in_deg, tile_e, tile_eoff, tile_m, tile_moff});
-    p->out_deg = pool_alloc<int32_t>(ctx, n);
-    p->row_ptr = pool_alloc<int32_t>(ctx, (int64_t)n + 1);
-    p->minima = pool_alloc<int32_t>(ctx, n);
-    if (p->sl.words > 0) {
-        p->rec = pool_alloc<uint64_t>(ctx, (int64_t)n * p->sl.words);
-        p->presence = pool_alloc<uint64_t>(ctx, ((int64_t)n + 63) / 64 * p->sl.words);
+    build_begin(ctx, b, space, d_fitness_raw, nb);
+    sync();
+    build_degree(ctx, b);
+    sync();
+    build_fill(ctx, b);
+    (void)hipStreamSynchronize(ctx->stream);
+    build_end(ctx, b);
+    if (b.status != FL_OK) {
+        build_abort(ctx, b);
+        return fail(ctx, b.status, "%s", b.err.c_str());
     }
-    for (void *b : scratch)
-        if (!b) return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
-    if (!p->out_deg || !p->row_ptr || !p->minima || (p->sl.words > 0 && (!p->rec || !p->presence)))
-        return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
-
-    he = fl::launch_degree(sp, p->sl, p->adjacent, d_fitness_raw, p->valid_raw, n, in_deg, p->out_deg, p->rec,
-                           p->presence, tile_e, tile_m, tile_eoff, tile_moff, d_sizes, s);
-    if (he == hipSuccess) he = hipMemcpyAsync(ctx->h_sizes, d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
-    if (he == hipSuccess) he = hipStreamSynchronize(s);
-    if (he != hipSuccess) return cleanup(fail(ctx, FL_EHIP, "degree count: %s", hipGetErrorString(he)));
-    const int64_t e = ctx->h_sizes->n_edges;
-    if (e >= (int64_t(1) << 31)) return cleanup(fail(ctx, FL_EOVERFLOW, "edge count %lld >= 2^31", (long long)e));
-    p->e = e;
-    p->m = ctx->h_sizes->n_minima;
-    p->col_idx = pool_alloc<int32_t>(ctx, e);
-    if (!p->col_idx) return cleanup(fail(ctx, FL_ENOMEM, "device allocation failed"));
-
-    he = fl::launch_fill(sp, p->sl, p->adjacent, d_fitness_raw, p->valid_raw, remap, p->rec, n, (int32_t)e,
-                         in_deg, p->out_deg, tile_eoff, tile_moff, p->row_ptr, p->col_idx, p->minima, s);
-    if (he == hipSuccess) he = hipEventRecord(p->ev[1], s);
-    if (he == hipSuccess) he = hipStreamSynchronize(s);
-    if (he != hipSuccess) return cleanup(fail(ctx, FL_EHIP, "CSR fill: %s", hipGetErrorString(he)));
-    p->timing.build_ms = elapsed(p->ev[0], p->ev[1]);
-
-    if (sizes) {
-        memset(sizes, 0, sizeof *sizes);
-        sizes->n_raw = p->n_raw;
-        sizes->n_valid = p->n;
-        sizes->n_edges = p->e;
-        sizes->n_minima = p->m;
-        sizes->n_slots = p->sl.k;
-        sizes->mask_words = p->sl.words;
-        sizes->f_opt = (double)p->f_opt;
-    }
-    *out = p;
-    return cleanup(FL_OK);
+    if (sizes) fill_sizes(b.p, sizes);
+    *out = b.p;
+    return FL_OK;
 }
 
 fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pagerank,
@@ -408,20 +660,10 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     ctx->err.clear();
     if (!p || !prm || !d_pagerank || (!d_minima && p->m > 0)) return fail(ctx, FL_EINVAL, "null argument");
     if (p->ctx != ctx) return fail(ctx, FL_EINVAL, "plan belongs to another context");
-    const double d = prm->damping;
-    if (!(d > 0.0 && d < 1.0)) return fail(ctx, FL_EINVAL, "damping must be in (0,1)");
-    if (!(prm->p >= 0.0) || !isfinite(prm->p)) return fail(ctx, FL_EINVAL, "p must be finite and >= 0");
-    if (!(prm->tol_l1 >= 0.0) || !isfinite(prm->tol_l1)) return fail(ctx, FL_EINVAL, "tol_l1 must be finite and >= 0");
-    if (prm->max_iter < 0) return fail(ctx, FL_EINVAL, "max_iter must be >= 0");
-    if (prm->row_mapping != 0 && prm->row_mapping != FL_ROWS_SLOTS && !valid_lanes(prm->row_mapping))
-        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS or a power of two <= 64");
-    if (prm->row_mapping == FL_ROWS_SLOTS && p->sl.words == 0)
-        return fail(ctx, FL_EINVAL, "the slot sweep needs at most %d candidate slots (space has %d)",
-                    fl::kMaxSlots, p->sl.k);
-    const double tol = prm->tol_l1 > 0.0 ? prm->tol_l1 : 2e-7;
-    const int32_t max_iter = prm->max_iter > 0 ? prm->max_iter : 1000;
-    int lanes = prm->row_mapping;
-    if (lanes == 0) lanes = p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e);
+    Resolved r;
+    fl_status st = resolve_params(ctx, p, prm, r);
+    if (st != FL_OK) return st;
+    const int lanes = r.lanes;
     const int kind = lanes == FL_ROWS_SLOTS ? fl::kSweepSlots : fl::kSweepCsr;
     FL_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
@@ -429,44 +671,31 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     PrArgs a{};
     a.kind = kind;
     a.adjacent = p->adjacent;
+    a.x_bytes = kind == fl::kSweepSlots ? x_bytes_of(p) : 0;
     // persistent grid: every workgroup resident at once (occupancy query), a
     // multiple of the XCD count so each XCD gets the same number of them
     int per_cu = 0;
     FL_HIP(fl::pr_iter_blocks_per_cu(a, p->sp, p->sl, lanes, &per_cu));
-    const int64_t resident = std::max<int64_t>(fl::kXcds, (int64_t)std::max(per_cu, 1) * ctx->num_cus / fl::kXcds * fl::kXcds);
+    const int64_t resident =
+        std::max<int64_t>(fl::kXcds, (int64_t)std::max(per_cu, 1) * ctx->num_cus / fl::kXcds * fl::kXcds);
     const int64_t rows_per_wg = kind == fl::kSweepSlots ? fl::kBlock : fl::kBlock / lanes;
     const int64_t groups = (p->n + rows_per_wg - 1) / rows_per_wg;
     const int grid = (int)std::min<int64_t>(resident, (groups + fl::kXcds - 1) / fl::kXcds * fl::kXcds);
-    const int64_t x_need = kind == fl::kSweepSlots ? p->n_raw : p->n;
-    if (!p->state) {
-        for (int j = 0; j < 2; ++j) p->y[j] = pool_alloc<float>(ctx, p->n);
-        p->state = pool_alloc<PrState>(ctx, 1);
-        if (!p->y[0] || !p->y[1] || !p->state) return fail(ctx, FL_ENOMEM, "device allocation failed");
-    }
-    if (x_need > p->x_cap) {
-        for (int j = 0; j < 2; ++j) {
-            ctx->pool.release(p->x[j]);
-            p->x[j] = pool_alloc<float>(ctx, x_need);
-        }
-        if (!p->x[0] || !p->x[1]) return fail(ctx, FL_ENOMEM, "device allocation failed");
-        p->x_cap = x_need;
-    }
-    // the init and iteration kernels each write 3 partial sums per workgroup
-    const int init_grid = (int)std::min<int64_t>((p->n + fl::kBlock - 1) / fl::kBlock, (int64_t)ctx->num_cus * 4);
-    const int need = std::max(grid, init_grid);
-    if (need > p->pr_grid) {
-        ctx->pool.release(p->partials);
-        p->partials = pool_alloc<double>(ctx, 3 * (int64_t)need);
-        if (!p->partials) return fail(ctx, FL_ENOMEM, "device allocation failed");
-        p->pr_grid = need;
-    }
+    st = ensure_pr_buffers(ctx, p, kind == fl::kSweepSlots);
+    if (st != FL_OK) return st;
+    // partial sums: one triple per tile (init, slot sweep) or per workgroup (CSR sweep)
+    const int32_t n_tiles = tiles_of(p);
+    const int init_grid = (int)std::min<int64_t>(n_tiles, (int64_t)ctx->num_cus * 4);
+    st = ensure_partials(ctx, p, std::max(grid, n_tiles));
+    if (st != FL_OK) return st;
     a.row_ptr = p->row_ptr;
     a.col_idx = p->col_idx;
     a.out_deg = p->out_deg;
     a.valid_raw = p->valid_raw;
     a.rec = p->rec;
     a.presence = p->presence;
-    a.x_bytes = (kind == fl::kSweepSlots && 4 * p->n_raw < (int64_t(1) << 31)) ? (int32_t)(4 * p->n_raw) : 0;
+    a.off = p->d_off;
+    a.k_slots = p->sl.k;
     a.y[0] = p->y[0];
     a.y[1] = p->y[1];
     a.x[0] = p->x[0];
@@ -474,9 +703,9 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     a.partials = p->partials;
     a.st = p->state;
     a.n = (int32_t)p->n;
-    a.d = d;
-    a.tol = tol;
-    a.max_iter = max_iter;
+    a.d = r.d;
+    a.tol = r.tol;
+    a.max_iter = r.max_iter;
 
     FL_HIP(hipEventRecord(p->ev[2], s));
     FL_HIP(hipMemsetAsync(p->state, 0, sizeof(PrState), s));
@@ -499,18 +728,18 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
         iterate_ms += elapsed(p->ev[5], p->ev[6]);
         if (hs->done) break;
         const double rate = (hs->resid_prev > 0.0) ? hs->resid / hs->resid_prev : 1.0;
-        if (rate > 0.0 && rate < 0.999 && hs->resid > tol) {
-            const double more = ceil(log(tol / hs->resid) / log(rate));
+        if (rate > 0.0 && rate < 0.999 && hs->resid > r.tol) {
+            const double more = ceil(log(r.tol / hs->resid) / log(rate));
             chunk = (int)std::min(64.0, std::max(2.0, more + 1.0));
         } else {
             chunk = 8;
         }
-        chunk = std::min(chunk, std::max(1, max_iter - hs->k));
+        chunk = std::min(chunk, std::max(1, r.max_iter - hs->k));
     }
     FL_HIP(hipEventRecord(p->ev[3], s));
     FL_HIP(fl::launch_pr_output(a, d_pagerank, s));
     if (p->m > 0) FL_HIP(hipMemcpyAsync(d_minima, p->minima, sizeof(int32_t) * p->m, hipMemcpyDeviceToDevice, s));
-    const double threshold = (1.0 + prm->p) * (double)p->f_opt;
+    const double threshold = (1.0 + r.p) * (double)p->f_opt;
     FL_HIP(fl::launch_score(d_pagerank, p->minima, (int32_t)p->m, p->fit_c, threshold, p->state, s));
     FL_HIP(hipEventRecord(p->ev[4], s));
     FL_HIP(hipMemcpyAsync(hs, p->state, sizeof(PrState), hipMemcpyDeviceToHost, s));
@@ -521,23 +750,9 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     p->timing.iterate_ms = iterate_ms;
     p->timing.iterations = hs->worked;
     p->timing.launches = launches;
-    if (out) {
-        memset(out, 0, sizeof *out);
-        out->n_raw = p->n_raw;
-        out->n_valid = p->n;
-        out->n_edges = p->e;
-        out->n_minima = p->m;
-        out->iterations = hs->k;
-        out->row_mapping = lanes;
-        out->n_slots = p->sl.k;
-        out->mask_words = p->sl.words;
-        out->residual_l1 = hs->resid;
-        out->f_opt = (double)p->f_opt;
-        out->mass_minima = hs->score_den;
-        out->mass_near = hs->score_num;
-        out->score = hs->score_den > 0.0 ? hs->score_num / hs->score_den : 0.0;
-    }
-    if (hs->done != 1)
+    const fl_status result = hs->done == 1 ? FL_OK : FL_ENOCONV;
+    if (out) fill_summary(p, *hs, lanes, result, out);
+    if (result != FL_OK)
         return fail(ctx, FL_ENOCONV, "no convergence after %d iterations (residual %.3e)", hs->k, hs->resid);
     return FL_OK;
 }
@@ -585,13 +800,355 @@ fl_status fl_analyze(fl_ctx *ctx, const fl_space *space, const float *d_fitness_
     if (st != FL_OK) return st;
     st = fl_execute(ctx, p, params, d_pagerank, d_minima, out);
     if (st == FL_OK || st == FL_ENOCONV) {
+        const std::string msg = ctx->err;
         const fl_status xs = fl_plan_export(ctx, p, d_valid_raw, nullptr, nullptr, nullptr);
         if (xs != FL_OK) st = xs;
+        else ctx->err = msg;
     }
     const std::string msg = ctx->err;
     fl_plan_destroy(ctx, p);
     ctx->err = msg;
     return st;
+}
+
+// ---- batches ----
+
+fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!out) return fail(ctx, FL_EINVAL, "null argument");
+    *out = nullptr;
+    FL_HIP(hipSetDevice(ctx->device));
+    fl_batch *b = new (std::nothrow) fl_batch;
+    if (!b) return fail(ctx, FL_ENOMEM, "out of host memory");
+    b->ctx = ctx;
+    for (int w = 1; w <= fl::kMaxWords; ++w) {
+        hipError_t he = fl::batch_sweep_blocks_per_cu(w, &b->sweep_per_cu[w]);
+        if (he != hipSuccess) {
+            delete b;
+            return fail(ctx, FL_EHIP, "occupancy query: %s", hipGetErrorString(he));
+        }
+    }
+    for (auto &e : b->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            delete b;
+            return fail(ctx, FL_EHIP, "hipEventCreate failed");
+        }
+    }
+    fl_status st = batch_reserve(b, 16, 1024);
+    if (st != FL_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return FL_OK;
+}
+
+fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *b) {
+    if (!ctx) return FL_EINVAL;
+    if (!b) return FL_OK;
+    if (b->ctx != ctx) return fail(ctx, FL_EINVAL, "batch belongs to another context");
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    batch_free_tables(b);
+    for (auto &e : b->ev) (void)hipEventDestroy(e);
+    delete b;
+    return FL_OK;
+}
+
+fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *prm, double *d_pagerank,
+                       int32_t *d_minima, int64_t tag) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!b || !p || !prm || !d_pagerank || (!d_minima && p->m > 0)) return fail(ctx, FL_EINVAL, "null argument");
+    if (b->ctx != ctx || p->ctx != ctx) return fail(ctx, FL_EINVAL, "batch or plan belongs to another context");
+    for (const auto &m : b->members)
+        if (m.plan == p) return fail(ctx, FL_EINVAL, "plan is already a member of this batch");
+    if (p->sl.words == 0 || x_bytes_of(p) == 0)
+        return fail(ctx, FL_EINVAL, "space has %d candidate slots or 2^29+ configurations: use fl_execute",
+                    p->sl.k);
+    Resolved r;
+    fl_status st = resolve_params(ctx, p, prm, r);
+    if (st != FL_OK) return st;
+    if (r.lanes != FL_ROWS_SLOTS) return fail(ctx, FL_EINVAL, "batches run the slot sweep only");
+    FL_HIP(hipSetDevice(ctx->device));
+    st = ensure_pr_buffers(ctx, p, true);
+    if (st != FL_OK) return st;
+    st = ensure_partials(ctx, p, tiles_of(p));
+    if (st != FL_OK) return st;
+    int64_t tiles = 0;
+    for (const auto &m : b->members) tiles += tiles_of(m.plan);
+    st = batch_reserve(b, (int)b->members.size() + 1, tiles + tiles_of(p));
+    if (st != FL_OK) return st;
+    fl_batch::Member m;
+    m.plan = p;
+    m.prm = r;
+    m.out_pr = d_pagerank;
+    m.out_min = d_minima;
+    m.tag = tag;
+    m.slot = b->free_slots.back();
+    b->free_slots.pop_back();
+    fl::BatchMember &bm = b->h_members[m.slot];
+    memset(&bm, 0, sizeof bm);
+    bm.rec = p->rec;
+    bm.presence = p->presence;
+    bm.off = p->d_off;
+    bm.valid_raw = p->valid_raw;
+    bm.out_deg = p->out_deg;
+    bm.minima = p->minima;
+    bm.fit_c = p->fit_c;
+    bm.y[0] = p->y[0];
+    bm.y[1] = p->y[1];
+    bm.x[0] = p->x[0];
+    bm.x[1] = p->x[1];
+    bm.partials = p->partials;
+    bm.st = p->state;
+    bm.out_pagerank = d_pagerank;
+    bm.out_minima = d_minima;
+    bm.d = r.d;
+    bm.tol = r.tol;
+    bm.threshold = (1.0 + r.p) * (double)p->f_opt;
+    bm.n = (int32_t)p->n;
+    bm.m = (int32_t)p->m;
+    bm.k_slots = p->sl.k;
+    bm.words = p->sl.words;
+    bm.x_bytes = x_bytes_of(p);
+    bm.n_tiles = tiles_of(p);
+    bm.max_iter = r.max_iter;
+    b->members.push_back(m);
+    return FL_OK;
+}
+
+fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_running) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!b || b->ctx != ctx) return fail(ctx, FL_EINVAL, "bad batch");
+    if (sweeps < 0) return fail(ctx, FL_EINVAL, "sweeps must be >= 0");
+    FL_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int64_t tc = b->tile_cap;
+    fl::TileRef *t_init = b->h_tiles, *t_sweep = b->h_tiles + tc, *t_out = b->h_tiles + 2 * tc;
+    int32_t *i_init = b->h_ids, *i_run = b->h_ids + b->capacity, *i_fin = b->h_ids + 2 * b->capacity;
+
+    // member table (rows of members that left are never read)
+    FL_HIP(hipMemcpyAsync(b->d_members, b->h_members, sizeof(fl::BatchMember) * b->capacity,
+                          hipMemcpyHostToDevice, s));
+    // members that joined since the last step: initial iterate
+    int32_t n_init = 0;
+    int64_t nt_init = 0;
+    for (auto &m : b->members) {
+        if (m.phase != 0) continue;
+        i_init[n_init++] = m.slot;
+        for (int32_t t = 0; t < tiles_of(m.plan); ++t) t_init[nt_init++] = {m.slot, t};
+        m.phase = 1;
+    }
+    if (n_init > 0) {
+        FL_HIP(hipMemcpyAsync(b->d_tiles, t_init, sizeof(fl::TileRef) * nt_init, hipMemcpyHostToDevice, s));
+        FL_HIP(hipMemcpyAsync(b->d_ids, i_init, sizeof(int32_t) * n_init, hipMemcpyHostToDevice, s));
+        FL_HIP(fl::launch_batch_init(b->d_members, b->d_tiles, (int32_t)nt_init, b->d_ids, n_init, s));
+    }
+    // running members, their tiles grouped by record width
+    int32_t n_run = 0;
+    int64_t group_begin[fl::kMaxWords + 2] = {};
+    int64_t nt = 0;
+    for (int w = 1; w <= fl::kMaxWords; ++w) {
+        group_begin[w] = nt;
+        for (auto &m : b->members) {
+            if (m.phase != 1 || m.plan->sl.words != w) continue;
+            i_run[n_run++] = m.slot;
+            for (int32_t t = 0; t < tiles_of(m.plan); ++t) t_sweep[nt++] = {m.slot, t};
+        }
+    }
+    group_begin[fl::kMaxWords + 1] = nt;
+    fl::TileRef *d_sweep = b->d_tiles + tc;
+    int32_t *d_run = b->d_ids + b->capacity;
+    if (n_run > 0 && sweeps > 0) {
+        FL_HIP(hipMemcpyAsync(d_sweep, t_sweep, sizeof(fl::TileRef) * nt, hipMemcpyHostToDevice, s));
+        FL_HIP(hipMemcpyAsync(d_run, i_run, sizeof(int32_t) * n_run, hipMemcpyHostToDevice, s));
+        FL_HIP(hipEventRecord(b->ev[0], s));
+        for (int32_t j = 0; j < sweeps; ++j) {
+            for (int w = 1; w <= fl::kMaxWords; ++w) {
+                const int64_t cnt = group_begin[w + 1] - group_begin[w];
+                if (cnt == 0) continue;
+                const int64_t resident = (int64_t)std::max(b->sweep_per_cu[w], 1) * ctx->num_cus / fl::kXcds * fl::kXcds;
+                const int grid = (int)std::max<int64_t>(
+                    fl::kXcds, std::min<int64_t>(resident, (cnt + fl::kXcds - 1) / fl::kXcds * fl::kXcds));
+                FL_HIP(fl::launch_batch_sweep(b->d_members, d_sweep + group_begin[w], (int32_t)cnt, w, grid, s));
+            }
+            FL_HIP(fl::launch_batch_finish(b->d_members, d_run, n_run, s));
+        }
+        FL_HIP(hipEventRecord(b->ev[1], s));
+        b->sweeps += sweeps;
+    }
+    // state of every running member
+    if (n_run > 0) {
+        FL_HIP(fl::launch_batch_states(b->d_members, d_run, n_run, b->d_states, s));
+        FL_HIP(hipMemcpyAsync(b->h_states, b->d_states, sizeof(PrState) * n_run, hipMemcpyDeviceToHost, s));
+    }
+    FL_HIP(hipStreamSynchronize(s));
+    if (n_run > 0 && sweeps > 0) b->sweep_ms += elapsed(b->ev[0], b->ev[1]);
+    // members that stopped: ranks, minima, C_p
+    int32_t n_fin = 0;
+    int64_t nt_fin = 0;
+    std::vector<int> fin_index;
+    for (int32_t j = 0; j < n_run; ++j) {
+        if (!b->h_states[j].done) continue;
+        for (size_t q = 0; q < b->members.size(); ++q) {
+            if (b->members[q].slot != i_run[j]) continue;
+            fl_batch::Member &m = b->members[q];
+            i_fin[n_fin++] = m.slot;
+            fin_index.push_back((int)q);
+            for (int32_t t = 0; t < tiles_of(m.plan); ++t) t_out[nt_fin++] = {m.slot, t};
+        }
+    }
+    if (n_fin > 0) {
+        fl::TileRef *d_out = b->d_tiles + 2 * tc;
+        int32_t *d_fin = b->d_ids + 2 * b->capacity;
+        FL_HIP(hipMemcpyAsync(d_out, t_out, sizeof(fl::TileRef) * nt_fin, hipMemcpyHostToDevice, s));
+        FL_HIP(hipMemcpyAsync(d_fin, i_fin, sizeof(int32_t) * n_fin, hipMemcpyHostToDevice, s));
+        FL_HIP(fl::launch_batch_output(b->d_members, d_out, (int32_t)nt_fin, d_fin, n_fin, b->d_states, s));
+        FL_HIP(hipMemcpyAsync(b->h_states, b->d_states, sizeof(PrState) * n_fin, hipMemcpyDeviceToHost, s));
+        FL_HIP(hipStreamSynchronize(s));
+        for (int32_t j = 0; j < n_fin; ++j) {
+            fl_batch::Member &m = b->members[fin_index[j]];
+            const PrState &hs = b->h_states[j];
+            fill_summary(m.plan, hs, FL_ROWS_SLOTS, hs.done == 1 ? FL_OK : FL_ENOCONV, &m.sum);
+            m.phase = 2;
+        }
+    }
+    if (n_running) {
+        int32_t cnt = 0;
+        for (const auto &m : b->members) cnt += (m.phase != 2);
+        *n_running = cnt;
+    }
+    return FL_OK;
+}
+
+fl_status fl_batch_collect(fl_ctx *ctx, fl_batch *b, int32_t max, int64_t *tags, fl_summary *out,
+                           int32_t *n_out) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!b || b->ctx != ctx || !n_out || max < 0 || (max > 0 && (!tags || !out)))
+        return fail(ctx, FL_EINVAL, "bad argument");
+    int32_t n = 0;
+    for (size_t q = 0; q < b->members.size() && n < max;) {
+        fl_batch::Member &m = b->members[q];
+        if (m.phase != 2) {
+            ++q;
+            continue;
+        }
+        tags[n] = m.tag;
+        out[n] = m.sum;
+        ++n;
+        b->free_slots.push_back(m.slot);
+        b->members.erase(b->members.begin() + (long)q);
+    }
+    *n_out = n;
+    return FL_OK;
+}
+
+fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *b, int64_t *sweeps, double *sweep_ms) {
+    if (!ctx) return FL_EINVAL;
+    if (!b || b->ctx != ctx) return fail(ctx, FL_EINVAL, "bad batch");
+    if (sweeps) *sweeps = b->sweeps;
+    if (sweep_ms) *sweep_ms = b->sweep_ms;
+    return FL_OK;
+}
+
+fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces, const float *const *d_fitness_raw,
+                           const fl_neighbourhood *nb, const fl_params *prm, double *const *d_pagerank,
+                           int32_t *const *d_minima, fl_summary *out) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (n_spaces < 0 || (n_spaces > 0 && (!spaces || !d_fitness_raw || !nb || !prm || !d_pagerank || !d_minima || !out)))
+        return fail(ctx, FL_EINVAL, "bad argument");
+    FL_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    // build every FFG with one synchronisation per stage
+    std::vector<Build> builds((size_t)n_spaces);
+    BuildSizes *h_sizes = nullptr;
+    if (n_spaces > 0 &&
+        hipHostMalloc((void **)&h_sizes, sizeof(BuildSizes) * n_spaces, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, FL_ENOMEM, "pinned allocation failed");
+    }
+    for (int32_t j = 0; j < n_spaces; ++j) {
+        builds[j].h_sizes = h_sizes + j;
+        build_begin(ctx, builds[j], &spaces[j], d_fitness_raw[j], nb[j]);
+    }
+    (void)hipStreamSynchronize(s);
+    for (auto &bd : builds) build_degree(ctx, bd);
+    (void)hipStreamSynchronize(s);
+    for (auto &bd : builds) build_fill(ctx, bd);
+    hipError_t he = hipStreamSynchronize(s);
+    for (auto &bd : builds) {
+        if (he != hipSuccess && bd.status == FL_OK) build_fail(bd, FL_EHIP, "%s", hipGetErrorString(he));
+        build_end(ctx, bd);
+    }
+    (void)hipHostFree(h_sizes);
+    fl_status worst = FL_OK;
+    std::vector<fl_status> status((size_t)n_spaces, FL_OK);
+    // PageRank: batchable spaces together, the others one at a time
+    fl_batch *b = nullptr;
+    fl_status st = fl_batch_create(ctx, &b);
+    if (st != FL_OK) {
+        for (auto &bd : builds) build_abort(ctx, bd);
+        return st;
+    }
+    int32_t in_batch = 0;
+    for (int32_t j = 0; j < n_spaces; ++j) {
+        memset(&out[j], 0, sizeof out[j]);
+        Build &bd = builds[j];
+        if (bd.status != FL_OK) {
+            status[j] = bd.status;
+            out[j].status = bd.status;
+            continue;
+        }
+        fl_plan *p = bd.p;
+        Resolved r;
+        if (resolve_params(ctx, p, &prm[j], r) != FL_OK) {
+            status[j] = FL_EINVAL;
+            out[j].status = FL_EINVAL;
+            fill_sizes(p, &out[j]);
+            out[j].status = FL_EINVAL;
+            continue;
+        }
+        if (p->sl.words > 0 && x_bytes_of(p) > 0 && r.lanes == FL_ROWS_SLOTS) {
+            st = fl_batch_add(ctx, b, p, &prm[j], d_pagerank[j], d_minima[j], j);
+            if (st == FL_OK) {
+                ++in_batch;
+                continue;
+            }
+        }
+        st = fl_execute(ctx, p, &prm[j], d_pagerank[j], d_minima[j], &out[j]);
+        status[j] = st;
+    }
+    int32_t running = in_batch;
+    while (running > 0 && st != FL_EHIP) {
+        st = fl_batch_step(ctx, b, 8, &running);
+        if (st != FL_OK) break;
+        int64_t tags[64];
+        fl_summary sums[64];
+        int32_t got = 0;
+        do {
+            fl_batch_collect(ctx, b, 64, tags, sums, &got);
+            for (int32_t q = 0; q < got; ++q) {
+                out[tags[q]] = sums[q];
+                status[tags[q]] = (fl_status)sums[q].status;
+            }
+        } while (got == 64);
+    }
+    const std::string msg = ctx->err;
+    fl_batch_destroy(ctx, b);
+    for (auto &bd : builds)
+        if (bd.p) fl_plan_destroy(ctx, bd.p);
+    ctx->err = msg;
+    if (st != FL_OK) return st;
+    for (int32_t j = 0; j < n_spaces; ++j)
+        if (status[j] != FL_OK && (worst == FL_OK || worst == FL_ENOCONV)) worst = status[j];
+    if (worst != FL_OK && ctx->err.empty()) ctx->err = "at least one space failed; see the per-space status";
+    return worst;
 }
 
 }  // extern "C"

@@ -87,9 +87,11 @@ struct PrArgs {
     const int32_t *valid_raw;
     const uint64_t *rec;    // node records (SlotTable), slot sweep only
     const uint64_t *presence;  // per wave of 64 nodes: OR of their in-edge slot bits
+    const int32_t *off;     // slot raw-index offsets (device copy of SlotTable.off)
+    int32_t k_slots;
     float *y[2];            // ping-pong iterate (node ids), slot k&1 holds y_k
     float *x[2];            // y / out_deg (0 at sinks): node ids (CSR) or raw indices (slots)
-    double *partials;       // 3 * grid doubles: per-workgroup sums
+    double *partials;       // 3 doubles per tile (slot sweep) or per workgroup (CSR sweep)
     PrState *st;
     int32_t n;              // N
     int32_t kind;           // SweepKind
@@ -98,6 +100,31 @@ struct PrArgs {
     int32_t max_iter;
     int32_t adjacent;
     int32_t x_bytes;        // bytes of each x buffer when < 2^31 (slot sweep uses buffer loads), else 0
+};
+
+// One member of a batch: an FFG with its own power iteration, run together
+// with the other members in segmented launches.  Device resident.
+struct BatchMember {
+    const uint64_t *rec;       // node records
+    const uint64_t *presence;  // per-wave slot presence
+    const int32_t *off;        // slot raw-index offsets (k_slots, ascending)
+    const int32_t *valid_raw;
+    const int32_t *out_deg;
+    const int32_t *minima;
+    const float *fit_c;
+    float *y[2];
+    float *x[2];               // raw-index space
+    double *partials;          // 3 per tile: sum y, residual, sink sum
+    PrState *st;
+    double *out_pagerank;      // caller's outputs
+    int32_t *out_minima;
+    double d, tol, threshold;
+    int32_t n, m, k_slots, words, x_bytes, n_tiles, max_iter, pad;
+};
+
+struct TileRef {
+    int32_t member;  // index into the member table
+    int32_t tile;    // tile of that member (kBlock nodes)
 };
 
 // ---- launchers (fl_kernels.hip); all enqueue on `stream` ----
@@ -123,5 +150,20 @@ hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const Slo
 hipError_t launch_pr_output(const PrArgs &a, double *pagerank, hipStream_t stream);
 hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m,
                         const float *fit_c, double threshold, PrState *st, hipStream_t stream);
+
+// Batched power iteration.  `tiles` lists the tiles to work on; `members`
+// lists member indices for the per-member kernels.
+hipError_t launch_batch_init(const BatchMember *members, const TileRef *tiles, int32_t n_tiles,
+                             const int32_t *member_ids, int32_t n_members, hipStream_t stream);
+hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, int32_t n_tiles, int words,
+                              int grid, hipStream_t stream);
+hipError_t batch_sweep_blocks_per_cu(int words, int *blocks);
+hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, int32_t n_members,
+                               hipStream_t stream);
+hipError_t launch_batch_output(const BatchMember *members, const TileRef *tiles, int32_t n_tiles,
+                               const int32_t *member_ids, int32_t n_members, PrState *states_out,
+                               hipStream_t stream);
+hipError_t launch_batch_states(const BatchMember *members, const int32_t *member_ids, int32_t n_members,
+                               PrState *states_out, hipStream_t stream);
 
 }  // namespace fl

@@ -18,6 +18,8 @@
 // kBatch slots are issued back to back before any of them is used.
 #include <math.h>
 
+#include <algorithm>
+
 #include "fl_internal.h"
 
 namespace fl {
@@ -541,132 +543,152 @@ __global__ __launch_bounds__(kBlock) void k_fill_generic(SpaceDesc sp, const flo
 //   r'[w] = d * sum_{u->w} r[u]/out_deg(u) + (d * sum_{sinks} r + 1 - d) / N.
 // Stored iterate y_k = r_k up to s_k = 1/sum(y_k); x_k = y_k/out_deg.  The
 // edge sum is FP32; the per-node affine update, the residual
-// ||r_{k+1} - r_k||_1, the renormalisation and the sink mass are FP64.  Each
-// workgroup writes FP64 partial sums; the last one to finish (ticket) reduces
-// them in a fixed order and sets s, c and the stop flag for the next launch.
+// ||r_{k+1} - r_k||_1, the renormalisation and the sink mass are FP64.
+//
+// Each tile of kBlock nodes (each workgroup for the CSR sweep) writes its
+// three FP64 sums (sum y', sum |y' - r|, sum of y' over sinks) to its slot of
+// a partials array; a one-workgroup kernel then reduces them in a fixed order
+// and sets s, c, the residual and the stop flag for the next sweep.  (Having
+// the last workgroup of the sweep do this instead needs an agent-scope
+// release from every workgroup, which costs more than the extra launch.)
 
-// How the workgroups of a sweep hand their partial sums to the one that
-// finishes the step:
-//   0  each workgroup's ticket increment is an agent-scope acquire-release RMW;
-//   1  the increment only releases, and just the elected workgroup acquires;
-//   2  no ticket: a one-workgroup kernel finishes the step after the sweep.
-#ifndef FL_SYNC_MODE
-#define FL_SYNC_MODE 2
-#endif
-
-__device__ bool elect_last(uint32_t *ticket) {
-    __shared__ bool last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#if FL_SYNC_MODE == 0
-        const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-#else
-        const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-#endif
-        last = (t == gridDim.x - 1);
+// Sum three values over the workgroup (valid in every thread), fixed tree.
+__device__ void block_sum3(double &a, double &b, double &c) {
+    __shared__ double part[3][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if (lane == 0) {
+        part[0][wid] = a;
+        part[1][wid] = b;
+        part[2][wid] = c;
     }
     __syncthreads();
-    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return last;
+    a = part[0][0];
+    b = part[1][0];
+    c = part[2][0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) {
+        a += part[0][w];
+        b += part[1][w];
+        c += part[2][w];
+    }
+    __syncthreads();
 }
 
-// Reduce the g workgroups' partial sums in a fixed order and set up the next
-// step (s, c, residual, stop flag).  Runs in one workgroup.
-__device__ void pr_finish(const PrArgs &a, int g, bool first) {
+__device__ __forceinline__ void write_partials(double *partials, int32_t j, double ps, double pr, double pk) {
+    block_sum3(ps, pr, pk);
+    if (threadIdx.x == 0) {
+        double *pp = partials + 3 * (int64_t)j;
+        pp[0] = ps;
+        pp[1] = pr;
+        pp[2] = pk;
+    }
+}
+
+// Reduce `count` partial triples in a fixed order and set up the next step.
+// One workgroup.  first: the triples come from the initial iterate.
+__device__ void finish_step(PrState *st, const double *__restrict__ partials, int32_t count, double d, double tol,
+                            int32_t max_iter, int32_t n, bool first) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int b0 = 0; b0 < g; b0 += kBlock * 8) {
-        double v0[8], v1[8], v2[8];
+    for (int32_t t0 = 0; t0 < count; t0 += 4 * kBlock) {
+        double v[4][3];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int b = b0 + u * kBlock + threadIdx.x;
-            v0[u] = b < g ? __hip_atomic_load(&a.partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
-            v1[u] = b < g ? __hip_atomic_load(&a.partials[g + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
-            v2[u] = b < g ? __hip_atomic_load(&a.partials[2 * g + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+        for (int u = 0; u < 4; ++u) {
+            const int32_t t = t0 + u * kBlock + threadIdx.x;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v[u][q] = t < count ? partials[3 * (int64_t)t + q] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            s0 += v0[u];
-            s1 += v1[u];
-            s2 += v2[u];
+        for (int u = 0; u < 4; ++u) {
+            s0 += v[u][0];
+            s1 += v[u][1];
+            s2 += v[u][2];
         }
     }
-    s0 = block_sum(s0);
-    s1 = block_sum(s1);
-    s2 = block_sum(s2);
+    block_sum3(s0, s1, s2);
     if (threadIdx.x == 0) {
-        PrState *st = a.st;
-        const double sigma = s0, sink = s2;
-        const double s = 1.0 / sigma;
-        st->sigma = sigma;
-        st->sink = sink;
+        const double s = 1.0 / s0;
+        st->sigma = s0;
+        st->sink = s2;
         st->s = s;
-        st->c = (a.d * sink * s + (1.0 - a.d)) / (double)a.n;
-        if (!first) {
+        st->c = (d * s2 * s + (1.0 - d)) / (double)n;
+        if (first) {
+            st->k = 0;
+            st->done = 0;
+            st->worked = 0;
+            st->resid = 0.0;
+            st->resid_prev = 0.0;
+        } else {
             st->resid_prev = st->resid;
             st->resid = s1;
             st->k += 1;
             st->worked += 1;
-            if (s1 < a.tol)
+            if (s1 < tol)
                 st->done = 1;
-            else if (st->k >= a.max_iter)
+            else if (st->k >= max_iter)
                 st->done = 2;
         }
-        st->ticket = 0;
     }
 }
 
-__device__ __forceinline__ void pr_block_end(const PrArgs &a, double ps, double pr, double pk, bool first) {
-    ps = block_sum(ps);
-    pr = block_sum(pr);
-    pk = block_sum(pk);
-    const int g = gridDim.x;
-    if (threadIdx.x == 0) {
-        a.partials[blockIdx.x] = ps;
-        a.partials[g + blockIdx.x] = pr;
-        a.partials[2 * g + blockIdx.x] = pk;
-    }
-#if FL_SYNC_MODE != 2
-    if (elect_last(&a.st->ticket)) pr_finish(a, g, first);
-#else
-    (void)first;
-#endif
-}
-
-// Finishing kernel of sync mode 2 (one workgroup): skipped, like the sweep
-// it follows, once the stop flag is set.
+// Step kernel: skipped, like the sweep it follows, once the stop flag is set.
 template <bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_pr_finish(PrArgs a, int g) {
+__global__ __launch_bounds__(kBlock) void k_pr_finish(PrArgs a, int32_t count) {
     if (!FIRST && a.st->done) return;
-    pr_finish(a, g, FIRST);
+    finish_step(a.st, a.partials, count, a.d, a.tol, a.max_iter, a.n, FIRST);
+}
+
+// Initial iterate r = 1/N of one tile of kBlock nodes, with its partial sums.
+__device__ __forceinline__ void init_tile(int32_t tile, int32_t n, const int32_t *__restrict__ out_deg,
+                                          const int32_t *__restrict__ xmap, float *y0v, float *x0v,
+                                          double *partials) {
+    const int32_t v = tile * kBlock + threadIdx.x;
+    const float y0 = (float)(1.0 / (double)n);
+    double ps = 0.0, pk = 0.0;
+    if (v < n) {
+        const int32_t deg = out_deg[v];
+        y0v[v] = y0;
+        x0v[xmap ? xmap[v] : v] = deg > 0 ? y0 / (float)deg : 0.0f;
+        ps = (double)y0;
+        if (deg == 0) pk = (double)y0;
+    }
+    write_partials(partials, tile, ps, 0.0, pk);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
-    const float y0 = (float)(1.0 / (double)a.n);
-    double ps = 0.0, pk = 0.0;
-    for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += gridDim.x * kBlock) {
-        const int32_t deg = a.out_deg[v];
-        const int32_t xi = a.kind == kSweepSlots ? a.valid_raw[v] : v;
-        a.y[0][v] = y0;
-        a.x[0][xi] = deg > 0 ? y0 / (float)deg : 0.0f;
-        ps += (double)y0;
-        if (deg == 0) pk += (double)y0;
-    }
-    pr_block_end(a, ps, 0.0, pk, true);
+    const int32_t n_tiles = (a.n + kBlock - 1) / kBlock;
+    for (int32_t t = blockIdx.x; t < n_tiles; t += gridDim.x)
+        init_tile(t, a.n, a.out_deg, a.kind == kSweepSlots ? a.valid_raw : nullptr, a.y[0], a.x[0], a.partials);
 }
 
-// Tile t of the persistent grid, in "front" order: XCD j = b % 8 owns the
-// contiguous j-th eighth of the tiles, and its workgroups take consecutive
-// tiles in turn, so at any time an XCD sweeps a narrow band of nodes and the
-// x values that band gathers stay in its L2.
+// Tiles of the persistent grid.  XCD j = b % 8 owns the contiguous j-th
+// eighth of the tiles.  In "front" order (FL_TILE_ORDER 0) its workgroups
+// take consecutive tiles in turn, so at any time an XCD sweeps a narrow band
+// of nodes and the x values that band gathers stay in its L2; in "block"
+// order (1) each workgroup sweeps its own contiguous run of tiles.
+#ifndef FL_TILE_ORDER
+#define FL_TILE_ORDER 0
+#endif
 struct TileWalk {
     int32_t first, end, step;
     __device__ TileWalk(int32_t n_tiles) {
         const int g = gridDim.x;
         const int xcd = blockIdx.x % kXcds;
         const int32_t per = (n_tiles + kXcds - 1) / kXcds;
-        first = per * xcd + blockIdx.x / kXcds;
-        end = min(per * (xcd + 1), n_tiles);
-        step = g / kXcds;
+        const int32_t lo = per * xcd, hi = min(per * (xcd + 1), n_tiles);
+        const int nb = g / kXcds, l = blockIdx.x / kXcds;
+#if FL_TILE_ORDER == 0
+        first = lo + l;
+        end = hi;
+        step = nb;
+#else
+        const int32_t run = (per + nb - 1) / nb;
+        first = lo + l * run;
+        end = min(first + run, hi);
+        step = 1;
+#endif
     }
 };
 
@@ -722,7 +744,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
         for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
         if (lane == 0 && v < a.n) pr_node_update(a, v, v, acc, sd, c, s, y_in, y_out, x_out, ps, pr, pk);
     }
-    pr_block_end(a, ps, pr, pk, false);
+    write_partials(a.partials, blockIdx.x, ps, pr, pk);
 }
 
 // Slot sweep: one node per lane, 64 consecutive nodes per wave.  For every
@@ -733,75 +755,206 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
 // so the 32 loads of a batch issue back to back with no per-lane branching.
 // Slots run in ascending raw-index order, the order of the CSR rows, so the
 // FP32 sum equals the one-lane-per-row CSR sweep's bit for bit.
+// Slot sweep of one tile of kBlock nodes: one node per lane, 64 consecutive
+// nodes per wave.  For every candidate slot whose in-edge bit is set, gather
+// x at raw index i + off[s] (x lives in raw-index space, so neither col_idx
+// nor an index remap is read).  A slot no lane of the wave needs is skipped
+// with a scalar branch on the wave's presence word; the other lanes' loads of
+// that slot get an out-of-range buffer offset and return 0, so the 32 loads
+// of a batch issue back to back with no per-lane branching.  Slots run in
+// ascending raw-index order, the order of the CSR rows, so the FP32 sum
+// equals the one-lane-per-row CSR sweep's bit for bit.  The plain and the
+// batched sweep both run this routine, so their results agree bit for bit.
+struct SweepTile {
+    const uint64_t *rec, *presence;
+    const int32_t *off;  // slot offsets, device memory (read through the scalar unit)
+    const float *y_in, *x_in;
+    float *y_out, *x_out;
+    double *partials;
+    double s, c, sd;
+    int32_t n, k_slots, x_bytes;
+};
+
 template <int W, bool BUF>
-__global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a, SlotTable sl) {
+__device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
+    const __amdgpu_buffer_rsrc_t xr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)q.x_in, (short)0, q.x_bytes, 0x00020000);
+    const int32_t v = tile * kBlock + threadIdx.x;
+    const bool active = v < q.n;
+    Record<W> r;
+    float yin = 0.0f;
+    if (active) {
+        r = load_record<W>(q.rec, v);
+        yin = q.y_in[v];
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j) r.w[j] = 0ull;
+    }
+    const int32_t i = r.raw();
+    const uint32_t i4 = 4u * (uint32_t)i;
+    // this wave's slot presence, loaded through the scalar unit; a wave past
+    // the last node (in the last tile) has no entry and skips
+    const int32_t first = __builtin_amdgcn_readfirstlane(tile * kBlock + (int32_t)(threadIdx.x & ~63u));
+    const uint64_t *pw = q.presence + (int64_t)(first >> 6) * W;
+    const bool live = first < q.n;
+    float acc = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 2 * W; ++b) {
+        if (32 * b >= q.k_slots || !live) break;
+        const uint64_t pq = pw[b >> 1];
+        const uint32_t any = (b & 1) ? (uint32_t)(pq >> 32) : (uint32_t)pq;
+        if (any == 0u) continue;
+        const uint32_t bits = r.word32(b) & batch_mask(b, q.k_slots);
+        const uint32_t nbits = ~bits;
+        float val[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            val[u] = 0.0f;
+            if ((any >> u) & 1u) {
+                if (BUF) {
+                    // out-of-range offset (the load returns 0) where this lane's bit is clear
+                    const uint32_t byte = ((nbits << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)q.off[32 * b + u]);
+                    val[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, byte, 0, 0));
+                } else {
+                    val[u] = ((bits >> u) & 1u) ? q.x_in[i + q.off[32 * b + u]] : 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) acc += val[u];
+    }
+    double ps = 0.0, pr = 0.0, pk = 0.0;
+    if (active) {
+        const float yf = (float)(q.sd * (double)acc + q.c);
+        const int32_t deg = r.out_deg();
+        q.y_out[v] = yf;
+        q.x_out[i] = deg > 0 ? yf / (float)deg : 0.0f;
+        ps = (double)yf;
+        pr = fabs((double)yf - q.s * (double)yin);
+        if (deg == 0) pk = (double)yf;
+    }
+    write_partials(q.partials, tile, ps, pr, pk);
+}
+
+template <int W, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     const PrState *st = a.st;
     if (st->done) return;
     const int32_t k = st->k;
-    const float *__restrict__ y_in = a.y[k & 1];
-    const float *__restrict__ x_in = a.x[k & 1];
-    float *__restrict__ y_out = a.y[(k + 1) & 1];
-    float *__restrict__ x_out = a.x[(k + 1) & 1];
-    const double s = st->s, c = st->c;
-    const double sd = s * a.d;
-    const __amdgpu_buffer_rsrc_t xr =
-        __builtin_amdgcn_make_buffer_rsrc((void *)x_in, (short)0, a.x_bytes, 0x00020000);
+    SweepTile q;
+    q.rec = a.rec;
+    q.presence = a.presence;
+    q.off = a.off;
+    q.y_in = a.y[k & 1];
+    q.x_in = a.x[k & 1];
+    q.y_out = a.y[(k + 1) & 1];
+    q.x_out = a.x[(k + 1) & 1];
+    q.partials = a.partials;
+    q.s = st->s;
+    q.c = st->c;
+    q.sd = q.s * a.d;
+    q.n = a.n;
+    q.k_slots = a.k_slots;
+    q.x_bytes = a.x_bytes;
     const TileWalk w((a.n + kBlock - 1) / kBlock);
-    double ps = 0.0, pr = 0.0, pk = 0.0;
+    for (int32_t t = w.first; t < w.end; t += w.step) sweep_tile<W, BUF>(q, t);
+}
+
+// ---------------------------------------------------------------------------
+// Batched power iteration: many FFGs (members) swept together.  A tile list
+// names (member, tile) pairs; each tile reads its member's descriptor through
+// the scalar unit and writes its own three FP64 partial sums, so a member's
+// result does not depend on which other members share the launch.  A member
+// whose stop flag is set is skipped.
+
+template <int W, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchMember *__restrict__ members,
+                                                        const TileRef *__restrict__ tiles, int32_t n_tiles) {
+    const TileWalk w(n_tiles);
     for (int32_t t = w.first; t < w.end; t += w.step) {
-        const int32_t v = t * kBlock + threadIdx.x;
-        const bool active = v < a.n;
-        Record<W> r;
-        if (active) {
-            r = load_record<W>(a.rec, v);
-        } else {
-#pragma unroll
-            for (int q = 0; q < W; ++q) r.w[q] = 0ull;
-        }
-        const int32_t i = r.raw();
-        const uint32_t i4 = 4u * (uint32_t)i;
-        // this wave's slot presence, loaded through the scalar unit; a wave
-        // past the last node (in the last tile) has no entry and skips
-        const int32_t first = __builtin_amdgcn_readfirstlane(t * kBlock + (int32_t)(threadIdx.x & ~63u));
-        const uint64_t *pw = a.presence + (int64_t)(first >> 6) * W;
-        float acc = 0.0f;
-#pragma unroll
-        for (int b = 0; b < 2 * W; ++b) {
-            if (32 * b >= sl.k || first >= a.n) break;
-            const uint32_t bits = r.word32(b) & batch_mask(b, sl.k);
-            const uint64_t pq = pw[b >> 1];
-            const uint32_t any = (b & 1) ? (uint32_t)(pq >> 32) : (uint32_t)pq;
-            if (any == 0u) continue;
-            const uint32_t nbits = ~bits;
-            float val[32];
-#pragma unroll
-            for (int u = 0; u < 32; ++u) {
-                val[u] = 0.0f;
-                if ((any >> u) & 1u) {
-                    if (BUF) {
-                        // out-of-range offset (the load returns 0) where this lane's bit is clear
-                        const uint32_t byte = ((nbits << (31 - u)) & 0x80000000u) |
-                                              (i4 + 4u * (uint32_t)sl.off[32 * b + u]);
-                        val[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, byte, 0, 0));
-                    } else {
-                        val[u] = ((bits >> u) & 1u) ? x_in[i + sl.off[32 * b + u]] : 0.0f;
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 32; ++u) acc += val[u];
-        }
-        if (active) {
-            const float yf = (float)(sd * (double)acc + c);
-            const int32_t deg = r.out_deg();
-            y_out[v] = yf;
-            x_out[i] = deg > 0 ? yf / (float)deg : 0.0f;
-            ps += (double)yf;
-            pr += fabs((double)yf - s * (double)y_in[v]);
-            if (deg == 0) pk += (double)yf;
-        }
+        const TileRef tr = tiles[t];
+        const BatchMember &m = members[tr.member];
+        const PrState *st = m.st;
+        if (st->done) continue;
+        const int32_t k = st->k;
+        SweepTile q;
+        q.rec = m.rec;
+        q.presence = m.presence;
+        q.off = m.off;
+        q.y_in = m.y[k & 1];
+        q.x_in = m.x[k & 1];
+        q.y_out = m.y[(k + 1) & 1];
+        q.x_out = m.x[(k + 1) & 1];
+        q.partials = m.partials;
+        q.s = st->s;
+        q.c = st->c;
+        q.sd = q.s * m.d;
+        q.n = m.n;
+        q.k_slots = m.k_slots;
+        q.x_bytes = m.x_bytes;
+        sweep_tile<W, BUF>(q, tr.tile);
     }
-    pr_block_end(a, ps, pr, pk, false);
+}
+
+// Initial iterate r = 1/N of every listed tile, with its partial sums.
+__global__ __launch_bounds__(kBlock) void k_batch_init(const BatchMember *__restrict__ members,
+                                                       const TileRef *__restrict__ tiles, int32_t n_tiles) {
+    for (int32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const TileRef tr = tiles[t];
+        const BatchMember &m = members[tr.member];
+        init_tile(tr.tile, m.n, m.out_deg, m.valid_raw, m.y[0], m.x[0], m.partials);
+    }
+}
+
+// One workgroup per listed member: reduce its tiles' partial sums and set up
+// its next step, exactly as for a single space.
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_batch_finish(const BatchMember *__restrict__ members,
+                                                         const int32_t *__restrict__ member_ids) {
+    const BatchMember &m = members[member_ids[blockIdx.x]];
+    if (!FIRST && m.st->done) return;
+    finish_step(m.st, m.partials, m.n_tiles, m.d, m.tol, m.max_iter, m.n, FIRST);
+}
+
+// Ranks r = y * s into the member's output for every listed tile.
+__global__ __launch_bounds__(kBlock) void k_batch_output(const BatchMember *__restrict__ members,
+                                                         const TileRef *__restrict__ tiles, int32_t n_tiles) {
+    for (int32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const TileRef tr = tiles[t];
+        const BatchMember &m = members[tr.member];
+        const int32_t v = tr.tile * kBlock + threadIdx.x;
+        if (v < m.n) m.out_pagerank[v] = (double)m.y[m.st->k & 1][v] * m.st->s;
+    }
+}
+
+// One workgroup per listed member: copy its minima out, C_p sums (as k_score),
+// and a snapshot of its state into states_out[blockIdx.x].
+__global__ __launch_bounds__(kBlock) void k_batch_score(const BatchMember *__restrict__ members,
+                                                        const int32_t *__restrict__ member_ids,
+                                                        PrState *__restrict__ states_out) {
+    const BatchMember &m = members[member_ids[blockIdx.x]];
+    PrState *st = m.st;
+    double num = 0.0, den = 0.0;
+    for (int32_t j = threadIdx.x; j < m.m; j += kBlock) {
+        const int32_t v = m.minima[j];
+        m.out_minima[j] = v;
+        const double r = m.out_pagerank[v];
+        den += r;
+        if ((double)m.fit_c[v] <= m.threshold) num += r;
+    }
+    num = block_sum(num);
+    den = block_sum(den);
+    if (threadIdx.x == 0) {
+        st->score_num = num;
+        st->score_den = den;
+        states_out[blockIdx.x] = *st;
+    }
+}
+
+__global__ void k_batch_states(const BatchMember *__restrict__ members, const int32_t *__restrict__ member_ids,
+                               int32_t n_members, PrState *__restrict__ states_out) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n_members) states_out[j] = *members[member_ids[j]].st;
 }
 
 __global__ __launch_bounds__(kBlock) void k_pr_output(PrArgs a, double *__restrict__ pagerank) {
@@ -938,10 +1091,9 @@ hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, c
 }
 
 hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream) {
+    const int32_t n_tiles = (a.n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_pr_init, dim3(grid), dim3(kBlock), 0, stream, a);
-#if FL_SYNC_MODE == 2
-    hipLaunchKernelGGL(k_pr_finish<true>, dim3(1), dim3(kBlock), 0, stream, a, grid);
-#endif
+    hipLaunchKernelGGL(k_pr_finish<true>, dim3(1), dim3(kBlock), 0, stream, a, n_tiles);
     return hipGetLastError();
 }
 
@@ -956,22 +1108,14 @@ hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const Slo
 hipError_t launch_pr_iter(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
                           int grid, hipStream_t stream) {
     (void)sp;
-    if (a.kind == kSweepSlots) {
-        const void *fn = slot_sweep_kernel(a, sl.words);
-        if (!fn) return hipErrorInvalidValue;
-        void *args[] = {(void *)&a, (void *)&sl};
-        hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
-        if (e != hipSuccess) return e;
-    } else {
-        const void *fn = csr_sweep_kernel(lanes);
-        if (!fn) return hipErrorInvalidValue;
-        void *args[] = {(void *)&a};
-        hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
-        if (e != hipSuccess) return e;
-    }
-#if FL_SYNC_MODE == 2
-    hipLaunchKernelGGL(k_pr_finish<false>, dim3(1), dim3(kBlock), 0, stream, a, grid);
-#endif
+    const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(lanes);
+    if (!fn) return hipErrorInvalidValue;
+    void *args[] = {(void *)&a};
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+    if (e != hipSuccess) return e;
+    // partial sums: one triple per tile (slot sweep) or per workgroup (CSR sweep)
+    const int32_t count = a.kind == kSweepSlots ? (a.n + kBlock - 1) / kBlock : grid;
+    hipLaunchKernelGGL(k_pr_finish<false>, dim3(1), dim3(kBlock), 0, stream, a, count);
     return hipGetLastError();
 }
 
@@ -985,6 +1129,68 @@ hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m
                         const float *fit_c, double threshold, PrState *st, hipStream_t stream) {
     hipLaunchKernelGGL(k_score, dim3(1), dim3(kBlock), 0, stream, pagerank, minima, m, fit_c,
                        threshold, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const BatchMember *members, const TileRef *tiles, int32_t n_tiles,
+                             const int32_t *member_ids, int32_t n_members, hipStream_t stream) {
+    if (n_tiles > 0)
+        hipLaunchKernelGGL(k_batch_init, dim3(std::min<int32_t>(n_tiles, 8192)), dim3(kBlock), 0, stream, members,
+                           tiles, n_tiles);
+    if (n_members > 0)
+        hipLaunchKernelGGL(k_batch_finish<true>, dim3(n_members), dim3(kBlock), 0, stream, members, member_ids);
+    return hipGetLastError();
+}
+
+static const void *batch_sweep_kernel(int words) {
+    switch (words) {
+        case 1: return (const void *)k_batch_sweep<1, true>;
+        case 2: return (const void *)k_batch_sweep<2, true>;
+        case 3: return (const void *)k_batch_sweep<3, true>;
+        case 4: return (const void *)k_batch_sweep<4, true>;
+        case 5: return (const void *)k_batch_sweep<5, true>;
+        default: return nullptr;
+    }
+}
+
+hipError_t batch_sweep_blocks_per_cu(int words, int *blocks) {
+    const void *fn = batch_sweep_kernel(words);
+    if (!fn) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
+}
+
+hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, int32_t n_tiles, int words,
+                              int grid, hipStream_t stream) {
+    const void *fn = batch_sweep_kernel(words);
+    if (!fn) return hipErrorInvalidValue;
+    if (n_tiles == 0) return hipSuccess;
+    void *args[] = {(void *)&members, (void *)&tiles, (void *)&n_tiles};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+}
+
+hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, int32_t n_members,
+                               hipStream_t stream) {
+    if (n_members > 0)
+        hipLaunchKernelGGL(k_batch_finish<false>, dim3(n_members), dim3(kBlock), 0, stream, members, member_ids);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_output(const BatchMember *members, const TileRef *tiles, int32_t n_tiles,
+                               const int32_t *member_ids, int32_t n_members, PrState *states_out,
+                               hipStream_t stream) {
+    if (n_tiles > 0)
+        hipLaunchKernelGGL(k_batch_output, dim3(std::min<int32_t>(n_tiles, 8192)), dim3(kBlock), 0, stream, members,
+                           tiles, n_tiles);
+    if (n_members > 0)
+        hipLaunchKernelGGL(k_batch_score, dim3(n_members), dim3(kBlock), 0, stream, members, member_ids, states_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_states(const BatchMember *members, const int32_t *member_ids, int32_t n_members,
+                               PrState *states_out, hipStream_t stream) {
+    if (n_members > 0)
+        hipLaunchKernelGGL(k_batch_states, dim3((n_members + 63) / 64), dim3(64), 0, stream, members, member_ids,
+                           n_members, states_out);
     return hipGetLastError();
 }
 

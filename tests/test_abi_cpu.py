@@ -47,9 +47,9 @@ def test_binding_prototypes_cover_the_header():
 
 def test_struct_layouts_match_header():
     from paper_2210_01465_amd import _abi
-    # fl_params: 3 doubles + 2 int32; fl_summary: 4 int64 + 4 int32 + 5 doubles
+    # fl_params: 3 doubles + 2 int32; fl_summary: 4 int64 + 6 int32 + 5 doubles
     assert ctypes.sizeof(_abi.fl_params) == 32
-    assert ctypes.sizeof(_abi.fl_summary) == 4 * 8 + 4 * 4 + 5 * 8
+    assert ctypes.sizeof(_abi.fl_summary) == 4 * 8 + 6 * 4 + 5 * 8
     assert ctypes.sizeof(_abi.fl_timing) == 4 * 8 + 2 * 4
 
 

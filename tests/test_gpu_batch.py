@@ -1,0 +1,163 @@
+"""GPU: batched and continuously batched analyses (fl_batch_*, fl_analyze_batch).
+
+A member's results must equal its plain slot-sweep run (fl_execute with
+FL_ROWS_SLOTS) bit for bit, whatever else shares the batch and whenever it
+joins; against the FP64 oracle the usual tolerances hold.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_01465_amd import synth
+
+pytestmark = pytest.mark.gpu
+ROWS_SLOTS = -1
+L1_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2210_01465_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def mixed_spaces():
+    spaces = [synth.tiny(s) for s in range(4)] + [synth.mid()]
+    spaces += [s for s in (synth.fuzz_space(j, max_params=6, max_radix=8) for j in range(12))
+               if s.n_valid > 0 and s.n_raw <= 200_000]
+    spaces += synth.batched()[0:36:9]
+    return spaces
+
+
+def plain(ctx, space, nb, d, p):
+    import torch
+    from paper_2210_01465_amd import api
+    fit = torch.from_numpy(space.fitness_raw).cuda()
+    plan = api.plan_create(ctx, space.radix, fit, nb)
+    pr, mins, info = api.execute(plan, d, p, row_mapping=ROWS_SLOTS)
+    out = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+    plan.close()
+    return out
+
+
+def test_batch_equals_plain(ctx):
+    import torch
+    from paper_2210_01465_amd import api
+    spaces = mixed_spaces()
+    dampings = [(0.8, 0.85, 0.9)[j % 3] for j in range(len(spaces))]
+    nbs = [("hamming", "adjacent")[j % 2] for j in range(len(spaces))]
+    say(f"batch of {len(spaces)} spaces")
+    batch = api.Batch(ctx)
+    fits, plans = [], []
+    for j, s in enumerate(spaces):
+        fits.append(torch.from_numpy(s.fitness_raw).cuda())
+        plans.append(api.plan_create(ctx, s.radix, fits[-1], nbs[j]))
+        batch.add(plans[-1], dampings[j], 0.05, tag=j)
+    done = {}
+    while True:
+        running = batch.step(8)
+        for tag, pr, mins, info in batch.collect():
+            done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+        if running == 0:
+            break
+    batch.close()
+    assert sorted(done) == list(range(len(spaces)))
+    for j, s in enumerate(spaces):
+        say(f"compare {s.name} {nbs[j]} d={dampings[j]}")
+        ref = plain(ctx, s, nbs[j], dampings[j], 0.05)
+        pr, mins, info = done[j]
+        assert info["status"] == 0
+        assert np.array_equal(pr, ref[0]), s.name
+        assert np.array_equal(mins, ref[1]), s.name
+        assert info["iterations"] == ref[2]["iterations"]
+        assert info["score"] == ref[2]["score"]
+    for pl in plans:
+        pl.close()
+
+
+def test_members_join_mid_run(ctx):
+    """Continuous batching: members added while others are running."""
+    import torch
+    from paper_2210_01465_amd import api
+    spaces = [synth.mid(), synth.tiny(0), synth.tiny(1)] + synth.batched()[9:45:9]
+    batch = api.Batch(ctx)
+    fits, plans, done = [], [], {}
+    pending = list(range(len(spaces)))
+    say("join mid-run")
+    steps = 0
+    while True:
+        if pending:
+            j = pending.pop(0)
+            fits.append(torch.from_numpy(spaces[j].fitness_raw).cuda())
+            plans.append(api.plan_create(ctx, spaces[j].radix, fits[-1], "hamming"))
+            batch.add(plans[-1], 0.85, 0.05, tag=j)
+        running = batch.step(3)
+        steps += 1
+        for tag, pr, mins, info in batch.collect():
+            done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+        if running == 0 and not pending:
+            break
+    batch.close()
+    assert steps > len(spaces) // 2
+    for j, s in enumerate(spaces):
+        ref = plain(ctx, s, "hamming", 0.85, 0.05)
+        assert np.array_equal(done[j][0], ref[0]), s.name
+        assert done[j][2]["score"] == ref[2]["score"]
+    for pl in plans:
+        pl.close()
+
+
+def test_analyze_batch_against_oracle(ctx):
+    import torch
+    from paper_2210_01465_amd import api
+    spaces = [synth.tiny(5), synth.mid(), synth.fuzz_space(3, max_params=5, max_radix=7)]
+    rng = np.random.default_rng(2)
+    wide = synth.Space("wide", (200,), (rng.permutation(200) + 1.0).astype(np.float32))   # not batchable
+    empty = synth.Space("empty", (4, 4), np.full(16, np.nan, np.float32))                 # invalid
+    spaces += [wide, empty]
+    nbs = ["hamming", "adjacent", "hamming", "hamming", "hamming"]
+    say("fl_analyze_batch")
+    res = api.analyze_batch([s.radix for s in spaces],
+                            [torch.from_numpy(s.fitness_raw).cuda() for s in spaces], nbs, 0.85, 0.05,
+                            ctx=ctx)
+    assert res[4].info["status"] == -1  # FL_EINVAL: no valid configuration
+    for j in range(4):
+        s = spaces[j]
+        o = oracle.analyze(s.radix, s.fitness_raw, oracle.HAMMING if nbs[j] == "hamming" else oracle.ADJACENT)
+        assert res[j].info["status"] == 0
+        assert np.array_equal(res[j].minima.cpu().numpy(), o.graph.minima)
+        assert float(np.abs(res[j].pagerank.cpu().numpy() - o.pagerank).sum()) <= L1_TOL
+        assert abs(res[j].score - o.score) <= 1e-5
+
+
+def test_batch_rejects_bad_members(ctx):
+    import torch
+    from paper_2210_01465_amd import api, _abi
+    batch = api.Batch(ctx)
+    rng = np.random.default_rng(3)
+    fit = torch.from_numpy((rng.permutation(200) + 1.0).astype(np.float32)).cuda()
+    plan = api.plan_create(ctx, (200,), fit)
+    with pytest.raises(api.FLError) as e:
+        batch.add(plan)
+    assert e.value.status == _abi.FL_EINVAL
+    s = synth.tiny(0)
+    plan2 = api.plan_create(ctx, s.radix, torch.from_numpy(s.fitness_raw).cuda())
+    for kw in ({"damping": 1.0}, {"p": -1.0}):
+        with pytest.raises(api.FLError):
+            batch.add(plan2, **kw)
+    batch.add(plan2)
+    with pytest.raises(api.FLError):
+        batch.add(plan2)  # already a member
+    assert batch.step(100) == 0
+    assert len(batch.collect()) == 1
+    batch.close()
+    plan.close()
+    plan2.close()

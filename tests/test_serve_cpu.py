@@ -1,0 +1,119 @@
+"""Serving scheduler on the CPU: a fake backend (built on the oracle) stands
+in for the GPU engine, with a virtual clock, so admission, the FFG cache and
+continuous batching are tested without a device."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_01465_amd import serve, synth
+
+
+class FakeBackend:
+    """Members finish after as many steps as their oracle iteration count
+    needs; every build/step advances a virtual clock."""
+
+    def __init__(self, sweeps_per_step=4, step_cost=1e-4, build_cost=2e-4):
+        self.now = 0.0
+        self.sweeps = sweeps_per_step
+        self.step_cost, self.build_cost = step_cost, build_cost
+        self.members = {}
+        self.live_plans = 0
+        self.added_while_running = 0
+
+    def clock(self):
+        return self.now
+
+    def sleep(self, dt):
+        self.now += dt
+
+    def build(self, req):
+        self.now += self.build_cost
+        self.live_plans += 1
+        g = oracle.build_graph(req.radix, req.fitness, {"hamming": 0, "adjacent": 1}[req.neighbourhood])
+        return g, True
+
+    def plan_bytes(self, g):
+        return 64 * g.n_raw
+
+    def add(self, g, req):
+        if self.members:
+            self.added_while_running += 1
+        r, it, _ = g.pagerank(req.damping, 2e-7)
+        sc = g.score(r, req.p)[0]
+        self.members[req.rid] = [it, r, g.minima, {"score": sc, "iterations": it, "status": 0}]
+
+    def step(self):
+        self.now += self.step_cost
+        for m in self.members.values():
+            m[0] -= self.sweeps
+        return sum(1 for m in self.members.values() if m[0] > 0)
+
+    def collect(self):
+        out = [(rid, m[1], m[2], m[3]) for rid, m in self.members.items() if m[0] <= 0]
+        for rid, *_ in out:
+            del self.members[rid]
+        return out
+
+    def plain(self, g, req):
+        r, it, _ = g.pagerank(req.damping, 2e-7)
+        self.now += self.step_cost * (it // self.sweeps + 1)
+        return r, g.minima, {"score": g.score(r, req.p)[0], "iterations": it, "status": 0}
+
+    def release(self, g):
+        self.live_plans -= 1
+
+
+def make_requests(n, seed=0, rate=2000.0):
+    spaces = [synth.tiny(s) for s in range(3)] + [synth.fuzz_space(j, max_params=4, max_radix=6) for j in range(5)]
+    spaces = [s for s in spaces if s.n_valid > 0]
+    rng = np.random.default_rng(seed)
+    times = serve.poisson_arrivals(rate, n / rate, seed=seed)
+    reqs = []
+    for rid, t in enumerate(times[:n]):
+        j = int(rng.integers(len(spaces)))
+        s = spaces[j]
+        reqs.append(serve.Request(t, rid, (j, "hamming"), s.radix, s.fitness_raw, "hamming",
+                                  float(rng.choice([0.8, 0.85, 0.9])), 0.05))
+    return reqs
+
+
+def test_every_request_matches_its_plain_result():
+    reqs = make_requests(60)
+    fb = FakeBackend()
+    srv = serve.Server(fb, hbm_budget=1 << 30, clock=fb.clock, sleep=fb.sleep)
+    done = {d.rid: d for d in srv.run(reqs)}
+    assert sorted(done) == [r.rid for r in reqs]
+    for r in reqs:
+        g = oracle.build_graph(r.radix, r.fitness)
+        rr, _, _ = g.pagerank(r.damping, 2e-7)
+        assert done[r.rid].score == g.score(rr, r.p)[0]
+        assert done[r.rid].latency >= 0
+    assert fb.added_while_running > 0          # members joined a running batch
+    assert srv.stats["cache_hits"] > 0         # repeated spaces reuse their FFG
+    assert srv.stats["built"] <= 8
+
+
+def test_admission_respects_the_budget():
+    reqs = make_requests(40, seed=3, rate=50000.0)
+    fb = FakeBackend()
+    budget = 3 * 64 * 160 + (1 << 20) * 3       # room for about three tiny spaces
+    srv = serve.Server(fb, hbm_budget=budget, cache_budget=0, clock=fb.clock, sleep=fb.sleep)
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert srv.peak_bytes <= budget
+    assert fb.live_plans == 0                   # nothing cached (cache budget 0): all released
+
+
+def test_plain_path_and_summary():
+    reqs = make_requests(20, seed=4)
+    fb = FakeBackend()
+    done = serve.serve_plain(fb, reqs, clock=fb.clock, sleep=fb.sleep)
+    assert [d.rid for d in done] == sorted(r.rid for r in reqs)
+    summ = serve.latency_summary(done)
+    assert summ["n"] == len(reqs) and summ["p99_ms"] >= summ["p50_ms"] >= 0
+
+
+def test_poisson_arrivals_are_seeded():
+    a = serve.poisson_arrivals(1000.0, 0.5, seed=5)
+    b = serve.poisson_arrivals(1000.0, 0.5, seed=5)
+    assert a == b and 400 < len(a) < 600 and all(x < y for x, y in zip(a, a[1:]))
