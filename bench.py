@@ -103,6 +103,43 @@ def batched_leg(ctx, damping, p, tol, repeats: int = 3):
             "all_ok": all(r.info["status"] == 0 for r in res)}
 
 
+def serving_leg(ctx, large_space, large_fit, seconds: float, rate: float = 1000.0, warm: float = 0.5):
+    """Poisson stream (rate per second, seed 5) of analyses: 98 % drawn
+    uniformly from the 234 batched spaces, 2 % the large space; damping
+    uniform on {0.8, 0.85, 0.9}, p = 0.05.  Served with continuous batching,
+    then replayed one at a time in arrival order (FIFO); latency from arrival
+    to a host-visible result."""
+    import numpy as np
+    import torch
+    from paper_2210_01465_amd import serve, synth
+    spaces = synth.batched()
+    fits = [torch.from_numpy(s.fitness_raw).cuda() for s in spaces]
+    rng = np.random.default_rng(5)
+    times = serve.poisson_arrivals(rate, warm + seconds, seed=5)
+    reqs = []
+    for rid, t in enumerate(times):
+        d = float(rng.choice([0.8, 0.85, 0.9]))
+        if rng.random() < 0.02:
+            reqs.append(serve.Request(t, rid, ("large", "hamming"), large_space.radix, large_fit,
+                                      "hamming", d, 0.05))
+        else:
+            j = int(rng.integers(len(spaces)))
+            reqs.append(serve.Request(t, rid, (j, "hamming"), spaces[j].radix, fits[j], "hamming", d, 0.05))
+    free, _ = torch.cuda.mem_get_info()
+    backend = serve.GpuBackend(ctx)
+    srv = serve.Server(backend, hbm_budget=int(free * 0.5))
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    served = serve.latency_summary(done, since=warm)
+    plain = serve.latency_summary(serve.serve_plain(backend, reqs), since=warm)
+    backend.close()
+    for cached in list(srv.cache.values()):
+        cached[0].close()
+    return {"rate_per_s": rate, "seconds": seconds, "requests": len(reqs),
+            "served": served, "one_at_a_time": plain,
+            "cache_hits": int(srv.stats["cache_hits"]), "ffg_builds": int(srv.stats["built"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +152,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched leg (234 spaces in one fl_analyze_batch vs one at a time)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-seconds", type=float, default=2.0,
+                    help="measured length of the Poisson request stream (after 0.5 s warm-up)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times "
                          "(calibrates the HBM byte counters of a profiler)")
@@ -220,6 +260,10 @@ def main():
     if not args.no_batched:
         print("[bench] batched leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(ctx, damping, p, tol)
+
+    if not args.no_serving:
+        print("[bench] serving leg", file=sys.stderr, flush=True)
+        out["serving"] = serving_leg(ctx, space, fit, args.serving_seconds)
 
     ref = None
     if not args.no_cpu_baseline:

@@ -165,6 +165,19 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *plan, const fl_params *params,
 fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *plan, int32_t *d_valid_raw,
                          int32_t *d_row_ptr, int32_t *d_col_idx, int32_t *d_out_deg);
 
+/* Autotuner: time every sweep layout the plan allows (the slot sweep and the
+ * CSR sweep with 1, 2, 4, 8, 16, 32, 64 lanes per row) for `sweeps` forced
+ * power-iteration sweeps each (HIP events, after one warm-up sweep), store
+ * the fastest in the context's tuning cache under the plan's shape class
+ * (node-record width, neighbourhood, log2 N, mean in-degree) and return it
+ * in *best.  us_per_sweep (may be NULL) receives 8 times in microseconds in
+ * that layout order, -1 where a layout does not apply.  Afterwards
+ * fl_execute with row_mapping 0 uses the cached layout for plans of the
+ * same shape class.  The plan's iterate buffers are overwritten; outputs of
+ * earlier fl_execute calls are not touched.  Synchronises the stream. */
+fl_status fl_tune(fl_ctx *ctx, fl_plan *plan, const fl_params *params, int32_t sweeps, int32_t *best,
+                  double *us_per_sweep);
+
 /* Phase timings of the plan's last build and execute (see fl_timing). */
 fl_status fl_plan_timing(fl_ctx *ctx, const fl_plan *plan, fl_timing *out);
 

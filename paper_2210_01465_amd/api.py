@@ -8,6 +8,7 @@ points without the ``fl_`` prefix:
     plan_create                        fl_plan_create   (build the FFG)
     execute                            fl_execute       (PageRank, minima, C_p)
     plan_export / plan_timing          fl_plan_export / fl_plan_timing
+    tune                               fl_tune          (autotune the sweep layout)
     plan_destroy                       fl_plan_destroy
     analyze                            fl_analyze       (one shot)
     Batch / batch_create               fl_batch_create / _add / _step / _collect / _timing / _destroy
@@ -209,6 +210,22 @@ def plan_export(plan: Plan) -> dict:
     _check(ctx, rc, "fl_plan_export")
     t["col_idx"] = t["col_idx"][:E]
     return t
+
+
+TUNE_LAYOUTS = (-1, 1, 2, 4, 8, 16, 32, 64)
+
+
+def tune(plan: Plan, damping: float = 0.85, sweeps: int = 4) -> dict:
+    """Autotune the sweep layout for the plan's shape class (fl_tune).
+    Returns {"best": layout, "us_per_sweep": {layout: us}} (-1 = slot sweep)."""
+    best = ctypes.c_int32()
+    times = (ctypes.c_double * 8)()
+    prm = _params(damping, 0.05, 0.0, 0, 0)
+    rc = _abi.load().fl_tune(plan.ctx.handle, plan.handle, ctypes.byref(prm), int(sweeps),
+                             ctypes.byref(best), times)
+    _check(plan.ctx, rc, "fl_tune")
+    return {"best": int(best.value),
+            "us_per_sweep": {lay: float(t) for lay, t in zip(TUNE_LAYOUTS, times) if t >= 0}}
 
 
 def plan_timing(plan: Plan) -> dict:

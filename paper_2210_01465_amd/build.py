@@ -42,5 +42,31 @@ def build(out: str = LIB, extra: tuple = (), verbose: bool = False) -> str:
     return out
 
 
+def kernel_resources(source: str = "fl_kernels.hip") -> dict:
+    """Per-kernel register and scratch use of one source, from the compiler's
+    resource report (device pass only; nothing is linked).
+    Returns {mangled name: {"vgprs": int, "sgprs": int, "scratch": int, "occupancy": int}}."""
+    import re
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "--cuda-device-only", "-c",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Rpass-analysis=kernel-resource-usage", "-I", INCLUDE, "-I", CSRC,
+               "-o", os.path.join(tmp, "k.o"), os.path.join(CSRC, source)]
+        text = subprocess.run(cmd, check=True, capture_output=True, text=True).stderr
+    out, cur = {}, None
+    keys = {"VGPRs": "vgprs", "TotalSGPRs": "sgprs", "ScratchSize [bytes/lane]": "scratch",
+            "Occupancy [waves/SIMD]": "occupancy"}
+    for line in text.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+([A-Za-z \[\]/]+): (\d+)", line)
+        if m and cur is not None and m.group(1).strip() in keys:
+            cur[keys[m.group(1).strip()]] = int(m.group(2))
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

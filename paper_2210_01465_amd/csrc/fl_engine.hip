@@ -94,6 +94,7 @@ struct fl_ctx {
     int num_cus = 256;
     std::string err;
     DevicePool pool;
+    std::map<uint64_t, int> tuned;  // shape class -> sweep layout chosen by fl_tune
     BuildSizes *h_sizes = nullptr;  // pinned
     PrState *h_state = nullptr;     // pinned
 };
@@ -482,6 +483,62 @@ void fill_summary(const fl_plan *p, const PrState &hs, int lanes, fl_status stat
     out->score = hs.score_den > 0.0 ? hs.score_num / hs.score_den : 0.0;
 }
 
+// Shape class of a plan for the tuning cache: record width, neighbourhood,
+// log2 N and the mean in-degree rounded to a half.
+uint64_t shape_key(const fl_plan *p) {
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= p->n) ++lg;
+    const int64_t deg2 = p->n > 0 ? (2 * p->e + p->n / 2) / p->n : 0;
+    return ((uint64_t)p->sl.words << 56) | ((uint64_t)p->adjacent << 52) | ((uint64_t)lg << 40) |
+           (uint64_t)std::min<int64_t>(deg2, (int64_t(1) << 40) - 1);
+}
+
+// Grid, buffers and arguments of the power iteration of plan p in layout
+// `lanes` (FL_ROWS_SLOTS or CSR lanes per row).
+fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrArgs &a, int &grid,
+                     int &init_grid) {
+    const int kind = lanes == FL_ROWS_SLOTS ? fl::kSweepSlots : fl::kSweepCsr;
+    a = PrArgs{};
+    a.kind = kind;
+    a.adjacent = p->adjacent;
+    a.x_bytes = kind == fl::kSweepSlots ? x_bytes_of(p) : 0;
+    // persistent grid: every workgroup resident at once (occupancy query), a
+    // multiple of the XCD count so each XCD gets the same number of them
+    int per_cu = 0;
+    FL_HIP(fl::pr_iter_blocks_per_cu(a, p->sp, p->sl, lanes, &per_cu));
+    const int64_t resident =
+        std::max<int64_t>(fl::kXcds, (int64_t)std::max(per_cu, 1) * ctx->num_cus / fl::kXcds * fl::kXcds);
+    const int64_t rows_per_wg = kind == fl::kSweepSlots ? fl::kBlock : fl::kBlock / lanes;
+    const int64_t groups = (p->n + rows_per_wg - 1) / rows_per_wg;
+    grid = (int)std::min<int64_t>(resident, (groups + fl::kXcds - 1) / fl::kXcds * fl::kXcds);
+    fl_status st = ensure_pr_buffers(ctx, p, kind == fl::kSweepSlots);
+    if (st != FL_OK) return st;
+    // partial sums: one triple per tile (init, slot sweep) or per workgroup (CSR sweep)
+    const int32_t n_tiles = tiles_of(p);
+    init_grid = (int)std::min<int64_t>(n_tiles, (int64_t)ctx->num_cus * 4);
+    st = ensure_partials(ctx, p, std::max(grid, n_tiles));
+    if (st != FL_OK) return st;
+    a.row_ptr = p->row_ptr;
+    a.col_idx = p->col_idx;
+    a.out_deg = p->out_deg;
+    a.valid_raw = p->valid_raw;
+    a.rec = p->rec;
+    a.presence = p->presence;
+    a.off = p->d_off;
+    a.k_slots = p->sl.k;
+    a.y[0] = p->y[0];
+    a.y[1] = p->y[1];
+    a.x[0] = p->x[0];
+    a.x[1] = p->x[1];
+    a.partials = p->partials;
+    a.st = p->state;
+    a.n = (int32_t)p->n;
+    a.d = r.d;
+    a.tol = r.tol;
+    a.max_iter = r.max_iter;
+    return FL_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -663,49 +720,17 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     Resolved r;
     fl_status st = resolve_params(ctx, p, prm, r);
     if (st != FL_OK) return st;
-    const int lanes = r.lanes;
-    const int kind = lanes == FL_ROWS_SLOTS ? fl::kSweepSlots : fl::kSweepCsr;
+    int lanes = r.lanes;
+    if (prm->row_mapping == 0) {
+        const auto hit = ctx->tuned.find(shape_key(p));
+        if (hit != ctx->tuned.end()) lanes = hit->second;
+    }
     FL_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-
-    PrArgs a{};
-    a.kind = kind;
-    a.adjacent = p->adjacent;
-    a.x_bytes = kind == fl::kSweepSlots ? x_bytes_of(p) : 0;
-    // persistent grid: every workgroup resident at once (occupancy query), a
-    // multiple of the XCD count so each XCD gets the same number of them
-    int per_cu = 0;
-    FL_HIP(fl::pr_iter_blocks_per_cu(a, p->sp, p->sl, lanes, &per_cu));
-    const int64_t resident =
-        std::max<int64_t>(fl::kXcds, (int64_t)std::max(per_cu, 1) * ctx->num_cus / fl::kXcds * fl::kXcds);
-    const int64_t rows_per_wg = kind == fl::kSweepSlots ? fl::kBlock : fl::kBlock / lanes;
-    const int64_t groups = (p->n + rows_per_wg - 1) / rows_per_wg;
-    const int grid = (int)std::min<int64_t>(resident, (groups + fl::kXcds - 1) / fl::kXcds * fl::kXcds);
-    st = ensure_pr_buffers(ctx, p, kind == fl::kSweepSlots);
+    PrArgs a;
+    int grid = 0, init_grid = 0;
+    st = prepare_pr(ctx, p, r, lanes, a, grid, init_grid);
     if (st != FL_OK) return st;
-    // partial sums: one triple per tile (init, slot sweep) or per workgroup (CSR sweep)
-    const int32_t n_tiles = tiles_of(p);
-    const int init_grid = (int)std::min<int64_t>(n_tiles, (int64_t)ctx->num_cus * 4);
-    st = ensure_partials(ctx, p, std::max(grid, n_tiles));
-    if (st != FL_OK) return st;
-    a.row_ptr = p->row_ptr;
-    a.col_idx = p->col_idx;
-    a.out_deg = p->out_deg;
-    a.valid_raw = p->valid_raw;
-    a.rec = p->rec;
-    a.presence = p->presence;
-    a.off = p->d_off;
-    a.k_slots = p->sl.k;
-    a.y[0] = p->y[0];
-    a.y[1] = p->y[1];
-    a.x[0] = p->x[0];
-    a.x[1] = p->x[1];
-    a.partials = p->partials;
-    a.st = p->state;
-    a.n = (int32_t)p->n;
-    a.d = r.d;
-    a.tol = r.tol;
-    a.max_iter = r.max_iter;
 
     FL_HIP(hipEventRecord(p->ev[2], s));
     FL_HIP(hipMemsetAsync(p->state, 0, sizeof(PrState), s));
@@ -809,6 +834,48 @@ fl_status fl_analyze(fl_ctx *ctx, const fl_space *space, const float *d_fitness_
     fl_plan_destroy(ctx, p);
     ctx->err = msg;
     return st;
+}
+
+fl_status fl_tune(fl_ctx *ctx, fl_plan *p, const fl_params *prm, int32_t sweeps, int32_t *best,
+                  double *us_per_sweep) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!p || !prm || !best || p->ctx != ctx) return fail(ctx, FL_EINVAL, "bad argument");
+    if (sweeps < 1 || sweeps > 1000) return fail(ctx, FL_EINVAL, "sweeps must be in [1, 1000]");
+    Resolved r;
+    fl_status st = resolve_params(ctx, p, prm, r);
+    if (st != FL_OK) return st;
+    r.tol = 0.0;                // every timed sweep does work
+    r.max_iter = sweeps + 1;
+    FL_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int layouts[8] = {FL_ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64};
+    double best_us = 0.0;
+    *best = 0;
+    for (int j = 0; j < 8; ++j) {
+        if (us_per_sweep) us_per_sweep[j] = -1.0;
+        const int lanes = layouts[j];
+        if (lanes == FL_ROWS_SLOTS && p->sl.words == 0) continue;
+        PrArgs a;
+        int grid = 0, init_grid = 0;
+        st = prepare_pr(ctx, p, r, lanes, a, grid, init_grid);
+        if (st != FL_OK) return st;
+        FL_HIP(hipMemsetAsync(p->state, 0, sizeof(PrState), s));
+        FL_HIP(fl::launch_pr_init(a, init_grid, s));
+        FL_HIP(fl::launch_pr_iter(a, p->sp, p->sl, lanes, grid, s));  // warm-up sweep
+        FL_HIP(hipEventRecord(p->ev[5], s));
+        for (int32_t q = 0; q < sweeps; ++q) FL_HIP(fl::launch_pr_iter(a, p->sp, p->sl, lanes, grid, s));
+        FL_HIP(hipEventRecord(p->ev[6], s));
+        FL_HIP(hipStreamSynchronize(s));
+        const double us = 1e3 * elapsed(p->ev[5], p->ev[6]) / sweeps;
+        if (us_per_sweep) us_per_sweep[j] = us;
+        if (*best == 0 || us < best_us) {
+            best_us = us;
+            *best = lanes;
+        }
+    }
+    ctx->tuned[shape_key(p)] = *best;
+    return FL_OK;
 }
 
 // ---- batches ----

@@ -747,14 +747,17 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
     write_partials(a.partials, blockIdx.x, ps, pr, pk);
 }
 
-// Slot sweep: one node per lane, 64 consecutive nodes per wave.  For every
-// candidate slot whose in-edge bit is set, gather x at raw index i + off[s]
-// (x lives in raw-index space, so neither col_idx nor an index remap is read).
-// A slot no lane of the wave needs is skipped with a scalar branch; the other
-// lanes' loads of that slot get an out-of-range buffer offset and return 0,
-// so the 32 loads of a batch issue back to back with no per-lane branching.
-// Slots run in ascending raw-index order, the order of the CSR rows, so the
-// FP32 sum equals the one-lane-per-row CSR sweep's bit for bit.
+// Pointer into the constant address space: memory no kernel of the launch
+// writes.  Uniform loads through it may go through the scalar unit even after
+// the kernel has stored elsewhere, which keeps the slot offsets and presence
+// words in SGPRs instead of a VGPR per value.
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ const_ptr<T> to_const(const T *p) {
+    return (const_ptr<T>)p;
+}
+
 // Slot sweep of one tile of kBlock nodes: one node per lane, 64 consecutive
 // nodes per wave.  For every candidate slot whose in-edge bit is set, gather
 // x at raw index i + off[s] (x lives in raw-index space, so neither col_idx
@@ -766,8 +769,9 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
 // equals the one-lane-per-row CSR sweep's bit for bit.  The plain and the
 // batched sweep both run this routine, so their results agree bit for bit.
 struct SweepTile {
-    const uint64_t *rec, *presence;
-    const int32_t *off;  // slot offsets, device memory (read through the scalar unit)
+    const uint64_t *rec;
+    const_ptr<uint64_t> presence;  // per wave of 64 nodes
+    const_ptr<int32_t> off;        // slot offsets
     const float *y_in, *x_in;
     float *y_out, *x_out;
     double *partials;
@@ -795,7 +799,7 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
     // this wave's slot presence, loaded through the scalar unit; a wave past
     // the last node (in the last tile) has no entry and skips
     const int32_t first = __builtin_amdgcn_readfirstlane(tile * kBlock + (int32_t)(threadIdx.x & ~63u));
-    const uint64_t *pw = q.presence + (int64_t)(first >> 6) * W;
+    const_ptr<uint64_t> pw = q.presence + (int64_t)(first >> 6) * W;
     const bool live = first < q.n;
     float acc = 0.0f;
 #pragma unroll
@@ -803,7 +807,10 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
         if (32 * b >= q.k_slots || !live) break;
         const uint64_t pq = pw[b >> 1];
         const uint32_t any = (b & 1) ? (uint32_t)(pq >> 32) : (uint32_t)pq;
-        if (any == 0u) continue;
+        // (no early exit for any == 0 here: a branch around the whole batch
+        // makes the compiler duplicate the unrolled batches into separate
+        // paths and spill them to scratch; the per-slot tests below skip an
+        // empty batch's loads just as well)
         const uint32_t bits = r.word32(b) & batch_mask(b, q.k_slots);
         const uint32_t nbits = ~bits;
         float val[32];
@@ -843,8 +850,8 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     const int32_t k = st->k;
     SweepTile q;
     q.rec = a.rec;
-    q.presence = a.presence;
-    q.off = a.off;
+    q.presence = to_const(a.presence);
+    q.off = to_const(a.off);
     q.y_in = a.y[k & 1];
     q.x_in = a.x[k & 1];
     q.y_out = a.y[(k + 1) & 1];
@@ -871,28 +878,29 @@ template <int W, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchMember *__restrict__ members,
                                                         const TileRef *__restrict__ tiles, int32_t n_tiles) {
     const TileWalk w(n_tiles);
+    const_ptr<TileRef> tl = to_const(tiles);
     for (int32_t t = w.first; t < w.end; t += w.step) {
-        const TileRef tr = tiles[t];
-        const BatchMember &m = members[tr.member];
-        const PrState *st = m.st;
+        const int32_t member = tl[t].member, tile = tl[t].tile;
+        const_ptr<BatchMember> m = to_const(members) + member;
+        const_ptr<PrState> st = to_const(m->st);
         if (st->done) continue;
         const int32_t k = st->k;
         SweepTile q;
-        q.rec = m.rec;
-        q.presence = m.presence;
-        q.off = m.off;
-        q.y_in = m.y[k & 1];
-        q.x_in = m.x[k & 1];
-        q.y_out = m.y[(k + 1) & 1];
-        q.x_out = m.x[(k + 1) & 1];
-        q.partials = m.partials;
+        q.rec = m->rec;
+        q.presence = to_const(m->presence);
+        q.off = to_const(m->off);
+        q.y_in = m->y[k & 1];
+        q.x_in = m->x[k & 1];
+        q.y_out = m->y[(k + 1) & 1];
+        q.x_out = m->x[(k + 1) & 1];
+        q.partials = m->partials;
         q.s = st->s;
         q.c = st->c;
-        q.sd = q.s * m.d;
-        q.n = m.n;
-        q.k_slots = m.k_slots;
-        q.x_bytes = m.x_bytes;
-        sweep_tile<W, BUF>(q, tr.tile);
+        q.sd = q.s * m->d;
+        q.n = m->n;
+        q.k_slots = m->k_slots;
+        q.x_bytes = m->x_bytes;
+        sweep_tile<W, BUF>(q, tile);
     }
 }
 

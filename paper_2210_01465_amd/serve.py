@@ -153,6 +153,8 @@ class Server:
         cache budget is cached and shared; any other is owned by its request
         and released when the request finishes."""
         hit = self.cache.get(req.key)
+        if hit is not None and self.in_use.get(req.key, 0) > 0:
+            return False          # its FFG is running for another request: wait for it
         if hit is None:
             need = footprint_estimate(req.radix)
             self._evict(need)
@@ -173,8 +175,8 @@ class Server:
             plan, nbytes, batchable = hit
             shared = True
         self.peak_bytes = max(self.peak_bytes, self._held())
-        if (shared and self.in_use.get(req.key, 0) > 0) or not batchable:
-            # the shared plan is already a member (or cannot be batched): run it alone
+        if not batchable:
+            # a space the batched sweep cannot take runs alone
             pr, mins, info = self.backend.plain(plan, req)
             self._finish(req, pr, mins, info)
             if not shared:
