@@ -202,8 +202,11 @@ fl_status fl_analyze(fl_ctx *ctx, const fl_space *space, const float *d_fitness_
  * stop flag, and its results equal those of fl_execute with the slot sweep
  * (row_mapping FL_ROWS_SLOTS) bit for bit, whatever else runs in the batch.
  * Members join (fl_batch_add) and leave (fl_batch_collect) between steps.
- * A plan must stay alive while it is a member and may belong to one batch
- * at a time. */
+ * A member reads its plan's FFG and keeps its own iterate vectors (taken
+ * from the context's device cache at fl_batch_add, returned when it leaves),
+ * so one plan may be a member several times at once (say with different
+ * damping or p), in one or several batches; it must stay alive while it is
+ * a member.  fl_execute on a plan does not disturb its batch members. */
 typedef struct fl_batch fl_batch;
 
 fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out);
@@ -214,6 +217,8 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *batch);
 /* Add a plan as a member; it starts at the next fl_batch_step.  The outputs
  * (d_pagerank double[N], d_minima int32[M]) are caller-owned device buffers
  * written when the member finishes; `tag` is returned by fl_batch_collect.
+ * The member holds 8 n_raw + 8 N + 24 ceil(N/256) + 80 bytes of device
+ * memory of its own while it is in the batch.
  * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0 or
  * FL_ROWS_SLOTS, or a space the slot sweep cannot take: use fl_execute),
  * FL_ENOMEM, FL_EHIP. */

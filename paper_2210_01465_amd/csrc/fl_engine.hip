@@ -555,6 +555,11 @@ struct fl_batch {
         int slot = -1;    // row of the device member table
         int phase = 0;    // 0 waiting for initialisation, 1 running, 2 finished
         fl_summary sum{};
+        // the member's own iterate: y (node ids), x (raw indices), per-tile
+        // partial sums and state, from the context's pool
+        float *y[2] = {}, *x[2] = {};
+        double *partials = nullptr;
+        PrState *state = nullptr;
     };
     fl_ctx *ctx = nullptr;
     std::vector<Member> members;
@@ -572,6 +577,32 @@ struct fl_batch {
 };
 
 namespace {
+
+void member_release(fl_ctx *ctx, fl_batch::Member &m) {
+    for (int j = 0; j < 2; ++j) {
+        ctx->pool.release(m.y[j]);
+        ctx->pool.release(m.x[j]);
+        m.y[j] = m.x[j] = nullptr;
+    }
+    ctx->pool.release(m.partials);
+    ctx->pool.release(m.state);
+    m.partials = nullptr;
+    m.state = nullptr;
+}
+
+fl_status member_alloc(fl_ctx *ctx, const fl_plan *p, fl_batch::Member &m) {
+    for (int j = 0; j < 2; ++j) {
+        m.y[j] = pool_alloc<float>(ctx, p->n);
+        m.x[j] = pool_alloc<float>(ctx, p->n_raw);
+    }
+    m.partials = pool_alloc<double>(ctx, 3 * (int64_t)tiles_of(p));
+    m.state = pool_alloc<PrState>(ctx, 1);
+    if (!m.y[0] || !m.y[1] || !m.x[0] || !m.x[1] || !m.partials || !m.state) {
+        member_release(ctx, m);
+        return fail(ctx, FL_ENOMEM, "device allocation failed");
+    }
+    return FL_OK;
+}
 
 void batch_free_tables(fl_batch *b) {
     fl_ctx *ctx = b->ctx;
@@ -918,6 +949,7 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *b) {
     if (b->ctx != ctx) return fail(ctx, FL_EINVAL, "batch belongs to another context");
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto &m : b->members) member_release(ctx, m);
     batch_free_tables(b);
     for (auto &e : b->ev) (void)hipEventDestroy(e);
     delete b;
@@ -930,8 +962,6 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     ctx->err.clear();
     if (!b || !p || !prm || !d_pagerank || (!d_minima && p->m > 0)) return fail(ctx, FL_EINVAL, "null argument");
     if (b->ctx != ctx || p->ctx != ctx) return fail(ctx, FL_EINVAL, "batch or plan belongs to another context");
-    for (const auto &m : b->members)
-        if (m.plan == p) return fail(ctx, FL_EINVAL, "plan is already a member of this batch");
     if (p->sl.words == 0 || x_bytes_of(p) == 0)
         return fail(ctx, FL_EINVAL, "space has %d candidate slots or 2^29+ configurations: use fl_execute",
                     p->sl.k);
@@ -940,15 +970,13 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     if (st != FL_OK) return st;
     if (r.lanes != FL_ROWS_SLOTS) return fail(ctx, FL_EINVAL, "batches run the slot sweep only");
     FL_HIP(hipSetDevice(ctx->device));
-    st = ensure_pr_buffers(ctx, p, true);
-    if (st != FL_OK) return st;
-    st = ensure_partials(ctx, p, tiles_of(p));
-    if (st != FL_OK) return st;
     int64_t tiles = 0;
     for (const auto &m : b->members) tiles += tiles_of(m.plan);
     st = batch_reserve(b, (int)b->members.size() + 1, tiles + tiles_of(p));
     if (st != FL_OK) return st;
     fl_batch::Member m;
+    st = member_alloc(ctx, p, m);
+    if (st != FL_OK) return st;
     m.plan = p;
     m.prm = r;
     m.out_pr = d_pagerank;
@@ -965,12 +993,12 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     bm.out_deg = p->out_deg;
     bm.minima = p->minima;
     bm.fit_c = p->fit_c;
-    bm.y[0] = p->y[0];
-    bm.y[1] = p->y[1];
-    bm.x[0] = p->x[0];
-    bm.x[1] = p->x[1];
-    bm.partials = p->partials;
-    bm.st = p->state;
+    bm.y[0] = m.y[0];
+    bm.y[1] = m.y[1];
+    bm.x[0] = m.x[0];
+    bm.x[1] = m.x[1];
+    bm.partials = m.partials;
+    bm.st = m.state;
     bm.out_pagerank = d_pagerank;
     bm.out_minima = d_minima;
     bm.d = r.d;
@@ -1108,6 +1136,7 @@ fl_status fl_batch_collect(fl_ctx *ctx, fl_batch *b, int32_t max, int64_t *tags,
         tags[n] = m.tag;
         out[n] = m.sum;
         ++n;
+        member_release(ctx, m);   // the step that finished it synchronised the stream
         b->free_slots.push_back(m.slot);
         b->members.erase(b->members.begin() + (long)q);
     }

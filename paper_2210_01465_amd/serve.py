@@ -14,9 +14,10 @@ arrive over time.  The server
   long ones;
 * records, per request, the latency from arrival to a host-visible result.
 
-The GPU work goes through a backend object with four calls (``build``,
-``add``, ``step``, ``collect``) plus ``plain`` for the one-at-a-time
-reference path, so the scheduling logic can be exercised with any backend.
+The GPU work goes through a backend object (``build``, ``plan_bytes``,
+``member_bytes``, ``add``, ``step``, ``collect``, ``release``, plus ``plain``
+for the one-at-a-time reference path), so the scheduling logic can be
+exercised with any backend.
 """
 from __future__ import annotations
 
@@ -87,6 +88,11 @@ class GpuBackend:
         n, n_raw, e = int(s["n_valid"]), int(s["n_raw"]), int(s["n_edges"])
         return n_raw * 16 + n * (8 * max(int(s["mask_words"]), 1) + 28) + 4 * e
 
+    def member_bytes(self, plan) -> int:
+        s = plan.sizes
+        n, n_raw = int(s["n_valid"]), int(s["n_raw"])
+        return 8 * n_raw + 8 * n + 24 * ((n + 255) // 256) + 80
+
     def add(self, plan, req: Request) -> None:
         self.batch.add(plan, req.damping, req.p, tag=req.rid)
 
@@ -136,11 +142,11 @@ class Server:
     def _held(self) -> int:
         return self.cache_bytes + self.reserved
 
-    def _evict(self, need: int) -> None:
+    def _evict(self, need: int, keep=None) -> None:
         for key in list(self.cache):
             if self._held() + need <= self.hbm_budget:
                 return
-            if self.in_use.get(key, 0) > 0:
+            if key == keep or self.in_use.get(key, 0) > 0:
                 continue
             plan, nbytes, _ = self.cache.pop(key)
             self.cache_bytes -= nbytes
@@ -150,16 +156,18 @@ class Server:
     def _admit(self, req: Request) -> bool:
         """Build or reuse the request's plan and add it to the batch, if the
         budget allows; False leaves the request queued.  A plan that fits the
-        cache budget is cached and shared; any other is owned by its request
-        and released when the request finishes."""
+        cache budget is cached and shared (members running on one FFG keep
+        their own iterate vectors); any other is owned by its request and
+        released when the request finishes."""
         hit = self.cache.get(req.key)
-        if hit is not None and self.in_use.get(req.key, 0) > 0:
-            return False          # its FFG is running for another request: wait for it
+        n_raw = 1
+        for r in req.radix:
+            n_raw *= int(r)
+        need = 16 * n_raw + (footprint_estimate(req.radix) if hit is None else 0)
+        self._evict(need, keep=req.key)
+        if self._held() + need > self.hbm_budget and (self.running or self._held() > 0):
+            return False
         if hit is None:
-            need = footprint_estimate(req.radix)
-            self._evict(need)
-            if self._held() + need > self.hbm_budget and (self.running or self._held() > 0):
-                return False
             plan, batchable = self.backend.build(req)
             nbytes = self.backend.plan_bytes(plan)
             self.stats["built"] += 1
@@ -182,10 +190,13 @@ class Server:
             if not shared:
                 self._release(plan, nbytes)
             return True
+        mbytes = self.backend.member_bytes(plan)
+        self.reserved += mbytes
+        self.peak_bytes = max(self.peak_bytes, self._held())
         self.backend.add(plan, req)
         if shared:
             self.in_use[req.key] = self.in_use.get(req.key, 0) + 1
-        self.running[req.rid] = (req, req.key, plan, nbytes, shared)
+        self.running[req.rid] = (req, req.key, plan, nbytes, shared, mbytes)
         return True
 
     def _release(self, plan, nbytes) -> None:
@@ -214,7 +225,8 @@ class Server:
             if self.running:
                 self.backend.step()
                 for tag, pr, mins, info in self.backend.collect():
-                    req, key, plan, nbytes, shared = self.running.pop(tag)
+                    req, key, plan, nbytes, shared, mbytes = self.running.pop(tag)
+                    self.reserved -= mbytes
                     self._finish(req, pr, mins, info)
                     if shared:
                         self.in_use[key] -= 1

@@ -154,10 +154,47 @@ def test_batch_rejects_bad_members(ctx):
         with pytest.raises(api.FLError):
             batch.add(plan2, **kw)
     batch.add(plan2)
-    with pytest.raises(api.FLError):
-        batch.add(plan2)  # already a member
     assert batch.step(100) == 0
     assert len(batch.collect()) == 1
     batch.close()
     plan.close()
     plan2.close()
+
+
+def test_one_plan_many_members(ctx):
+    """Members on one FFG keep their own iterates: the same plan runs with
+    three dampings at once, in two batches, while fl_execute also runs on it;
+    each result equals its plain run bit for bit."""
+    import torch
+    from paper_2210_01465_amd import api
+    s = synth.mid()
+    say("one plan, members with d = 0.8, 0.85, 0.9 in two batches")
+    fit = torch.from_numpy(s.fitness_raw).cuda()
+    plan = api.plan_create(ctx, s.radix, fit, "hamming")
+    b1, b2 = api.Batch(ctx), api.Batch(ctx)
+    b1.add(plan, 0.8, 0.05, tag=0)
+    b1.add(plan, 0.85, 0.05, tag=1)
+    b2.add(plan, 0.9, 0.05, tag=2)
+    done = {}
+    b1.step(5)
+    b2.step(5)
+    mid_pr, _, mid_info = api.execute(plan, 0.85, 0.1, row_mapping=ROWS_SLOTS)  # between steps
+    mid_pr = mid_pr.cpu().numpy()
+    for _ in range(200):
+        r1, r2 = b1.step(8), b2.step(8)
+        for b in (b1, b2):
+            for tag, pr, mins, info in b.collect():
+                done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+        if r1 == 0 and r2 == 0:
+            break
+    b1.close()
+    b2.close()
+    plan.close()
+    assert sorted(done) == [0, 1, 2]
+    for tag, d in enumerate((0.8, 0.85, 0.9)):
+        ref = plain(ctx, s, "hamming", d, 0.05)
+        assert np.array_equal(done[tag][0], ref[0]), d
+        assert np.array_equal(done[tag][1], ref[1])
+        assert done[tag][2]["iterations"] == ref[2]["iterations"]
+    assert np.array_equal(mid_pr, done[1][0])          # same d: same ranks
+    assert mid_info["iterations"] == done[1][2]["iterations"]

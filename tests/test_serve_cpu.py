@@ -17,8 +17,10 @@ class FakeBackend:
         self.sweeps = sweeps_per_step
         self.step_cost, self.build_cost = step_cost, build_cost
         self.members = {}
+        self.built = []
         self.live_plans = 0
         self.added_while_running = 0
+        self.max_on_one_plan = 0                  # members sharing one FFG at once
 
     def clock(self):
         return self.now
@@ -30,17 +32,23 @@ class FakeBackend:
         self.now += self.build_cost
         self.live_plans += 1
         g = oracle.build_graph(req.radix, req.fitness, {"hamming": 0, "adjacent": 1}[req.neighbourhood])
+        self.built.append(g)
         return g, True
 
     def plan_bytes(self, g):
         return 64 * g.n_raw
+
+    def member_bytes(self, g):
+        return 16 * g.n_raw
 
     def add(self, g, req):
         if self.members:
             self.added_while_running += 1
         r, it, _ = g.pagerank(req.damping, 2e-7)
         sc = g.score(r, req.p)[0]
-        self.members[req.rid] = [it, r, g.minima, {"score": sc, "iterations": it, "status": 0}]
+        self.members[req.rid] = [it, r, g.minima, {"score": sc, "iterations": it, "status": 0}, g]
+        self.max_on_one_plan = max(self.max_on_one_plan,
+                                   sum(1 for m in self.members.values() if m[4] is g))
 
     def step(self):
         self.now += self.step_cost
@@ -50,6 +58,7 @@ class FakeBackend:
 
     def collect(self):
         out = [(rid, m[1], m[2], m[3]) for rid, m in self.members.items() if m[0] <= 0]
+        assert all(any(m[4] is b for b in self.built) for m in self.members.values())   # no member outlives its plan
         for rid, *_ in out:
             del self.members[rid]
         return out
@@ -61,6 +70,7 @@ class FakeBackend:
 
     def release(self, g):
         self.live_plans -= 1
+        self.built = [b for b in self.built if b is not g]
 
 
 def make_requests(n, seed=0, rate=2000.0):
@@ -91,12 +101,13 @@ def test_every_request_matches_its_plain_result():
     assert fb.added_while_running > 0          # members joined a running batch
     assert srv.stats["cache_hits"] > 0         # repeated spaces reuse their FFG
     assert srv.stats["built"] <= 8
+    assert fb.max_on_one_plan >= 2             # one cached FFG ran for several requests at once
 
 
 def test_admission_respects_the_budget():
     reqs = make_requests(40, seed=3, rate=50000.0)
     fb = FakeBackend()
-    budget = 3 * 64 * 160 + (1 << 20) * 3       # room for about three tiny spaces
+    budget = 3 * (64 + 16) * 160 + (1 << 20) * 3   # room for about three tiny spaces
     srv = serve.Server(fb, hbm_budget=budget, cache_budget=0, clock=fb.clock, sleep=fb.sleep)
     done = srv.run(reqs)
     assert len(done) == len(reqs)
