@@ -9,11 +9,15 @@ vector is resident in HBM before the timed region.
 
 value = FFG+PageRank edges traversed per second over the timed steps,
         sum(E * iterations) / wall time, in GTEPS.
-roofline = the PageRank iteration kernel: its algorithmic bytes per launch
-        ((20 + 8 W) N + 4 E for the slot sweep with W mask words per node,
-        20 N + 8 E for the CSR sweep) over its mean launch duration (HIP
-        events on the engine's stream, summed over the timed steps), against
-        8 TB/s HBM.
+roofline = the PageRank sweep kernel: its algorithmic bytes per launch
+        ((20 + 8 W) N + 4 E for the slot sweep with W record words per node,
+        20 N + 8 E for the CSR sweep) over its mean duration, from a pair of
+        HIP events around every sweep launch on the engine's stream during
+        the timed steps (launches after convergence, which exit at once, are
+        not counted), against 8 TB/s HBM.  traffic = HBM bytes per launch
+        from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by the same
+        counters on a plain copy (see --traffic-from), or null when the
+        kernel source changed since they were taken.
 cpu_baseline = the FP64 oracle on the same space at the same tolerance,
         single-threaded on the host.
 """
@@ -40,17 +44,60 @@ def kernel_digest() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the iteration kernel from the committed PMC
-    runs, or None when absent or taken on a different kernel source."""
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the sweep kernel from the committed PMC runs,
+    or None when absent, taken on another kernel, or on a different kernel
+    source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_digest") != kernel_digest():
+    if rec.get("kernel_digest") != kernel_digest() or rec.get("kernel") != kernel:
         return None
     return rec.get("bytes_per_launch")
+
+
+def _pmc_per_launch(csv_dir: str, counter: str, kernel_part: str):
+    """Mean counter value over the dispatches of kernels whose name contains
+    kernel_part and whose value is at least a tenth of the largest (this
+    drops the launches that exit at once after convergence)."""
+    import csv
+    import glob
+    vals = []
+    for f in glob.glob(os.path.join(csv_dir, "*counter_collection.csv")):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and kernel_part in r["Kernel_Name"]:
+                    vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {kernel_part} under {csv_dir}")
+    top = max(vals)
+    work = [v for v in vals if v >= 0.1 * top]
+    return sum(work) / len(work), len(work)
+
+
+def write_traffic(root: str, kernel_part: str, copy_bytes: int, command: str) -> dict:
+    """HBM bytes per launch of the sweep kernel from four rocprofv3 --pmc runs
+    under root: pmc_FETCH_SIZE and pmc_WRITE_SIZE (bench.py), and
+    pmc_FETCH_SIZE_copy / pmc_WRITE_SIZE_copy (bench.py --copy-probe
+    copy_bytes).  Each counter is scaled by copy_bytes over what it reads for
+    the copy, which moves copy_bytes each way."""
+    fetch, n = _pmc_per_launch(os.path.join(root, "pmc_FETCH_SIZE"), "FETCH_SIZE", kernel_part)
+    write, _ = _pmc_per_launch(os.path.join(root, "pmc_WRITE_SIZE"), "WRITE_SIZE", kernel_part)
+    cf, _ = _pmc_per_launch(os.path.join(root, "pmc_FETCH_SIZE_copy"), "FETCH_SIZE", "copyBuffer")
+    cw, _ = _pmc_per_launch(os.path.join(root, "pmc_WRITE_SIZE_copy"), "WRITE_SIZE", "copyBuffer")
+    f_fac, w_fac = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    rec = {"kernel": kernel_part, "kernel_digest": kernel_digest(), "launches": n,
+           "fetch_kib_per_launch": round(fetch, 1), "write_kib_per_launch": round(write, 1),
+           "copy_bytes": copy_bytes, "copy_fetch_kib": round(cf, 1), "copy_write_kib": round(cw, 1),
+           "fetch_factor": round(f_fac, 4), "write_factor": round(w_fac, 4),
+           "bytes_per_launch": int(fetch * 1024 * f_fac + write * 1024 * w_fac),
+           "command": command}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    return rec
 
 
 def workload(name: str):
@@ -158,7 +205,20 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times "
                          "(calibrates the HBM byte counters of a profiler)")
+    ap.add_argument("--traffic-from", metavar="DIR",
+                    help="write the sweep kernel's HBM traffic record from the rocprofv3 --pmc "
+                         "runs under DIR (no GPU needed) and exit")
+    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true>")
+    ap.add_argument("--traffic-copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--traffic-command", default="")
+    ap.add_argument("--no-sweep-events", action="store_true",
+                    help="time the steps without per-sweep events (roofline then from chunk events)")
     args = ap.parse_args()
+
+    if args.traffic_from:
+        print(json.dumps(write_traffic(args.traffic_from, args.traffic_kernel,
+                                       args.traffic_copy_bytes, args.traffic_command)))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this engine has no multi-GPU path "
@@ -211,6 +271,8 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    if not args.no_sweep_events:
+        api.profile(ctx, True)
     torch.cuda.synchronize()
     infos, timings = [], []
     t0 = time.perf_counter()
@@ -220,15 +282,17 @@ def main():
         timings.append(t)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    api.profile(ctx, False)
     print(f"[bench] {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
 
     info = infos[-1]
     N, E, M = info["n_valid"], info["n_edges"], info["n_minima"]
     edges = sum(i["n_edges"] * i["iterations"] for i in infos)
     gteps = edges / wall / 1e9
-    launches = sum(t["launches"] for t in timings)
-    iter_ms = sum(t["iterate_ms"] for t in timings)
-    avg_launch_s = iter_ms / 1e3 / launches
+    if args.no_sweep_events:        # chunk time over launches: includes the step kernels
+        avg_launch_s = sum(t["iterate_ms"] for t in timings) / 1e3 / sum(t["launches"] for t in timings)
+    else:                           # sweep kernels that did work, each between its own events
+        avg_launch_s = sum(t["sweep_ms"] for t in timings) / 1e3 / sum(t["iterations"] for t in timings)
     if info["row_mapping"] == -1:   # slot sweep: valid_raw, masks, y in/out, out_deg, x out; x gathers
         bytes_per_launch = (20 + 8 * info["mask_words"]) * N + 4 * E
         kernel = f"k_pr_iter_slots<{info['mask_words']}, {'true' if 4 * n_raw < 2 ** 31 else 'false'}>"
@@ -236,7 +300,7 @@ def main():
         bytes_per_launch = 20 * N + 8 * E
         kernel = f"k_pr_iter_csr<{info['row_mapping']}>"
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(kernel)
     alg_bytes = (8 * n_raw + 36 * N + 4 * E) + info["iterations"] * bytes_per_launch + 12 * M
     step_s = wall / args.steps
 
@@ -262,9 +326,11 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kernel,
                      "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": round(avg_launch_s * 1e6, 3)},
+                     "avg_launch_us": round(avg_launch_s * 1e6, 3),
+                     "timing": "chunk events / launches" if args.no_sweep_events
+                               else "per-sweep HIP events, working launches"},
         "phases_ms": {k: round(float(np.mean([t[k] for t in timings])), 4)
-                      for k in ("build_ms", "pagerank_ms", "iterate_ms", "score_ms")},
+                      for k in ("build_ms", "pagerank_ms", "iterate_ms", "sweep_ms", "score_ms")},
         "analysis_pct_hbm_alg": round(alg_bytes / step_s / (HBM_PEAK_GBS * 1e9), 4),
         "score": info["score"],
     }

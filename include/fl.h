@@ -115,6 +115,9 @@ typedef struct {
     double score_ms;     /* output of the ranks, minima and C_p */
     int32_t iterations;  /* iteration kernels that did work */
     int32_t launches;    /* iteration kernels launched (extra ones exit at once) */
+    double sweep_ms;     /* device time of the sweep kernels that did work (the
+                            edge gathers alone), summed; measured only while
+                            fl_profile is on for the context, else 0 */
 } fl_timing;
 
 typedef struct fl_ctx fl_ctx;
@@ -177,6 +180,12 @@ fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *plan, int32_t *d_valid_raw,
  * earlier fl_execute calls are not touched.  Synchronises the stream. */
 fl_status fl_tune(fl_ctx *ctx, fl_plan *plan, const fl_params *params, int32_t sweeps, int32_t *best,
                   double *us_per_sweep);
+
+/* Sweep profiling: while `enable` is non-zero, fl_execute brackets every
+ * sweep kernel with a pair of HIP events on the context's stream and reports
+ * the summed device time of the sweeps that did work in fl_timing.sweep_ms.
+ * Costs a few microseconds of host time per iteration; off by default. */
+fl_status fl_profile(fl_ctx *ctx, int32_t enable);
 
 /* Phase timings of the plan's last build and execute (see fl_timing). */
 fl_status fl_plan_timing(fl_ctx *ctx, const fl_plan *plan, fl_timing *out);

@@ -49,7 +49,7 @@ class fl_timing(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("pagerank_ms", ctypes.c_double),
                 ("iterate_ms", ctypes.c_double), ("score_ms", ctypes.c_double),
                 ("iterations", ctypes.c_int32),
-                ("launches", ctypes.c_int32)]
+                ("launches", ctypes.c_int32), ("sweep_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -67,6 +67,7 @@ PROTOTYPES = {
                                   ctypes.POINTER(fl_summary)]),
     "fl_plan_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "fl_plan_timing": (ctypes.c_int, [_P, _P, ctypes.POINTER(fl_timing)]),
+    "fl_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "fl_plan_destroy": (ctypes.c_int, [_P, _P]),
     "fl_analyze": (ctypes.c_int, [_P, ctypes.POINTER(fl_space), _P, ctypes.c_int,
                                   ctypes.POINTER(fl_params), _P, _P, _P,

@@ -9,6 +9,7 @@ points without the ``fl_`` prefix:
     execute                            fl_execute       (PageRank, minima, C_p)
     plan_export / plan_timing          fl_plan_export / fl_plan_timing
     tune                               fl_tune          (autotune the sweep layout)
+    profile                            fl_profile       (per-sweep device timing)
     plan_destroy                       fl_plan_destroy
     analyze                            fl_analyze       (one shot)
     Batch / batch_create               fl_batch_create / _add / _step / _collect / _timing / _destroy
@@ -226,6 +227,11 @@ def tune(plan: Plan, damping: float = 0.85, sweeps: int = 4) -> dict:
     _check(plan.ctx, rc, "fl_tune")
     return {"best": int(best.value),
             "us_per_sweep": {lay: float(t) for lay, t in zip(TUNE_LAYOUTS, times) if t >= 0}}
+
+
+def profile(ctx: Context, enable: bool = True) -> None:
+    """Time every sweep kernel with HIP events (fl_profile); see plan_timing's sweep_ms."""
+    _check(ctx, _abi.load().fl_profile(ctx.handle, int(bool(enable))), "fl_profile")
 
 
 def plan_timing(plan: Plan) -> dict:

@@ -95,6 +95,8 @@ struct fl_ctx {
     std::string err;
     DevicePool pool;
     std::map<uint64_t, int> tuned;  // shape class -> sweep layout chosen by fl_tune
+    bool profile = false;           // bracket every sweep kernel with events (fl_profile)
+    std::vector<hipEvent_t> sweep_ev;  // 2 per launch of the longest chunk so far
     BuildSizes *h_sizes = nullptr;  // pinned
     PrState *h_state = nullptr;     // pinned
 };
@@ -701,6 +703,7 @@ fl_status fl_destroy(fl_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     ctx->pool.release_all();
+    for (hipEvent_t e : ctx->sweep_ev) (void)hipEventDestroy(e);
     (void)hipHostFree(ctx->h_sizes);
     (void)hipHostFree(ctx->h_state);
     delete ctx;
@@ -772,16 +775,32 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     // few host round trips and few empty launches are needed.
     int launches = 0;
     int chunk = 16;
-    double iterate_ms = 0.0;
+    double iterate_ms = 0.0, sweep_ms = 0.0;
     PrState *hs = ctx->h_state;
     for (;;) {
+        if (ctx->profile && (int)ctx->sweep_ev.size() < 2 * chunk) {
+            for (int j = (int)ctx->sweep_ev.size(); j < 2 * chunk; ++j) {
+                hipEvent_t e;
+                FL_HIP(hipEventCreate(&e));
+                ctx->sweep_ev.push_back(e);
+            }
+        }
         FL_HIP(hipEventRecord(p->ev[5], s));
-        for (int j = 0; j < chunk; ++j) FL_HIP(fl::launch_pr_iter(a, p->sp, p->sl, lanes, grid, s));
+        for (int j = 0; j < chunk; ++j) {
+            if (ctx->profile) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j], s));
+            FL_HIP(fl::launch_pr_sweep(a, p->sl, lanes, grid, s));
+            if (ctx->profile) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j + 1], s));
+            FL_HIP(fl::launch_pr_step(a, grid, s));
+        }
         FL_HIP(hipEventRecord(p->ev[6], s));
+        const int before = launches;
         launches += chunk;
         FL_HIP(hipMemcpyAsync(hs, p->state, sizeof(PrState), hipMemcpyDeviceToHost, s));
         FL_HIP(hipStreamSynchronize(s));
         iterate_ms += elapsed(p->ev[5], p->ev[6]);
+        if (ctx->profile)   // launches past the converged iteration exit at once: not counted
+            for (int j = 0; j < chunk && before + j < hs->worked; ++j)
+                sweep_ms += elapsed(ctx->sweep_ev[2 * j], ctx->sweep_ev[2 * j + 1]);
         if (hs->done) break;
         const double rate = (hs->resid_prev > 0.0) ? hs->resid / hs->resid_prev : 1.0;
         if (rate > 0.0 && rate < 0.999 && hs->resid > r.tol) {
@@ -804,6 +823,7 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     p->timing.pagerank_ms = elapsed(p->ev[2], p->ev[3]);
     p->timing.score_ms = elapsed(p->ev[3], p->ev[4]);
     p->timing.iterate_ms = iterate_ms;
+    p->timing.sweep_ms = sweep_ms;
     p->timing.iterations = hs->worked;
     p->timing.launches = launches;
     const fl_status result = hs->done == 1 ? FL_OK : FL_ENOCONV;
@@ -824,6 +844,13 @@ fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *p, int32_t *d_valid_raw, in
     if (d_row_ptr) FL_HIP(hipMemcpyAsync(d_row_ptr, p->row_ptr, 4 * (p->n + 1), hipMemcpyDeviceToDevice, s));
     if (d_col_idx && p->e > 0) FL_HIP(hipMemcpyAsync(d_col_idx, p->col_idx, 4 * p->e, hipMemcpyDeviceToDevice, s));
     if (d_out_deg) FL_HIP(hipMemcpyAsync(d_out_deg, p->out_deg, 4 * p->n, hipMemcpyDeviceToDevice, s));
+    return FL_OK;
+}
+
+fl_status fl_profile(fl_ctx *ctx, int32_t enable) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    ctx->profile = enable != 0;
     return FL_OK;
 }
 

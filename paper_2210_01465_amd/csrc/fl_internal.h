@@ -144,6 +144,9 @@ hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, c
 hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream);
 hipError_t launch_pr_iter(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
                           int grid, hipStream_t stream);
+// The two halves of launch_pr_iter: the sweep kernel, then the step kernel.
+hipError_t launch_pr_sweep(const PrArgs &a, const SlotTable &sl, int lanes, int grid, hipStream_t stream);
+hipError_t launch_pr_step(const PrArgs &a, int grid, hipStream_t stream);
 // Workgroups of the sweep kernel for this layout that fit on one CU at once.
 hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
                                  int *blocks);

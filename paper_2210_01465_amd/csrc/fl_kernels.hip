@@ -1113,18 +1113,26 @@ hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const Slo
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
 }
 
-hipError_t launch_pr_iter(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
-                          int grid, hipStream_t stream) {
-    (void)sp;
+hipError_t launch_pr_sweep(const PrArgs &a, const SlotTable &sl, int lanes, int grid, hipStream_t stream) {
     const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(lanes);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {(void *)&a};
-    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
-    if (e != hipSuccess) return e;
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+}
+
+hipError_t launch_pr_step(const PrArgs &a, int grid, hipStream_t stream) {
     // partial sums: one triple per tile (slot sweep) or per workgroup (CSR sweep)
     const int32_t count = a.kind == kSweepSlots ? (a.n + kBlock - 1) / kBlock : grid;
     hipLaunchKernelGGL(k_pr_finish<false>, dim3(1), dim3(kBlock), 0, stream, a, count);
     return hipGetLastError();
+}
+
+hipError_t launch_pr_iter(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
+                          int grid, hipStream_t stream) {
+    (void)sp;
+    hipError_t e = launch_pr_sweep(a, sl, lanes, grid, stream);
+    if (e != hipSuccess) return e;
+    return launch_pr_step(a, grid, stream);
 }
 
 hipError_t launch_pr_output(const PrArgs &a, double *pagerank, hipStream_t stream) {
