@@ -237,7 +237,12 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *batch, fl_plan *plan, const fl_par
 /* Run up to `sweeps` power-iteration sweeps (Sec. VII-B) for every running
  * member; members that converge or reach max_iter finish: their ranks,
  * minima and C_p (Sec. VII-B, eq. 3) are written.  *n_running receives the
- * number of members not yet finished.  Synchronises the stream. */
+ * number of members not yet finished.  The sweep loop of a step (per sweep:
+ * one launch per node-record width, then the step launch) is captured once
+ * in a HIP graph and replayed by later steps of the same launch shape (the
+ * number of sweeps and grid sizes rounded to powers of two); member lists
+ * and their lengths live in device memory, so members may join and leave
+ * between replays.  Synchronises the stream. */
 fl_status fl_batch_step(fl_ctx *ctx, fl_batch *batch, int32_t sweeps, int32_t *n_running);
 
 /* Remove up to `max` finished members: their tags and summaries (status
@@ -245,8 +250,15 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *batch, int32_t sweeps, int32_t *n
 fl_status fl_batch_collect(fl_ctx *ctx, fl_batch *batch, int32_t max, int64_t *tags, fl_summary *out,
                            int32_t *n_out);
 
-/* Sweeps run and device time of the sweep launches (HIP events) so far. */
-fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *batch, int64_t *sweeps, double *sweep_ms);
+/* Sweeps run and device time of the sweep launches (HIP events) so far;
+ * graph_launches / graph_captures (may be NULL): steps that replayed the
+ * captured sweep loop and captures made. */
+fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *batch, int64_t *sweeps, double *sweep_ms,
+                          int64_t *graph_launches, int64_t *graph_captures);
+
+/* Use the captured HIP graph for the sweep loop (enable != 0, the default)
+ * or launch its kernels one by one.  Results are identical either way. */
+fl_status fl_batch_set_graphs(fl_ctx *ctx, fl_batch *batch, int32_t enable);
 
 /* One-shot batched analysis of n_spaces spaces: the FFGs are built with one
  * synchronisation per build stage, then PageRank runs as one batch (spaces

@@ -334,11 +334,18 @@ class Batch:
         return out
 
     def timing(self) -> dict:
-        sweeps = ctypes.c_int64()
+        sweeps, launches, captures = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         ms = ctypes.c_double()
         _check(self.ctx, _abi.load().fl_batch_timing(self.ctx.handle, self.handle, ctypes.byref(sweeps),
-                                                      ctypes.byref(ms)), "fl_batch_timing")
-        return {"sweeps": int(sweeps.value), "sweep_ms": float(ms.value)}
+                                                      ctypes.byref(ms), ctypes.byref(launches),
+                                                      ctypes.byref(captures)), "fl_batch_timing")
+        return {"sweeps": int(sweeps.value), "sweep_ms": float(ms.value),
+                "graph_launches": int(launches.value), "graph_captures": int(captures.value)}
+
+    def set_graphs(self, enable: bool) -> None:
+        """Replay the captured sweep loop (default) or launch kernel by kernel."""
+        _check(self.ctx, _abi.load().fl_batch_set_graphs(self.ctx.handle, self.handle, int(bool(enable))),
+               "fl_batch_set_graphs")
 
     def close(self):
         if self.handle:

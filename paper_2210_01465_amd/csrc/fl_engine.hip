@@ -572,10 +572,33 @@ struct fl_batch {
     int64_t tile_cap = 0;
     int32_t *d_ids = nullptr, *h_ids = nullptr;  // regions: init | running | finishing
     PrState *d_states = nullptr, *h_states = nullptr;
+    // list ranges read by the sweep and step kernels: [2w], [2w+1] start and
+    // length of the tiles of record width w (1..kMaxWords) in the sweep list,
+    // [kRunCount] running members, [kInitCount] joining ones
+    static constexpr int kRunCount = 2 * fl::kMaxWords + 2, kInitCount = kRunCount + 1, kCounts = 16;
+    int32_t *d_counts = nullptr, *h_counts = nullptr;
     int sweep_per_cu[fl::kMaxWords + 1] = {};
     int64_t sweeps = 0;
     double sweep_ms = 0.0;
     hipEvent_t ev[2] = {};
+    // the captured sweep loop of one step and the launch shape it was captured for
+    bool use_graphs = true;
+    hipStream_t capture_stream = nullptr;  // private, only ever captured (the context's stream may be the null stream)
+    hipGraphExec_t graph = nullptr;
+    struct Shape {
+        int32_t sweeps = 0, finish_grid = 0;
+        int32_t grid[fl::kMaxWords + 1] = {};
+        const void *members = nullptr, *tiles = nullptr, *ids = nullptr;
+        bool operator==(const Shape &o) const {
+            if (sweeps != o.sweeps || finish_grid != o.finish_grid || members != o.members || tiles != o.tiles ||
+                ids != o.ids)
+                return false;
+            for (int w = 0; w <= fl::kMaxWords; ++w)
+                if (grid[w] != o.grid[w]) return false;
+            return true;
+        }
+    } shape;
+    int64_t graph_launches = 0, graph_captures = 0;
 };
 
 namespace {
@@ -962,7 +985,25 @@ fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out) {
         }
     }
     fl_status st = batch_reserve(b, 16, 1024);
+    if (st == FL_OK && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        b->capture_stream = nullptr;
+        st = fail(ctx, FL_EHIP, "hipStreamCreateWithFlags failed");
+    }
+    if (st == FL_OK) {
+        b->d_counts = pool_alloc<int32_t>(ctx, fl_batch::kCounts);
+        if (!b->d_counts ||
+            hipHostMalloc((void **)&b->h_counts, sizeof(int32_t) * fl_batch::kCounts, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            st = fail(ctx, FL_ENOMEM, "batch counters: allocation failed");
+        }
+    }
     if (st != FL_OK) {
+        batch_free_tables(b);
+        if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+        ctx->pool.release(b->d_counts);
+        for (auto &e : b->ev)
+            if (e) (void)hipEventDestroy(e);
         delete b;
         return st;
     }
@@ -978,6 +1019,10 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *b) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &m : b->members) member_release(ctx, m);
     batch_free_tables(b);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    ctx->pool.release(b->d_counts);
+    if (b->h_counts) (void)hipHostFree(b->h_counts);
     for (auto &e : b->ev) (void)hipEventDestroy(e);
     delete b;
     return FL_OK;
@@ -1053,10 +1098,8 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
     fl::TileRef *t_init = b->h_tiles, *t_sweep = b->h_tiles + tc, *t_out = b->h_tiles + 2 * tc;
     int32_t *i_init = b->h_ids, *i_run = b->h_ids + b->capacity, *i_fin = b->h_ids + 2 * b->capacity;
 
-    // member table (rows of members that left are never read)
-    FL_HIP(hipMemcpyAsync(b->d_members, b->h_members, sizeof(fl::BatchMember) * b->capacity,
-                          hipMemcpyHostToDevice, s));
-    // members that joined since the last step: initial iterate
+    // host lists: joining members and their tiles, running members and
+    // their tiles grouped by record width
     int32_t n_init = 0;
     int64_t nt_init = 0;
     for (auto &m : b->members) {
@@ -1065,12 +1108,6 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         for (int32_t t = 0; t < tiles_of(m.plan); ++t) t_init[nt_init++] = {m.slot, t};
         m.phase = 1;
     }
-    if (n_init > 0) {
-        FL_HIP(hipMemcpyAsync(b->d_tiles, t_init, sizeof(fl::TileRef) * nt_init, hipMemcpyHostToDevice, s));
-        FL_HIP(hipMemcpyAsync(b->d_ids, i_init, sizeof(int32_t) * n_init, hipMemcpyHostToDevice, s));
-        FL_HIP(fl::launch_batch_init(b->d_members, b->d_tiles, (int32_t)nt_init, b->d_ids, n_init, s));
-    }
-    // running members, their tiles grouped by record width
     int32_t n_run = 0;
     int64_t group_begin[fl::kMaxWords + 2] = {};
     int64_t nt = 0;
@@ -1083,22 +1120,96 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         }
     }
     group_begin[fl::kMaxWords + 1] = nt;
+    int32_t *hc = b->h_counts;
+    memset(hc, 0, sizeof(int32_t) * fl_batch::kCounts);
+    for (int w = 1; w <= fl::kMaxWords; ++w) {
+        hc[2 * w] = (int32_t)group_begin[w];
+        hc[2 * w + 1] = (int32_t)(group_begin[w + 1] - group_begin[w]);
+    }
+    hc[fl_batch::kRunCount] = n_run;
+    hc[fl_batch::kInitCount] = n_init;
+
+    // uploads: member table (rows of members that left are never read),
+    // lists, counts
     fl::TileRef *d_sweep = b->d_tiles + tc;
     int32_t *d_run = b->d_ids + b->capacity;
+    FL_HIP(hipMemcpyAsync(b->d_members, b->h_members, sizeof(fl::BatchMember) * b->capacity,
+                          hipMemcpyHostToDevice, s));
+    FL_HIP(hipMemcpyAsync(b->d_counts, hc, sizeof(int32_t) * fl_batch::kCounts, hipMemcpyHostToDevice, s));
+    if (n_init > 0) {
+        FL_HIP(hipMemcpyAsync(b->d_tiles, t_init, sizeof(fl::TileRef) * nt_init, hipMemcpyHostToDevice, s));
+        FL_HIP(hipMemcpyAsync(b->d_ids, i_init, sizeof(int32_t) * n_init, hipMemcpyHostToDevice, s));
+        // joining members: initial iterate
+        FL_HIP(fl::launch_batch_init(b->d_members, b->d_tiles, (int32_t)nt_init, b->d_ids, n_init,
+                                     b->d_counts + fl_batch::kInitCount, s));
+    }
     if (n_run > 0 && sweeps > 0) {
         FL_HIP(hipMemcpyAsync(d_sweep, t_sweep, sizeof(fl::TileRef) * nt, hipMemcpyHostToDevice, s));
         FL_HIP(hipMemcpyAsync(d_run, i_run, sizeof(int32_t) * n_run, hipMemcpyHostToDevice, s));
-        FL_HIP(hipEventRecord(b->ev[0], s));
-        for (int32_t j = 0; j < sweeps; ++j) {
-            for (int w = 1; w <= fl::kMaxWords; ++w) {
-                const int64_t cnt = group_begin[w + 1] - group_begin[w];
-                if (cnt == 0) continue;
-                const int64_t resident = (int64_t)std::max(b->sweep_per_cu[w], 1) * ctx->num_cus / fl::kXcds * fl::kXcds;
-                const int grid = (int)std::max<int64_t>(
-                    fl::kXcds, std::min<int64_t>(resident, (cnt + fl::kXcds - 1) / fl::kXcds * fl::kXcds));
-                FL_HIP(fl::launch_batch_sweep(b->d_members, d_sweep + group_begin[w], (int32_t)cnt, w, grid, s));
+        // launch shape: grids rounded up to powers of two (times the XCD
+        // count) so that small changes of membership reuse the captured graph
+        fl_batch::Shape shape;
+        shape.sweeps = sweeps;
+        shape.members = b->d_members;
+        shape.tiles = b->d_tiles;
+        shape.ids = b->d_ids;
+        for (int w = 1; w <= fl::kMaxWords; ++w) {
+            const int32_t cnt = hc[2 * w + 1];
+            if (cnt == 0) continue;
+            const int64_t resident =
+                (int64_t)std::max(b->sweep_per_cu[w], 1) * ctx->num_cus / fl::kXcds * fl::kXcds;
+            int64_t g = fl::kXcds;
+            while (g < resident && g < cnt) g *= 2;
+            shape.grid[w] = (int32_t)std::max<int64_t>(fl::kXcds, std::min(g, resident));
+        }
+        int32_t fg = 1;
+        while (fg < n_run && fg < fl::kMaxFinishGrid) fg *= 2;
+        shape.finish_grid = fg;
+        auto enqueue = [&](hipStream_t q) -> hipError_t {
+            for (int32_t j = 0; j < sweeps; ++j) {
+                for (int w = 1; w <= fl::kMaxWords; ++w) {
+                    if (shape.grid[w] == 0) continue;
+                    hipError_t e = fl::launch_batch_sweep(b->d_members, d_sweep, b->d_counts + 2 * w, w,
+                                                          shape.grid[w], q);
+                    if (e != hipSuccess) return e;
+                }
+                hipError_t e = fl::launch_batch_finish(b->d_members, d_run, b->d_counts + fl_batch::kRunCount,
+                                                       shape.finish_grid, q);
+                if (e != hipSuccess) return e;
             }
-            FL_HIP(fl::launch_batch_finish(b->d_members, d_run, n_run, s));
+            return hipSuccess;
+        };
+        FL_HIP(hipEventRecord(b->ev[0], s));
+        if (b->use_graphs) {
+            if (!b->graph || !(shape == b->shape)) {
+                if (b->graph) {
+                    FL_HIP(hipGraphExecDestroy(b->graph));
+                    b->graph = nullptr;
+                }
+                // captured on the private stream (capture runs nothing),
+                // launched on the context's stream
+                hipGraph_t g = nullptr;
+                FL_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+                const hipError_t le = enqueue(b->capture_stream);
+                const hipError_t ce = hipStreamEndCapture(b->capture_stream, &g);
+                if (le != hipSuccess || ce != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return fail(ctx, FL_EHIP, "graph capture: %s",
+                                hipGetErrorString(le != hipSuccess ? le : ce));
+                }
+                const hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess) {
+                    b->graph = nullptr;
+                    return fail(ctx, FL_EHIP, "graph instantiation: %s", hipGetErrorString(ie));
+                }
+                b->shape = shape;
+                ++b->graph_captures;
+            }
+            FL_HIP(hipGraphLaunch(b->graph, s));
+            ++b->graph_launches;
+        } else {
+            FL_HIP(enqueue(s));
         }
         FL_HIP(hipEventRecord(b->ev[1], s));
         b->sweeps += sweeps;
@@ -1171,11 +1282,22 @@ fl_status fl_batch_collect(fl_ctx *ctx, fl_batch *b, int32_t max, int64_t *tags,
     return FL_OK;
 }
 
-fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *b, int64_t *sweeps, double *sweep_ms) {
+fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *b, int64_t *sweeps, double *sweep_ms,
+                          int64_t *graph_launches, int64_t *graph_captures) {
     if (!ctx) return FL_EINVAL;
     if (!b || b->ctx != ctx) return fail(ctx, FL_EINVAL, "bad batch");
     if (sweeps) *sweeps = b->sweeps;
     if (sweep_ms) *sweep_ms = b->sweep_ms;
+    if (graph_launches) *graph_launches = b->graph_launches;
+    if (graph_captures) *graph_captures = b->graph_captures;
+    return FL_OK;
+}
+
+fl_status fl_batch_set_graphs(fl_ctx *ctx, fl_batch *b, int32_t enable) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!b || b->ctx != ctx) return fail(ctx, FL_EINVAL, "bad batch");
+    b->use_graphs = enable != 0;
     return FL_OK;
 }
 

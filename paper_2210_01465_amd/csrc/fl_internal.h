@@ -15,6 +15,7 @@ constexpr int kCompactItems = 8;                  // raw configurations per thre
 constexpr int kCompactTile = kBlock * kCompactItems;
 constexpr int kXcds = 8;                          // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int kBatch = 16;                        // candidate slots whose loads are issued together
+constexpr int kMaxFinishGrid = 1024;              // workgroups of the batched step kernel (grid-stride)
 
 // Mixed-radix description of a search space X = S_1 x ... x S_n, parameter 0
 // most significant: stride[i] = prod_{j>i} radix[j].  Digits are peeled off
@@ -155,14 +156,18 @@ hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m
                         const float *fit_c, double threshold, PrState *st, hipStream_t stream);
 
 // Batched power iteration.  `tiles` lists the tiles to work on; `members`
-// lists member indices for the per-member kernels.
+// lists member indices for the per-member kernels.  The sweep kernel reads
+// its list's start and length (range_dev[0], range_dev[1]) and the step
+// kernel its list length from device memory, so launches captured in a
+// graph stay valid while the lists change between replays.
 hipError_t launch_batch_init(const BatchMember *members, const TileRef *tiles, int32_t n_tiles,
-                             const int32_t *member_ids, int32_t n_members, hipStream_t stream);
-hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, int32_t n_tiles, int words,
-                              int grid, hipStream_t stream);
+                             const int32_t *member_ids, int32_t n_members, const int32_t *n_members_dev,
+                             hipStream_t stream);
+hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, const int32_t *range_dev,
+                              int words, int grid, hipStream_t stream);
 hipError_t batch_sweep_blocks_per_cu(int words, int *blocks);
-hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, int32_t n_members,
-                               hipStream_t stream);
+hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, const int32_t *n_members_dev,
+                               int grid, hipStream_t stream);
 hipError_t launch_batch_output(const BatchMember *members, const TileRef *tiles, int32_t n_tiles,
                                const int32_t *member_ids, int32_t n_members, PrState *states_out,
                                hipStream_t stream);

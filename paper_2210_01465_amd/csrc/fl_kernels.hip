@@ -876,9 +876,13 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
 
 template <int W, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchMember *__restrict__ members,
-                                                        const TileRef *__restrict__ tiles, int32_t n_tiles) {
-    const TileWalk w(n_tiles);
-    const_ptr<TileRef> tl = to_const(tiles);
+                                                        const TileRef *__restrict__ tiles,
+                                                        const int32_t *__restrict__ range_dev) {
+    // the list's start and length are read from device memory, so a captured
+    // launch stays valid while members join and leave between replays
+    const int32_t begin = to_const(range_dev)[0], count = to_const(range_dev)[1];
+    const TileWalk w(count);
+    const_ptr<TileRef> tl = to_const(tiles) + begin;
     for (int32_t t = w.first; t < w.end; t += w.step) {
         const int32_t member = tl[t].member, tile = tl[t].tile;
         const_ptr<BatchMember> m = to_const(members) + member;
@@ -914,14 +918,20 @@ __global__ __launch_bounds__(kBlock) void k_batch_init(const BatchMember *__rest
     }
 }
 
-// One workgroup per listed member: reduce its tiles' partial sums and set up
-// its next step, exactly as for a single space.
+// One workgroup per listed member (grid-stride over the list, whose length
+// is read from device memory): reduce its tiles' partial sums and set up its
+// next step, exactly as for a single space.
 template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_batch_finish(const BatchMember *__restrict__ members,
-                                                         const int32_t *__restrict__ member_ids) {
-    const BatchMember &m = members[member_ids[blockIdx.x]];
-    if (!FIRST && m.st->done) return;
-    finish_step(m.st, m.partials, m.n_tiles, m.d, m.tol, m.max_iter, m.n, FIRST);
+                                                         const int32_t *__restrict__ member_ids,
+                                                         const int32_t *__restrict__ n_members_dev) {
+    const int32_t n_members = *to_const(n_members_dev);
+    for (int32_t j = blockIdx.x; j < n_members; j += gridDim.x) {
+        const BatchMember &m = members[member_ids[j]];
+        if (!FIRST && m.st->done) continue;   // uniform per workgroup
+        finish_step(m.st, m.partials, m.n_tiles, m.d, m.tol, m.max_iter, m.n, FIRST);
+        __syncthreads();                       // block_sum3's LDS is reused by the next member
+    }
 }
 
 // Ranks r = y * s into the member's output for every listed tile.
@@ -1149,12 +1159,14 @@ hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m
 }
 
 hipError_t launch_batch_init(const BatchMember *members, const TileRef *tiles, int32_t n_tiles,
-                             const int32_t *member_ids, int32_t n_members, hipStream_t stream) {
+                             const int32_t *member_ids, int32_t n_members, const int32_t *n_members_dev,
+                             hipStream_t stream) {
     if (n_tiles > 0)
         hipLaunchKernelGGL(k_batch_init, dim3(std::min<int32_t>(n_tiles, 8192)), dim3(kBlock), 0, stream, members,
                            tiles, n_tiles);
     if (n_members > 0)
-        hipLaunchKernelGGL(k_batch_finish<true>, dim3(n_members), dim3(kBlock), 0, stream, members, member_ids);
+        hipLaunchKernelGGL(k_batch_finish<true>, dim3(std::min<int32_t>(n_members, kMaxFinishGrid)), dim3(kBlock), 0,
+                           stream, members, member_ids, n_members_dev);
     return hipGetLastError();
 }
 
@@ -1175,19 +1187,18 @@ hipError_t batch_sweep_blocks_per_cu(int words, int *blocks) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
 }
 
-hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, int32_t n_tiles, int words,
-                              int grid, hipStream_t stream) {
+hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, const int32_t *range_dev,
+                              int words, int grid, hipStream_t stream) {
     const void *fn = batch_sweep_kernel(words);
     if (!fn) return hipErrorInvalidValue;
-    if (n_tiles == 0) return hipSuccess;
-    void *args[] = {(void *)&members, (void *)&tiles, (void *)&n_tiles};
+    void *args[] = {(void *)&members, (void *)&tiles, (void *)&range_dev};
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
 }
 
-hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, int32_t n_members,
-                               hipStream_t stream) {
-    if (n_members > 0)
-        hipLaunchKernelGGL(k_batch_finish<false>, dim3(n_members), dim3(kBlock), 0, stream, members, member_ids);
+hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, const int32_t *n_members_dev,
+                               int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_finish<false>, dim3(grid), dim3(kBlock), 0, stream, members, member_ids,
+                       n_members_dev);
     return hipGetLastError();
 }
 

@@ -115,6 +115,57 @@ def test_members_join_mid_run(ctx):
         pl.close()
 
 
+def _run_stream(ctx, spaces, graphs):
+    """Members join one per step (adjacent neighbourhood for odd ones) and
+    the finished ones leave, so the member lists change between replays of
+    the captured sweep loop."""
+    import torch
+    from paper_2210_01465_amd import api
+    batch = api.Batch(ctx)
+    batch.set_graphs(graphs)
+    fits, plans, done = [], [], {}
+    pending = list(range(len(spaces)))
+    while True:
+        if pending:
+            j = pending.pop(0)
+            fits.append(torch.from_numpy(spaces[j].fitness_raw).cuda())
+            plans.append(api.plan_create(ctx, spaces[j].radix, fits[-1], ("hamming", "adjacent")[j % 2]))
+            batch.add(plans[-1], (0.8, 0.85, 0.9)[j % 3], 0.05, tag=j)
+        running = batch.step(4)
+        for tag, pr, mins, info in batch.collect():
+            done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+        if running == 0 and not pending:
+            break
+    timing = batch.timing()
+    batch.close()
+    for pl in plans:
+        pl.close()
+    return done, timing
+
+
+def test_graph_replays_equal_eager_launches(ctx):
+    """The captured sweep loop, replayed across steps with host copies,
+    state readbacks and output kernels between replays, gives the same ranks
+    bit for bit as launching its kernels one by one; every replay is checked
+    through the members that finish after it."""
+    spaces = [synth.tiny(2), synth.mid()] + synth.batched()[3:120:7] + [synth.tiny(5)]
+    say(f"graph vs eager, {len(spaces)} joining members")
+    eager, t_eager = _run_stream(ctx, spaces, graphs=False)
+    graph, t_graph = _run_stream(ctx, spaces, graphs=True)
+    assert t_eager["graph_launches"] == 0
+    assert t_graph["graph_launches"] > t_graph["graph_captures"] > 0   # captured graphs were replayed
+    assert t_graph["sweeps"] == t_eager["sweeps"]
+    assert sorted(graph) == sorted(eager) == list(range(len(spaces)))
+    for j in range(len(spaces)):
+        assert np.array_equal(graph[j][0], eager[j][0]), spaces[j].name
+        assert np.array_equal(graph[j][1], eager[j][1])
+        assert graph[j][2]["iterations"] == eager[j][2]["iterations"]
+        assert graph[j][2]["score"] == eager[j][2]["score"]
+    for j in (0, 1, len(spaces) - 1):   # and against the plain path
+        ref = plain(ctx, spaces[j], ("hamming", "adjacent")[j % 2], (0.8, 0.85, 0.9)[j % 3], 0.05)
+        assert np.array_equal(graph[j][0], ref[0])
+
+
 def test_analyze_batch_against_oracle(ctx):
     import torch
     from paper_2210_01465_amd import api
