@@ -16,6 +16,7 @@ constexpr int kCompactTile = kBlock * kCompactItems;
 constexpr int kXcds = 8;                          // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int kBatch = 16;                        // candidate slots whose loads are issued together
 constexpr int kMaxFinishGrid = 1024;              // workgroups of the batched step kernel (grid-stride)
+constexpr int kFinishBlock = 1024;                // threads of a step kernel workgroup (1 mod 3)
 
 // Mixed-radix description of a search space X = S_1 x ... x S_n, parameter 0
 // most significant: stride[i] = prod_{j>i} radix[j].  Digits are peeled off

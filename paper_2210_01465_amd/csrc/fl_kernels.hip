@@ -553,8 +553,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_generic(SpaceDesc sp, const flo
 // release from every workgroup, which costs more than the extra launch.)
 
 // Sum three values over the workgroup (valid in every thread), fixed tree.
+template <int B = kBlock>
 __device__ void block_sum3(double &a, double &b, double &c) {
-    __shared__ double part[3][kBlock / 64];
+    __shared__ double part[3][B / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     a = wave_sum(a);
     b = wave_sum(b);
@@ -569,7 +570,7 @@ __device__ void block_sum3(double &a, double &b, double &c) {
     b = part[1][0];
     c = part[2][0];
 #pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w) {
+    for (int w = 1; w < B / 64; ++w) {
         a += part[0][w];
         b += part[1][w];
         c += part[2][w];
@@ -588,26 +589,36 @@ __device__ __forceinline__ void write_partials(double *partials, int32_t j, doub
 }
 
 // Reduce `count` partial triples in a fixed order and set up the next step.
-// One workgroup.  first: the triples come from the initial iterate.
+// One workgroup of kFinishBlock threads.  The triples are read as one flat
+// array with consecutive threads on consecutive doubles; rounds of
+// 3 kFinishBlock elements keep the component of a thread's q-th element of
+// a round fixed at (threadIdx.x + q kFinishBlock) mod 3.  first: the triples
+// come from the initial iterate.
 __device__ void finish_step(PrState *st, const double *__restrict__ partials, int32_t count, double d, double tol,
                             int32_t max_iter, int32_t n, bool first) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int32_t t0 = 0; t0 < count; t0 += 4 * kBlock) {
+    constexpr int B = kFinishBlock, kRound = 3 * B;
+    const int64_t total = 3 * (int64_t)count;
+    double r[3] = {0.0, 0.0, 0.0};   // r[q]: component (threadIdx.x + q B) mod 3
+    for (int64_t e0 = 0; e0 < total; e0 += 4 * kRound) {
         double v[4][3];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int32_t t = t0 + u * kBlock + threadIdx.x;
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int q = 0; q < 3; ++q) v[u][q] = t < count ? partials[3 * (int64_t)t + q] : 0.0;
-        }
+            for (int q = 0; q < 3; ++q) {
+                const int64_t e = e0 + u * kRound + q * B + threadIdx.x;
+                v[u][q] = e < total ? partials[e] : 0.0;
+            }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            s0 += v[u][0];
-            s1 += v[u][1];
-            s2 += v[u][2];
-        }
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) r[q] += v[u][q];
     }
-    block_sum3(s0, s1, s2);
+    static_assert(B % 3 == 1, "component rotation assumes B = 1 mod 3");
+    const int c0 = threadIdx.x % 3;   // component of r[0]; r[q] holds component (c0 + q) mod 3
+    double s0 = c0 == 0 ? r[0] : (c0 == 2 ? r[1] : r[2]);
+    double s1 = c0 == 1 ? r[0] : (c0 == 0 ? r[1] : r[2]);
+    double s2 = c0 == 2 ? r[0] : (c0 == 1 ? r[1] : r[2]);
+    block_sum3<B>(s0, s1, s2);
     if (threadIdx.x == 0) {
         const double s = 1.0 / s0;
         st->sigma = s0;
@@ -635,7 +646,7 @@ __device__ void finish_step(PrState *st, const double *__restrict__ partials, in
 
 // Step kernel: skipped, like the sweep it follows, once the stop flag is set.
 template <bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_pr_finish(PrArgs a, int32_t count) {
+__global__ __launch_bounds__(kFinishBlock) void k_pr_finish(PrArgs a, int32_t count) {
     if (!FIRST && a.st->done) return;
     finish_step(a.st, a.partials, count, a.d, a.tol, a.max_iter, a.n, FIRST);
 }
@@ -922,7 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_init(const BatchMember *__rest
 // is read from device memory): reduce its tiles' partial sums and set up its
 // next step, exactly as for a single space.
 template <bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_batch_finish(const BatchMember *__restrict__ members,
+__global__ __launch_bounds__(kFinishBlock) void k_batch_finish(const BatchMember *__restrict__ members,
                                                          const int32_t *__restrict__ member_ids,
                                                          const int32_t *__restrict__ n_members_dev) {
     const int32_t n_members = *to_const(n_members_dev);
@@ -1111,7 +1122,7 @@ hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, c
 hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream) {
     const int32_t n_tiles = (a.n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_pr_init, dim3(grid), dim3(kBlock), 0, stream, a);
-    hipLaunchKernelGGL(k_pr_finish<true>, dim3(1), dim3(kBlock), 0, stream, a, n_tiles);
+    hipLaunchKernelGGL(k_pr_finish<true>, dim3(1), dim3(kFinishBlock), 0, stream, a, n_tiles);
     return hipGetLastError();
 }
 
@@ -1133,7 +1144,7 @@ hipError_t launch_pr_sweep(const PrArgs &a, const SlotTable &sl, int lanes, int 
 hipError_t launch_pr_step(const PrArgs &a, int grid, hipStream_t stream) {
     // partial sums: one triple per tile (slot sweep) or per workgroup (CSR sweep)
     const int32_t count = a.kind == kSweepSlots ? (a.n + kBlock - 1) / kBlock : grid;
-    hipLaunchKernelGGL(k_pr_finish<false>, dim3(1), dim3(kBlock), 0, stream, a, count);
+    hipLaunchKernelGGL(k_pr_finish<false>, dim3(1), dim3(kFinishBlock), 0, stream, a, count);
     return hipGetLastError();
 }
 
@@ -1165,7 +1176,7 @@ hipError_t launch_batch_init(const BatchMember *members, const TileRef *tiles, i
         hipLaunchKernelGGL(k_batch_init, dim3(std::min<int32_t>(n_tiles, 8192)), dim3(kBlock), 0, stream, members,
                            tiles, n_tiles);
     if (n_members > 0)
-        hipLaunchKernelGGL(k_batch_finish<true>, dim3(std::min<int32_t>(n_members, kMaxFinishGrid)), dim3(kBlock), 0,
+        hipLaunchKernelGGL(k_batch_finish<true>, dim3(std::min<int32_t>(n_members, kMaxFinishGrid)), dim3(kFinishBlock), 0,
                            stream, members, member_ids, n_members_dev);
     return hipGetLastError();
 }
@@ -1197,7 +1208,7 @@ hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, 
 
 hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, const int32_t *n_members_dev,
                                int grid, hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch_finish<false>, dim3(grid), dim3(kBlock), 0, stream, members, member_ids,
+    hipLaunchKernelGGL(k_batch_finish<false>, dim3(grid), dim3(kFinishBlock), 0, stream, members, member_ids,
                        n_members_dev);
     return hipGetLastError();
 }
