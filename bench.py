@@ -139,7 +139,7 @@ def batched_leg(ctx, damping, p, tol, repeats: int = 3):
     t0 = time.perf_counter()
     for s, f in zip(spaces, fits):
         plan = api.plan_create(ctx, s.radix, f, "hamming")
-        api.execute(plan, damping, p, tol=tol, row_mapping=-1)
+        api.execute(plan, damping, p, tol=tol)
         plan.close()
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--traffic-from", metavar="DIR",
                     help="write the sweep kernel's HBM traffic record from the rocprofv3 --pmc "
                          "runs under DIR (no GPU needed) and exit")
-    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true>")
+    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true, true>")
     ap.add_argument("--traffic-copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--traffic-command", default="")
     ap.add_argument("--no-sweep-events", action="store_true",
@@ -293,9 +293,11 @@ def main():
         avg_launch_s = sum(t["iterate_ms"] for t in timings) / 1e3 / sum(t["launches"] for t in timings)
     else:                           # sweep kernels that did work, each between its own events
         avg_launch_s = sum(t["sweep_ms"] for t in timings) / 1e3 / sum(t["iterations"] for t in timings)
-    if info["row_mapping"] == -1:   # slot sweep: valid_raw, masks, y in/out, out_deg, x out; x gathers
+    if info["row_mapping"] in (-1, -2):   # slot sweeps: records, y in/out, x out; x gathers
         bytes_per_launch = (20 + 8 * info["mask_words"]) * N + 4 * E
-        kernel = f"k_pr_iter_slots<{info['mask_words']}, {'true' if 4 * n_raw < 2 ** 31 else 'false'}>"
+        buf = 16 * ((n_raw + 3) // 4) < 2 ** 31
+        kernel = (f"k_pr_iter_slots<{info['mask_words']}, {'true' if buf else 'false'}, "
+                  f"{'true' if info['row_mapping'] == -2 else 'false'}>")
     else:                           # CSR sweep: row_ptr, out_deg, y in/out, x out, col_idx, x gathers
         bytes_per_launch = 20 * N + 8 * E
         kernel = f"k_pr_iter_csr<{info['row_mapping']}>"

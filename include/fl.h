@@ -74,11 +74,21 @@ typedef struct {
  *   p         proportion for C_p as a fraction (0.05 = 5 %), p >= 0 and finite.
  *   tol_l1    stop when ||r_{k+1} - r_k||_1 < tol_l1 (0 => 2e-7).
  *   max_iter  iteration cap (0 => 1000); reaching it gives FL_ENOCONV.
- *   row_mapping  layout of the PageRank sweep: 0 = automatic; FL_ROWS_SLOTS =
- *             one node per lane over the in-edge slot masks (needs at most 128
- *             candidate slots per node); 1, 2, 4, 8, 16, 32 or 64 = that many
- *             lanes per row over the CSR. */
+ *   row_mapping  layout of the PageRank sweep: 0 = automatic (the layout
+ *             fl_tune cached for the plan's shape class, else
+ *             FL_ROWS_SLOTS_WIN where available, else FL_ROWS_SLOTS, else
+ *             CSR lanes from the mean in-degree); FL_ROWS_SLOTS = one node
+ *             per lane over the in-edge slot records (needs at most 256
+ *             candidate slots per node); FL_ROWS_SLOTS_WIN = the same with
+ *             the slots of offset |off| <= 256 read from a per-wave window
+ *             of x staged in LDS (also needs fewer than 2^29 raw
+ *             configurations); 1, 2, 4, 8, 16, 32 or 64 = that many lanes
+ *             per row over the CSR.  Every layout sums a row's terms in the
+ *             same order: the slot layouts and the one-lane CSR layout give
+ *             the same ranks bit for bit. */
 #define FL_ROWS_SLOTS (-1)
+#define FL_ROWS_SLOTS_WIN (-2)
+#define FL_TUNE_LAYOUTS 9
 typedef struct {
     double damping;
     double p;
@@ -168,15 +178,15 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *plan, const fl_params *params,
 fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *plan, int32_t *d_valid_raw,
                          int32_t *d_row_ptr, int32_t *d_col_idx, int32_t *d_out_deg);
 
-/* Autotuner: time every sweep layout the plan allows (the slot sweep and the
- * CSR sweep with 1, 2, 4, 8, 16, 32, 64 lanes per row) for `sweeps` forced
- * power-iteration sweeps each (HIP events, after one warm-up sweep), store
- * the fastest in the context's tuning cache under the plan's shape class
- * (node-record width, neighbourhood, log2 N, mean in-degree) and return it
- * in *best.  us_per_sweep (may be NULL) receives 8 times in microseconds in
- * that layout order, -1 where a layout does not apply.  Afterwards
- * fl_execute with row_mapping 0 uses the cached layout for plans of the
- * same shape class.  The plan's iterate buffers are overwritten; outputs of
+/* Autotuner: time every sweep layout the plan allows (the windowed and the
+ * plain slot sweep, then the CSR sweep with 1, 2, 4, 8, 16, 32, 64 lanes
+ * per row) for `sweeps` forced power-iteration sweeps each (HIP events,
+ * after one warm-up sweep), store the fastest in the context's tuning cache
+ * under the plan's shape class (node-record width, neighbourhood, log2 N,
+ * mean in-degree) and return it in *best.  us_per_sweep (may be NULL)
+ * receives FL_TUNE_LAYOUTS times in microseconds in that layout order, -1
+ * where a layout does not apply.  Afterwards fl_execute with row_mapping 0
+ * uses the cached layout for plans of the same shape class.  The plan's iterate buffers are overwritten; outputs of
  * earlier fl_execute calls are not touched.  Synchronises the stream. */
 fl_status fl_tune(fl_ctx *ctx, fl_plan *plan, const fl_params *params, int32_t sweeps, int32_t *best,
                   double *us_per_sweep);

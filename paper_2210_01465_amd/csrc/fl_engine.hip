@@ -213,11 +213,18 @@ fl::SlotTable make_slots(const SpaceDesc &sp, bool adjacent) {
         }
     }
     std::sort(slots.begin(), slots.end(), [](const Slot &x, const Slot &y) { return x.off < y.off; });
+    t.win_lo = -1;
     for (size_t s = 0; s < slots.size(); ++s) {
         t.off[s] = (int32_t)slots[s].off;
         t.delta[s] = (int16_t)slots[s].delta;
         t.dim[s] = (uint8_t)slots[s].dim;
+        if (std::llabs(slots[s].off) <= fl::kWinMaxOff) {   // contiguous: the slots are sorted by offset
+            if (t.win_lo < 0) t.win_lo = (int32_t)s;
+            t.win_hi = (int32_t)s + 1;
+            t.win_t = std::max<int32_t>(t.win_t, (int32_t)std::llabs(slots[s].off));
+        }
     }
+    if (t.win_lo < 0) t.win_lo = t.win_hi = t.win_t = 0;
     return t;
 }
 
@@ -412,10 +419,24 @@ void fill_sizes(const fl_plan *p, fl_summary *sizes) {
 }
 
 // Analysis parameters with the defaults applied.
+// Bytes of an x buffer in raw-index space (n_raw rounded up to whole 16-byte
+// groups) when buffer loads can address it with room for the out-of-range
+// offset bit, else 0.
+int32_t x_bytes_of(const fl_plan *p) {
+    const int64_t b = 4 * ((p->n_raw + 3) / 4 * 4);
+    return b < (int64_t(1) << 31) ? (int32_t)b : 0;
+}
+
+bool is_slot_layout(int lanes) { return lanes == FL_ROWS_SLOTS || lanes == FL_ROWS_SLOTS_WIN; }
+
+// The windowed slot sweep is available: records, buffer-addressable x, and
+// at least one slot within the window reach.
+bool window_ok(const fl_plan *p) { return p->sl.words > 0 && x_bytes_of(p) > 0 && p->sl.win_t > 0; }
+
 struct Resolved {
     double d, p, tol;
     int32_t max_iter;
-    int lanes;  // FL_ROWS_SLOTS or CSR lanes
+    int lanes;  // FL_ROWS_SLOTS, FL_ROWS_SLOTS_WIN or CSR lanes
 };
 
 fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Resolved &r) {
@@ -424,16 +445,20 @@ fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Re
     if (!(prm->p >= 0.0) || !isfinite(prm->p)) return fail(ctx, FL_EINVAL, "p must be finite and >= 0");
     if (!(prm->tol_l1 >= 0.0) || !isfinite(prm->tol_l1)) return fail(ctx, FL_EINVAL, "tol_l1 must be finite and >= 0");
     if (prm->max_iter < 0) return fail(ctx, FL_EINVAL, "max_iter must be >= 0");
-    if (prm->row_mapping != 0 && prm->row_mapping != FL_ROWS_SLOTS && !valid_lanes(prm->row_mapping))
-        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS or a power of two <= 64");
-    if (prm->row_mapping == FL_ROWS_SLOTS && p->sl.words == 0)
+    if (prm->row_mapping != 0 && !is_slot_layout(prm->row_mapping) && !valid_lanes(prm->row_mapping))
+        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS, FL_ROWS_SLOTS_WIN or a power of two <= 64");
+    if (is_slot_layout(prm->row_mapping) && p->sl.words == 0)
         return fail(ctx, FL_EINVAL, "the slot sweep needs at most %d candidate slots (space has %d)",
                     fl::kMaxSlots, p->sl.k);
+    if (prm->row_mapping == FL_ROWS_SLOTS_WIN && !window_ok(p))
+        return fail(ctx, FL_EINVAL, "the windowed slot sweep needs a raw index space below 2^29 configurations");
     r.d = d;
     r.p = prm->p;
     r.tol = prm->tol_l1 > 0.0 ? prm->tol_l1 : 2e-7;
     r.max_iter = prm->max_iter > 0 ? prm->max_iter : 1000;
-    r.lanes = prm->row_mapping ? prm->row_mapping : (p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e));
+    r.lanes = prm->row_mapping ? prm->row_mapping
+                               : (window_ok(p) ? FL_ROWS_SLOTS_WIN
+                                               : (p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e)));
     return FL_OK;
 }
 
@@ -444,7 +469,7 @@ fl_status ensure_pr_buffers(fl_ctx *ctx, fl_plan *p, bool slots) {
         p->state = pool_alloc<PrState>(ctx, 1);
         if (!p->y[0] || !p->y[1] || !p->state) return fail(ctx, FL_ENOMEM, "device allocation failed");
     }
-    const int64_t x_need = slots ? p->n_raw : p->n;
+    const int64_t x_need = slots ? (p->n_raw + 3) / 4 * 4 : p->n;   // whole 16-byte groups (windowed sweep)
     if (x_need > p->x_cap) {
         for (int j = 0; j < 2; ++j) {
             ctx->pool.release(p->x[j]);
@@ -470,9 +495,7 @@ fl_status ensure_partials(fl_ctx *ctx, fl_plan *p, int64_t triples) {
     return FL_OK;
 }
 
-int32_t x_bytes_of(const fl_plan *p) {
-    return 4 * p->n_raw < (int64_t(1) << 31) ? (int32_t)(4 * p->n_raw) : 0;
-}
+
 
 void fill_summary(const fl_plan *p, const PrState &hs, int lanes, fl_status status, fl_summary *out) {
     fill_sizes(p, out);
@@ -496,14 +519,19 @@ uint64_t shape_key(const fl_plan *p) {
 }
 
 // Grid, buffers and arguments of the power iteration of plan p in layout
-// `lanes` (FL_ROWS_SLOTS or CSR lanes per row).
+// `lanes` (FL_ROWS_SLOTS, FL_ROWS_SLOTS_WIN or CSR lanes per row).
 fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrArgs &a, int &grid,
                      int &init_grid) {
-    const int kind = lanes == FL_ROWS_SLOTS ? fl::kSweepSlots : fl::kSweepCsr;
+    const int kind = is_slot_layout(lanes) ? fl::kSweepSlots : fl::kSweepCsr;
     a = PrArgs{};
     a.kind = kind;
     a.adjacent = p->adjacent;
     a.x_bytes = kind == fl::kSweepSlots ? x_bytes_of(p) : 0;
+    if (lanes == FL_ROWS_SLOTS_WIN) {
+        a.win_t = p->sl.win_t;
+        a.win_lo = p->sl.win_lo;
+        a.win_hi = p->sl.win_hi;
+    }
     // persistent grid: every workgroup resident at once (occupancy query), a
     // multiple of the XCD count so each XCD gets the same number of them
     int per_cu = 0;
@@ -618,7 +646,7 @@ void member_release(fl_ctx *ctx, fl_batch::Member &m) {
 fl_status member_alloc(fl_ctx *ctx, const fl_plan *p, fl_batch::Member &m) {
     for (int j = 0; j < 2; ++j) {
         m.y[j] = pool_alloc<float>(ctx, p->n);
-        m.x[j] = pool_alloc<float>(ctx, p->n_raw);
+        m.x[j] = pool_alloc<float>(ctx, (p->n_raw + 3) / 4 * 4);
     }
     m.partials = pool_alloc<double>(ctx, 3 * (int64_t)tiles_of(p));
     m.state = pool_alloc<PrState>(ctx, 1);
@@ -930,13 +958,14 @@ fl_status fl_tune(fl_ctx *ctx, fl_plan *p, const fl_params *prm, int32_t sweeps,
     r.max_iter = sweeps + 1;
     FL_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    const int layouts[8] = {FL_ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64};
+    const int layouts[FL_TUNE_LAYOUTS] = {FL_ROWS_SLOTS_WIN, FL_ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64};
     double best_us = 0.0;
     *best = 0;
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < FL_TUNE_LAYOUTS; ++j) {
         if (us_per_sweep) us_per_sweep[j] = -1.0;
         const int lanes = layouts[j];
         if (lanes == FL_ROWS_SLOTS && p->sl.words == 0) continue;
+        if (lanes == FL_ROWS_SLOTS_WIN && !window_ok(p)) continue;
         PrArgs a;
         int grid = 0, init_grid = 0;
         st = prepare_pr(ctx, p, r, lanes, a, grid, init_grid);
@@ -1040,7 +1069,7 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     Resolved r;
     fl_status st = resolve_params(ctx, p, prm, r);
     if (st != FL_OK) return st;
-    if (r.lanes != FL_ROWS_SLOTS) return fail(ctx, FL_EINVAL, "batches run the slot sweep only");
+    if (!is_slot_layout(r.lanes)) return fail(ctx, FL_EINVAL, "batches run the slot sweep only");
     FL_HIP(hipSetDevice(ctx->device));
     int64_t tiles = 0;
     for (const auto &m : b->members) tiles += tiles_of(m.plan);
@@ -1081,6 +1110,11 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     bm.k_slots = p->sl.k;
     bm.words = p->sl.words;
     bm.x_bytes = x_bytes_of(p);
+    if (window_ok(p)) {   // the batched sweep always reads window slots from LDS
+        bm.win_t = p->sl.win_t;
+        bm.win_lo = p->sl.win_lo;
+        bm.win_hi = p->sl.win_hi;
+    }
     bm.n_tiles = tiles_of(p);
     bm.max_iter = r.max_iter;
     b->members.push_back(m);
@@ -1246,7 +1280,8 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         for (int32_t j = 0; j < n_fin; ++j) {
             fl_batch::Member &m = b->members[fin_index[j]];
             const PrState &hs = b->h_states[j];
-            fill_summary(m.plan, hs, FL_ROWS_SLOTS, hs.done == 1 ? FL_OK : FL_ENOCONV, &m.sum);
+            fill_summary(m.plan, hs, window_ok(m.plan) ? FL_ROWS_SLOTS_WIN : FL_ROWS_SLOTS,
+                         hs.done == 1 ? FL_OK : FL_ENOCONV, &m.sum);
             m.phase = 2;
         }
     }
@@ -1359,7 +1394,7 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
             out[j].status = FL_EINVAL;
             continue;
         }
-        if (p->sl.words > 0 && x_bytes_of(p) > 0 && r.lanes == FL_ROWS_SLOTS) {
+        if (p->sl.words > 0 && x_bytes_of(p) > 0 && is_slot_layout(r.lanes)) {
             st = fl_batch_add(ctx, b, p, &prm[j], d_pagerank[j], d_minima[j], j);
             if (st == FL_OK) {
                 ++in_batch;

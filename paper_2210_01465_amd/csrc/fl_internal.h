@@ -17,6 +17,8 @@ constexpr int kXcds = 8;                          // MI355X: 8 XCDs, workgroups 
 constexpr int kBatch = 16;                        // candidate slots whose loads are issued together
 constexpr int kMaxFinishGrid = 1024;              // workgroups of the batched step kernel (grid-stride)
 constexpr int kFinishBlock = 1024;                // threads of a step kernel workgroup (1 mod 3)
+constexpr int kWinCap = 1024;                     // floats of x a wave stages in LDS (windowed slot sweep)
+constexpr int kWinMaxOff = 256;                   // largest |slot offset| served from the window
 
 // Mixed-radix description of a search space X = S_1 x ... x S_n, parameter 0
 // most significant: stride[i] = prod_{j>i} radix[j].  Digits are peeled off
@@ -45,6 +47,7 @@ struct SpaceDesc {
 struct SlotTable {
     int32_t k;
     int32_t words;
+    int32_t win_t, win_lo, win_hi;  // slots [win_lo, win_hi) have |off| <= win_t <= kWinMaxOff (0: none)
     int32_t off[kMaxSlots];
     int16_t delta[kMaxSlots];
     uint8_t dim[kMaxSlots];
@@ -101,7 +104,9 @@ struct PrArgs {
     double tol;
     int32_t max_iter;
     int32_t adjacent;
-    int32_t x_bytes;        // bytes of each x buffer when < 2^31 (slot sweep uses buffer loads), else 0
+    int32_t x_bytes;        // bytes of each x buffer (n_raw rounded up to 4 floats) when < 2^31, else 0
+    int32_t win_t;          // windowed slot sweep: slots [win_lo, win_hi) have |off| <= win_t; 0 = off
+    int32_t win_lo, win_hi;
 };
 
 // One member of a batch: an FFG with its own power iteration, run together
@@ -121,7 +126,8 @@ struct BatchMember {
     double *out_pagerank;      // caller's outputs
     int32_t *out_minima;
     double d, tol, threshold;
-    int32_t n, m, k_slots, words, x_bytes, n_tiles, max_iter, pad;
+    int32_t n, m, k_slots, words, x_bytes, n_tiles, max_iter;
+    int32_t win_t, win_lo, win_hi;   // window slots (see PrArgs)
 };
 
 struct TileRef {

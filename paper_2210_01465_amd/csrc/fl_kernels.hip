@@ -788,9 +788,18 @@ struct SweepTile {
     double *partials;
     double s, c, sd;
     int32_t n, k_slots, x_bytes;
+    int32_t win_t, win_lo, win_hi;  // window slots [win_lo, win_hi): |off| <= win_t (0: none)
 };
 
-template <int W, bool BUF>
+// With WIN, each wave first copies x[base, base + len) into its own LDS row,
+// where [base, base + len) covers its nodes' raw indices widened by win_t on
+// both sides (base rounded down to a multiple of 4, len <= kWinCap), using a
+// few dense 16-byte loads; the window slots then read x from LDS instead of
+// gathering it through the texture path.  A wave whose nodes span too wide a
+// raw range (it straddles a hole of excluded configurations) gathers every
+// slot as without WIN.  Values and their order of addition do not change, so
+// the result is the same bit for bit.
+template <int W, bool BUF, bool WIN>
 __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
     const __amdgpu_buffer_rsrc_t xr =
         __builtin_amdgcn_make_buffer_rsrc((void *)q.x_in, (short)0, q.x_bytes, 0x00020000);
@@ -812,6 +821,36 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
     const int32_t first = __builtin_amdgcn_readfirstlane(tile * kBlock + (int32_t)(threadIdx.x & ~63u));
     const_ptr<uint64_t> pw = q.presence + (int64_t)(first >> 6) * W;
     const bool live = first < q.n;
+    bool use_win = false;
+    int32_t base = 0;
+    float *row = nullptr;
+    if constexpr (WIN) {
+        __shared__ float win[kBlock / 64][kWinCap];
+        row = win[threadIdx.x >> 6];
+        if (live && q.win_t > 0) {
+            const int32_t last = min(63, q.n - 1 - first);   // highest lane holding a node
+            const int32_t lo = __builtin_amdgcn_readfirstlane(i);
+            const int32_t hi = __builtin_amdgcn_readlane(i, last);
+            base = ((lo - q.win_t) >> 2) << 2;                // floor to a multiple of 4
+            const int32_t len = hi + q.win_t + 1 - base;
+            use_win = len <= kWinCap;
+            if (use_win) {
+                // negative positions wrap to offsets >= 2^31 and load 0; the
+                // x buffers hold whole 16-byte groups up to x_bytes
+                const int32_t n4 = (len + 3) >> 2;
+                for (int32_t j = (int32_t)(threadIdx.x & 63); j < n4; j += 64) {
+                    const uint32_t byte = 4u * (uint32_t)(base + 4 * j);
+                    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                    const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(xr, byte, 0, 0);
+                    *reinterpret_cast<u32x4 *>(row + 4 * j) = t;
+                }
+                // the row is read by other lanes of this wave only
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+    }
     float acc = 0.0f;
 #pragma unroll
     for (int b = 0; b < 2 * W; ++b) {
@@ -829,7 +868,14 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
         for (int u = 0; u < 32; ++u) {
             val[u] = 0.0f;
             if ((any >> u) & 1u) {
-                if (BUF) {
+                const int sl = 32 * b + u;
+                if (WIN && use_win && sl >= q.win_lo && sl < q.win_hi) {
+                    // in [0, len) for every lane whose bit is set
+                    const bool on = (bits >> u) & 1u;
+                    const int32_t idx = on ? i + q.off[sl] - base : 0;
+                    const float xv = row[idx];
+                    val[u] = on ? xv : 0.0f;
+                } else if (BUF) {
                     // out-of-range offset (the load returns 0) where this lane's bit is clear
                     const uint32_t byte = ((nbits << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)q.off[32 * b + u]);
                     val[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, byte, 0, 0));
@@ -854,7 +900,7 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
     write_partials(q.partials, tile, ps, pr, pk);
 }
 
-template <int W, bool BUF>
+template <int W, bool BUF, bool WIN>
 __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     const PrState *st = a.st;
     if (st->done) return;
@@ -874,8 +920,11 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     q.n = a.n;
     q.k_slots = a.k_slots;
     q.x_bytes = a.x_bytes;
+    q.win_t = a.win_t;
+    q.win_lo = a.win_lo;
+    q.win_hi = a.win_hi;
     const TileWalk w((a.n + kBlock - 1) / kBlock);
-    for (int32_t t = w.first; t < w.end; t += w.step) sweep_tile<W, BUF>(q, t);
+    for (int32_t t = w.first; t < w.end; t += w.step) sweep_tile<W, BUF, WIN>(q, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -915,7 +964,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchMember *__res
         q.n = m->n;
         q.k_slots = m->k_slots;
         q.x_bytes = m->x_bytes;
-        sweep_tile<W, BUF>(q, tile);
+        q.win_t = m->win_t;
+        q.win_lo = m->win_lo;
+        q.win_hi = m->win_hi;
+        sweep_tile<W, BUF, BUF>(q, tile);
     }
 }
 
@@ -1021,7 +1073,8 @@ size_t digit_lds(const SpaceDesc &sp) { return sizeof(uint32_t) * kBlock * (size
 // when the x vector's byte size leaves room for the out-of-range offset.
 template <int W>
 const void *slot_sweep_fn(const PrArgs &a) {
-    return a.x_bytes > 0 ? (const void *)k_pr_iter_slots<W, true> : (const void *)k_pr_iter_slots<W, false>;
+    if (a.x_bytes == 0) return (const void *)k_pr_iter_slots<W, false, false>;
+    return a.win_t > 0 ? (const void *)k_pr_iter_slots<W, true, true> : (const void *)k_pr_iter_slots<W, true, false>;
 }
 
 const void *slot_sweep_kernel(const PrArgs &a, int words) {

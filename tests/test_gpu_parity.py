@@ -101,21 +101,63 @@ def test_fuzz_parity(ctx, seed):
         check_parity(ctx, s, nb, damping=(0.5, 0.85, 0.9)[seed % 3], p=(0.0, 0.05, 0.15)[seed % 3])
 
 
-ROWS_SLOTS = -1
+ROWS_SLOTS, ROWS_SLOTS_WIN = -1, -2
 
 
-@pytest.mark.parametrize("lanes", [ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lanes", [ROWS_SLOTS_WIN, ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64])
 def test_every_row_mapping(ctx, lanes):
-    """Every sweep layout: the slot sweep and the CSR sweep with 1..64 lanes."""
+    """Every sweep layout: the windowed and the plain slot sweep and the CSR
+    sweep with 1..64 lanes."""
     for nb in ("hamming", "adjacent"):
         check_parity(ctx, synth.tiny(3), nb, row_mapping=lanes)
         check_parity(ctx, synth.fuzz_space(5, max_params=6, max_radix=8), nb, row_mapping=lanes)
     check_parity(ctx, synth.mid(), "hamming", row_mapping=lanes)
 
 
+def test_slot_layouts_agree_bit_for_bit(ctx):
+    """The windowed slot sweep reads the same x values as the plain one and
+    adds them in the same order: identical ranks, also against the one-lane
+    CSR sweep.  The spaces cover waves whose window starts below raw index 0
+    or ends in the last 16-byte group, waves that straddle holes of excluded
+    configurations (no window), a last parameter with offsets up to the
+    window reach and beyond, and both neighbourhoods."""
+    import torch
+    from paper_2210_01465_amd import api
+    rng = np.random.default_rng(17)
+    spaces = [synth.tiny(7), synth.mid()]
+    spaces += [s for s in (synth.fuzz_space(j, max_params=6, max_radix=9, p_exclude=0.4) for j in range(30, 40))
+               if s.n_valid > 0 and s.n_raw <= 300_000]
+    for radix in ((3, 5, 2, 120), (60, 64), (120, 2), (2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3)):
+        n_raw = int(np.prod(radix))
+        f = np.where(rng.random(n_raw) < 0.3, np.nan, rng.lognormal(0.0, 0.5, n_raw))
+        spaces.append(_space(f"win{radix}", radix, f))
+    for s in spaces:
+        for nb in ("hamming", "adjacent"):
+            say(f"layouts agree {s.name} radix={s.radix} nb={nb}")
+            fit = torch.from_numpy(np.ascontiguousarray(s.fitness_raw)).cuda()
+            plan = api.plan_create(ctx, s.radix, fit, nb)
+            try:
+                if plan.sizes["mask_words"] == 0:
+                    continue
+                outs = {}
+                for lay in (ROWS_SLOTS_WIN, ROWS_SLOTS, 1):
+                    try:
+                        pr, _, info = api.execute(plan, 0.85, 0.05, row_mapping=lay)
+                    except api.FLError:
+                        assert lay == ROWS_SLOTS_WIN   # window unavailable: must be refused, not wrong
+                        continue
+                    outs[lay] = (pr.cpu().numpy(), info["iterations"])
+                ref = outs[ROWS_SLOTS]
+                for lay, (pr, it) in outs.items():
+                    assert it == ref[1] and np.array_equal(pr, ref[0]), (s.name, nb, lay)
+            finally:
+                plan.close()
+
+
 def test_mask_widths(ctx):
-    """K = 64 and 65 (one / two mask words), 128 (full) and 129 (generic
-    kernels, CSR sweep only)."""
+    """Candidate slots K' = 2 sum(r - 1): 128 (three record words), 130,
+    256 (five words, the most a record holds) and 258 (generic kernels, CSR
+    sweep only), for Hamming; adjacent stays small."""
     rng = np.random.default_rng(5)
     for radix in ((33, 33), (34, 33), (65, 65), (65, 66), (129,), (130,)):
         n_raw = int(np.prod(radix))
@@ -216,7 +258,7 @@ def test_error_paths(ctx):
     plan = api.plan_create(ctx, (8,), ones)
     try:
         for kw in ({"damping": 0.0}, {"damping": 1.0}, {"damping": float("nan")},
-                   {"p": -0.1}, {"p": float("inf")}, {"row_mapping": 3}, {"row_mapping": -2},
+                   {"p": -0.1}, {"p": float("inf")}, {"row_mapping": 3}, {"row_mapping": -3},
                    {"max_iter": -1}):
             args = {"damping": 0.85, "p": 0.05}
             args.update(kw)
@@ -227,9 +269,10 @@ def test_error_paths(ctx):
         plan.close()
     wide = api.plan_create(ctx, (200,), torch.arange(1, 201, dtype=torch.float32, device="cuda"))
     try:
-        with pytest.raises(api.FLError) as e:
-            api.execute(wide, row_mapping=ROWS_SLOTS)
-        assert e.value.status == _abi.FL_EINVAL
+        for lay in (ROWS_SLOTS, ROWS_SLOTS_WIN):
+            with pytest.raises(api.FLError) as e:
+                api.execute(wide, row_mapping=lay)
+            assert e.value.status == _abi.FL_EINVAL
     finally:
         wide.close()
 
