@@ -225,6 +225,29 @@ fl::SlotTable make_slots(const SpaceDesc &sp, bool adjacent) {
         }
     }
     if (t.win_lo < 0) t.win_lo = t.win_hi = t.win_t = 0;
+    // runs of each parameter's slots (checked: a space where they were not
+    // contiguous would take the generic kernels)
+    for (int k = 0; k < sp.n; ++k) {
+        const int reach = adjacent ? std::min(1, sp.radix[k] - 1) : sp.radix[k] - 1;
+        t.blk_len[k] = (int16_t)reach;
+        t.blk_neg[k] = t.blk_pos[k] = 0;
+        if (reach <= 0) continue;
+        int neg = -1, pos = -1;
+        for (int s = 0; s < t.k; ++s) {
+            if (t.dim[s] != k) continue;
+            if (t.delta[s] == -reach) neg = s;
+            if (t.delta[s] == 1) pos = s;
+        }
+        bool ok = neg >= 0 && pos >= 0;
+        for (int d = 0; ok && d < reach; ++d)
+            ok = t.dim[neg + d] == k && t.delta[neg + d] == d - reach && t.dim[pos + d] == k && t.delta[pos + d] == d + 1;
+        if (!ok) {
+            t.words = 0;
+            return t;
+        }
+        t.blk_neg[k] = (int16_t)neg;
+        t.blk_pos[k] = (int16_t)pos;
+    }
     return t;
 }
 
@@ -393,9 +416,9 @@ void build_fill(fl_ctx *ctx, Build &b) {
     p->col_idx = pool_alloc<int32_t>(ctx, e);
     if (!p->col_idx) return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
-    hipError_t he = fl::launch_fill(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, b.remap, p->rec, (int32_t)p->n,
-                                    (int32_t)e, b.in_deg, p->out_deg, b.tile_eoff, b.tile_moff, p->row_ptr,
-                                    p->col_idx, p->minima, s);
+    hipError_t he = fl::launch_fill(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, b.remap, p->rec, p->presence,
+                                    (int32_t)p->n, (int32_t)e, b.in_deg, p->out_deg, b.tile_eoff, b.tile_moff,
+                                    p->row_ptr, p->col_idx, p->minima, s);
     if (he == hipSuccess) he = hipEventRecord(p->ev[1], s);
     if (he != hipSuccess) build_fail(b, FL_EHIP, "CSR fill: %s", hipGetErrorString(he));
 }

@@ -18,6 +18,7 @@ constexpr int kBatch = 16;                        // candidate slots whose loads
 constexpr int kMaxFinishGrid = 1024;              // workgroups of the batched step kernel (grid-stride)
 constexpr int kFinishBlock = 1024;                // threads of a step kernel workgroup (1 mod 3)
 constexpr int kWinCap = 1024;                     // floats of x a wave stages in LDS (windowed slot sweep)
+constexpr int kFillStage = 6144;                  // col_idx entries of a tile assembled in LDS by the fill
 constexpr int kWinMaxOff = 256;                   // largest |slot offset| served from the window
 
 // Mixed-radix description of a search space X = S_1 x ... x S_n, parameter 0
@@ -51,6 +52,11 @@ struct SlotTable {
     int32_t off[kMaxSlots];
     int16_t delta[kMaxSlots];
     uint8_t dim[kMaxSlots];
+    // Parameter k's slots form two contiguous runs in slot order (every
+    // offset of a less significant parameter is below the stride of a more
+    // significant one): deltas -len..-1 at [neg[k], neg[k] + len[k]) and
+    // +1..+len at [pos[k], pos[k] + len[k]).
+    int16_t blk_neg[kMaxParams], blk_pos[kMaxParams], blk_len[kMaxParams];
 };
 
 // Sizes produced on the device by the build scans, copied to the host once.
@@ -146,9 +152,9 @@ hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent,
                          int64_t *tile_eoff, int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream);
 hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                        const int32_t *valid_raw, const int32_t *remap, const uint64_t *rec,
-                       int32_t n, int32_t n_edges, const int32_t *in_deg, const int32_t *out_deg,
-                       const int64_t *tile_eoff, const int32_t *tile_moff, int32_t *row_ptr,
-                       int32_t *col_idx, int32_t *minima, hipStream_t stream);
+                       const uint64_t *presence, int32_t n, int32_t n_edges, const int32_t *in_deg,
+                       const int32_t *out_deg, const int64_t *tile_eoff, const int32_t *tile_moff,
+                       int32_t *row_ptr, int32_t *col_idx, int32_t *minima, hipStream_t stream);
 hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream);
 hipError_t launch_pr_iter(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
                           int grid, hipStream_t stream);

@@ -29,6 +29,17 @@ __device__ __forceinline__ bool valid_fitness(float f) { return f > 0.0f && f < 
 // fitness <= 0 or -inf (NaN and +inf mark excluded configurations)
 __device__ __forceinline__ bool bad_fitness(float f) { return !(f != f) && !(f > 0.0f); }
 
+// Pointer into the constant address space: memory no kernel of the launch
+// writes.  Uniform loads through it may go through the scalar unit even after
+// the kernel has stored elsewhere, which keeps the slot offsets and presence
+// words in SGPRs instead of a VGPR per value.
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ const_ptr<T> to_const(const T *p) {
+    return (const_ptr<T>)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll
@@ -124,18 +135,7 @@ __device__ T scan_tiles(const T *in, T *out, int n_tiles) {
 }
 
 // ---------------------------------------------------------------------------
-// Mixed-radix digits and candidate slots.
-
-// Digits of raw index i, least significant first, into the calling thread's
-// column of the workgroup's digit table: dig[k * kBlock] = x_k.
-__device__ __forceinline__ void store_digits(const SpaceDesc &sp, uint32_t i, uint32_t *dig) {
-    uint32_t q = i;
-    for (int k = sp.n - 1; k >= 0; --k) {
-        const uint32_t qn = (uint32_t)(((uint64_t)q * sp.magic[k]) >> sp.shift[k]);
-        dig[k * kBlock] = q - qn * (uint32_t)sp.radix[k];
-        q = qn;
-    }
-}
+// Node records and candidate slots.
 
 // Node records: W 64-bit words; in-edge bits first, then out_deg in bits
 // 24..31 and the raw index in bits 32..63 of the last word.
@@ -289,9 +289,32 @@ __global__ __launch_bounds__(kBlock) void k_compact_write(const float *__restric
 // strictly lower fitness (edges out of v).  The slot kernel also records the
 // in-edges as a bit mask over the node's candidate slots.
 
+// Bits [lo, hi) of a 64-bit word, 0 <= lo, hi <= 64.
+__device__ __forceinline__ uint64_t range_bits(int32_t lo, int32_t hi) {
+    return hi > lo ? ((~0ull >> (64 - hi)) & (~0ull << lo)) : 0ull;
+}
+
+// Set bits [lo, hi) of a W-word mask; the range lies inside slot run
+// [run_lo, run_hi), whose words (uniform) bound the words touched.
 template <int W>
+__device__ __forceinline__ void set_bits(uint64_t (&m)[W], int32_t lo, int32_t hi, int32_t run_lo, int32_t run_hi) {
+    const int32_t w0 = run_lo >> 6, w1 = (run_hi - 1) >> 6;
+#pragma unroll
+    for (int q = 0; q < W; ++q)
+        if (q >= w0 && q <= w1)
+            m[q] |= range_bits(min(max(lo - 64 * q, 0), 64), min(max(hi - 64 * q, 0), 64));
+}
+
+// Slot version.  A node's existing slots for parameter k are the last
+// min(x_k, len) of the parameter's negative run and the first
+// min(r_k - 1 - x_k, len) of its positive run, so the existence mask takes a
+// few shifts per parameter.  The fitness gathers then run like the sweep's:
+// a slot no lane of the wave has is skipped with a scalar branch, and lanes
+// without it get the out-of-range buffer offset (the load returns 0, which
+// no comparison below counts).
+template <int W, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable sl,
-                                                         const float *__restrict__ fit,
+                                                         const float *__restrict__ fit, int32_t fit_bytes,
                                                          const int32_t *__restrict__ valid_raw, int32_t n,
                                                          int32_t *__restrict__ in_deg,
                                                          int32_t *__restrict__ out_deg,
@@ -299,40 +322,63 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
                                                          uint64_t *__restrict__ presence,
                                                          int64_t *__restrict__ tile_e,
                                                          int32_t *__restrict__ tile_m) {
-    extern __shared__ uint32_t s_dig[];
-    uint32_t *dig = s_dig + threadIdx.x;
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-    int32_t din = 0, dout = 0;
-    uint64_t m[W];
+    const bool active = v < n;
+    const uint32_t i = active ? (uint32_t)valid_raw[v] : 0u;
+    const float fv = active ? fit[i] : 0.0f;
+    uint64_t ex[W], m[W];
 #pragma unroll
-    for (int q = 0; q < W; ++q) m[q] = 0ull;
-    if (v < n) {
-        const uint32_t i = (uint32_t)valid_raw[v];
-        const float fv = fit[i];
-        store_digits(sp, i, dig);
+    for (int q = 0; q < W; ++q) ex[q] = m[q] = 0ull;
+    if (active) {
+        uint32_t qv = i;
+        for (int k = sp.n - 1; k >= 0; --k) {   // digits, least significant first
+            const uint32_t qn = (uint32_t)(((uint64_t)qv * sp.magic[k]) >> sp.shift[k]);
+            const int32_t x = (int32_t)(qv - qn * (uint32_t)sp.radix[k]);
+            qv = qn;
+            const int32_t len = sl.blk_len[k];
+            if (len <= 0) continue;
+            const int32_t nb = sl.blk_neg[k], pb = sl.blk_pos[k];
+            const int32_t a = min(x, len), bcnt = min(sp.radix[k] - 1 - x, len);
+            set_bits<W>(ex, nb + len - a, nb + len, nb, nb + len);
+            set_bits<W>(ex, pb, pb + bcnt, pb, pb + len);
+        }
+    }
+    const __amdgpu_buffer_rsrc_t fr = __builtin_amdgcn_make_buffer_rsrc((void *)fit, (short)0, fit_bytes, 0x00020000);
+    const uint32_t i4 = 4u * i;
+    int32_t dout = 0;
 #pragma unroll
-        for (int q = 0; q < W; ++q) {
-            for (int s0 = q * 64; s0 < q * 64 + 64 && s0 < sl.k; s0 += kBatch) {
-                float fc[kBatch];
+    for (int b = 0; b < 2 * W; ++b) {
+        if (32 * b >= sl.k) break;
+        const uint32_t exb = (b & 1) ? (uint32_t)(ex[b >> 1] >> 32) : (uint32_t)ex[b >> 1];
+        const uint32_t any = __builtin_amdgcn_readfirstlane(wave_or(exb));
+        const uint32_t nex = ~exb;
+        float fc[32];
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const int s = s0 + u;
-                    fc[u] = NAN;
-                    if (s < sl.k) {
-                        const int k = sl.dim[s];
-                        const int32_t a = (int32_t)dig[k * kBlock] + sl.delta[s];
-                        if (a >= 0 && a < sp.radix[k]) fc[u] = fit[(int32_t)i + sl.off[s]];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const bool in = (fc[u] > fv) & (fc[u] < INFINITY);
-                    din += in;
-                    dout += (fc[u] < fv);
-                    if (in) m[q] |= 1ull << ((s0 + u) & 63);
+        for (int u = 0; u < 32; ++u) {
+            fc[u] = 0.0f;
+            if ((any >> u) & 1u) {
+                if (BUF) {
+                    const uint32_t byte = ((nex << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)sl.off[32 * b + u]);
+                    fc[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(fr, byte, 0, 0));
+                } else {
+                    fc[u] = ((exb >> u) & 1u) ? fit[(int32_t)i + sl.off[32 * b + u]] : 0.0f;
                 }
             }
         }
+        uint32_t inb = 0u;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            // a neighbour that is worse (in-edge; +inf marks an excluded one),
+            // or better (out-edge; 0 marks a slot the node does not have)
+            if ((fc[u] > fv) & (fc[u] < INFINITY)) inb |= 1u << u;
+            dout += (fc[u] < fv) & (fc[u] > 0.0f);
+        }
+        m[b >> 1] |= (b & 1) ? ((uint64_t)inb << 32) : (uint64_t)inb;
+    }
+    int32_t din = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) din += __popcll(m[q]);
+    if (active) {
         in_deg[v] = din;
         out_deg[v] = dout;
         const uint64_t tail = ((uint64_t)i << 32) | ((uint64_t)(uint32_t)dout << 24);
@@ -441,13 +487,17 @@ __device__ __forceinline__ void fill_rows(int32_t v, int32_t n, int32_t n_edges,
 }
 
 // Slot version: the in-edges come from the node records of the degree pass.
-// Slots are sorted by raw-index offset, so the position of an in-edge in its
-// row is the number of in-edge bits below its slot.  Every lane walks the
-// slots in the same order, so the remap gathers of one slot are
-// near-contiguous across the wave.
-template <int W>
+// Slots are sorted by raw-index offset, so a row's in-edges come out in
+// ascending source id when every lane walks its set bits in slot order.  The
+// remap gathers of a slot skip slots no lane of the wave needs (presence
+// word) and use the out-of-range buffer offset for lanes whose bit is clear,
+// as in the sweep.  The tile's rows are one contiguous range of col_idx; when
+// it fits, it is assembled in LDS and written out with coalesced stores
+// instead of one scattered 4-byte store per edge.
+template <int W, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_fill_slots(SlotTable sl, const int32_t *__restrict__ remap,
-                                                       const uint64_t *__restrict__ rec, int32_t n,
+                                                       int32_t remap_bytes, const uint64_t *__restrict__ rec,
+                                                       const uint64_t *__restrict__ presence, int32_t n,
                                                        int32_t n_edges, const int32_t *__restrict__ in_deg,
                                                        const int32_t *__restrict__ out_deg,
                                                        const int64_t *__restrict__ tile_eoff,
@@ -455,34 +505,67 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(SlotTable sl, const int32
                                                        int32_t *__restrict__ row_ptr,
                                                        int32_t *__restrict__ col_idx,
                                                        int32_t *__restrict__ minima) {
+    __shared__ int32_t stage[kFillStage];
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-    const int32_t din = v < n ? in_deg[v] : 0;
-    const int32_t sink = (v < n && out_deg[v] == 0) ? 1 : 0;
+    const bool active = v < n;
+    const int32_t din = active ? in_deg[v] : 0;
+    const int32_t sink = (active && out_deg[v] == 0) ? 1 : 0;
     int32_t e_off;
     fill_rows(v, n, n_edges, din, sink, tile_eoff, tile_moff, row_ptr, minima, e_off);
-    if (v >= n || din == 0) return;
-    const Record<W> r = load_record<W>(rec, v);
+    const int64_t e_begin = tile_eoff[blockIdx.x];
+    const int64_t e_end = blockIdx.x + 1 < gridDim.x ? tile_eoff[blockIdx.x + 1] : (int64_t)n_edges;
+    const int32_t count = (int32_t)(e_end - e_begin);
+    const bool staged = count <= kFillStage;   // uniform over the workgroup
+    const __amdgpu_buffer_rsrc_t rr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)remap, (short)0, remap_bytes, 0x00020000);
+    Record<W> r;
+    if (active) {
+        r = load_record<W>(rec, v);
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j) r.w[j] = 0ull;
+    }
     const int32_t i = r.raw();
+    const uint32_t i4 = 4u * (uint32_t)i;
+    const int32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * kBlock + (int32_t)(threadIdx.x & ~63u));
+    const_ptr<uint64_t> pw = to_const(presence) + (int64_t)(first >> 6) * W;
+    const bool live = first < n;
+    int32_t pos = e_off;
     const int32_t end = e_off + din;
 #pragma unroll
     for (int b = 0; b < 2 * W; ++b) {
-        if (32 * b >= sl.k) break;
+        if (32 * b >= sl.k || !live) break;
+        const uint64_t pq = pw[b >> 1];
+        const uint32_t any = (b & 1) ? (uint32_t)(pq >> 32) : (uint32_t)pq;
         const uint32_t bits = r.word32(b) & batch_mask(b, sl.k);
-        if (bits == 0u) continue;
+        const uint32_t nbits = ~bits;
         int32_t src[32];
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
-            const int s = 32 * b + u;
-            src[u] = ((bits >> u) & 1u) ? remap[i + sl.off[s]] : -1;
+            src[u] = 0;
+            if ((any >> u) & 1u) {
+                if (BUF) {
+                    const uint32_t byte = ((nbits << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)sl.off[32 * b + u]);
+                    src[u] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rr, byte, 0, 0);
+                } else {
+                    src[u] = ((bits >> u) & 1u) ? remap[i + sl.off[32 * b + u]] : 0;
+                }
+            }
         }
-        int32_t pos = e_off + bits_below<W>(r, 32 * b);
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
-            if ((bits >> u) & 1u) {
-                if (pos < end) col_idx[pos] = src[u];
+            if (((bits >> u) & 1u) && pos < end) {
+                if (staged)
+                    stage[pos - (int32_t)e_begin] = src[u];
+                else
+                    col_idx[pos] = src[u];
                 ++pos;
             }
         }
+    }
+    if (staged) {
+        __syncthreads();
+        for (int32_t j = threadIdx.x; j < count; j += kBlock) col_idx[e_begin + j] = stage[j];
     }
 }
 
@@ -758,16 +841,6 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
     write_partials(a.partials, blockIdx.x, ps, pr, pk);
 }
 
-// Pointer into the constant address space: memory no kernel of the launch
-// writes.  Uniform loads through it may go through the scalar unit even after
-// the kernel has stored elsewhere, which keeps the slot offsets and presence
-// words in SGPRs instead of a VGPR per value.
-template <typename T>
-using const_ptr = const __attribute__((address_space(4))) T *;
-template <typename T>
-__device__ __forceinline__ const_ptr<T> to_const(const T *p) {
-    return (const_ptr<T>)p;
-}
 
 // Slot sweep of one tile of kBlock nodes: one node per lane, 64 consecutive
 // nodes per wave.  For every candidate slot whose in-edge bit is set, gather
@@ -1067,7 +1140,6 @@ __global__ __launch_bounds__(kBlock) void k_score(const double *__restrict__ pag
     }
 }
 
-size_t digit_lds(const SpaceDesc &sp) { return sizeof(uint32_t) * kBlock * (size_t)sp.n; }
 
 // The slot sweep kernel for W record words, with out-of-range buffer loads
 // when the x vector's byte size leaves room for the out-of-range offset.
@@ -1120,18 +1192,39 @@ hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, fl
     return hipGetLastError();
 }
 
+template <int W>
+static const void *degree_slots_kernel(bool buf) {
+    return buf ? (const void *)k_degree_slots<W, true> : (const void *)k_degree_slots<W, false>;
+}
+
 hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                          const int32_t *valid_raw, int32_t n, int32_t *in_deg, int32_t *out_deg,
                          uint64_t *rec, uint64_t *presence, int64_t *tile_e, int32_t *tile_m,
                          int64_t *tile_eoff, int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream) {
     const int32_t tiles = (n + kBlock - 1) / kBlock;
-    const size_t lds = digit_lds(sp);
+    if (sl.words > 0) {
+        // buffer loads of the fitness need 4 n_raw < 2^31 (room for the out-of-range bit)
+        const bool buf = 4 * (int64_t)sp.n_raw < (int64_t(1) << 31);
+        const int32_t fit_bytes = buf ? 4 * sp.n_raw : 0;
+        const void *fn = nullptr;
+        switch (sl.words) {
+            case 1: fn = degree_slots_kernel<1>(buf); break;
+            case 2: fn = degree_slots_kernel<2>(buf); break;
+            case 3: fn = degree_slots_kernel<3>(buf); break;
+            case 4: fn = degree_slots_kernel<4>(buf); break;
+            case 5: fn = degree_slots_kernel<5>(buf); break;
+            default: return hipErrorInvalidValue;
+        }
+        SpaceDesc d = sp;
+        SlotTable t = sl;
+        void *args[] = {(void *)&d, (void *)&t, (void *)&fit, (void *)&fit_bytes, (void *)&valid_raw, (void *)&n,
+                        (void *)&in_deg, (void *)&out_deg, (void *)&rec, (void *)&presence, (void *)&tile_e,
+                        (void *)&tile_m};
+        hipError_t e = hipLaunchKernel(fn, dim3(tiles), dim3(kBlock), args, 0, stream);
+        if (e != hipSuccess) return e;
+    }
     switch (sl.words) {
-        case 1: hipLaunchKernelGGL(k_degree_slots<1>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
-        case 2: hipLaunchKernelGGL(k_degree_slots<2>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
-        case 3: hipLaunchKernelGGL(k_degree_slots<3>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
-        case 4: hipLaunchKernelGGL(k_degree_slots<4>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
-        case 5: hipLaunchKernelGGL(k_degree_slots<5>, dim3(tiles), dim3(kBlock), lds, stream, sp, sl, fit, valid_raw, n, in_deg, out_deg, rec, presence, tile_e, tile_m); break;
+        case 1: case 2: case 3: case 4: case 5: break;
         case 0:
             if (adjacent)
                 hipLaunchKernelGGL(k_degree_generic<true>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
@@ -1147,18 +1240,37 @@ hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent,
     return hipGetLastError();
 }
 
+template <int W>
+static const void *fill_slots_kernel(bool buf) {
+    return buf ? (const void *)k_fill_slots<W, true> : (const void *)k_fill_slots<W, false>;
+}
+
 hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                        const int32_t *valid_raw, const int32_t *remap, const uint64_t *rec,
-                       int32_t n, int32_t n_edges, const int32_t *in_deg, const int32_t *out_deg,
-                       const int64_t *tile_eoff, const int32_t *tile_moff, int32_t *row_ptr,
-                       int32_t *col_idx, int32_t *minima, hipStream_t stream) {
+                       const uint64_t *presence, int32_t n, int32_t n_edges, const int32_t *in_deg,
+                       const int32_t *out_deg, const int64_t *tile_eoff, const int32_t *tile_moff,
+                       int32_t *row_ptr, int32_t *col_idx, int32_t *minima, hipStream_t stream) {
     const int32_t tiles = (n + kBlock - 1) / kBlock;
+    if (sl.words > 0) {
+        // buffer loads of remap need 4 n_raw < 2^31 (room for the out-of-range bit)
+        const bool buf = 4 * (int64_t)sp.n_raw < (int64_t(1) << 31);
+        const int32_t remap_bytes = buf ? 4 * sp.n_raw : 0;
+        const void *fn = nullptr;
+        switch (sl.words) {
+            case 1: fn = fill_slots_kernel<1>(buf); break;
+            case 2: fn = fill_slots_kernel<2>(buf); break;
+            case 3: fn = fill_slots_kernel<3>(buf); break;
+            case 4: fn = fill_slots_kernel<4>(buf); break;
+            case 5: fn = fill_slots_kernel<5>(buf); break;
+            default: return hipErrorInvalidValue;
+        }
+        SlotTable t = sl;
+        void *args[] = {(void *)&t, (void *)&remap, (void *)&remap_bytes, (void *)&rec, (void *)&presence,
+                        (void *)&n, (void *)&n_edges, (void *)&in_deg, (void *)&out_deg, (void *)&tile_eoff,
+                        (void *)&tile_moff, (void *)&row_ptr, (void *)&col_idx, (void *)&minima};
+        return hipLaunchKernel(fn, dim3(tiles), dim3(kBlock), args, 0, stream);
+    }
     switch (sl.words) {
-        case 1: hipLaunchKernelGGL(k_fill_slots<1>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
-        case 2: hipLaunchKernelGGL(k_fill_slots<2>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
-        case 3: hipLaunchKernelGGL(k_fill_slots<3>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
-        case 4: hipLaunchKernelGGL(k_fill_slots<4>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
-        case 5: hipLaunchKernelGGL(k_fill_slots<5>, dim3(tiles), dim3(kBlock), 0, stream, sl, remap, rec, n, n_edges, in_deg, out_deg, tile_eoff, tile_moff, row_ptr, col_idx, minima); break;
         case 0:
             if (adjacent)
                 hipLaunchKernelGGL(k_fill_generic<true>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw, remap,
