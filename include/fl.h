@@ -75,11 +75,11 @@ typedef struct {
  *   tol_l1    stop when ||r_{k+1} - r_k||_1 < tol_l1 (0 => 2e-7).
  *   max_iter  iteration cap (0 => 1000); reaching it gives FL_ENOCONV.
  *   row_mapping  layout of the PageRank sweep: 0 = automatic (the layout
- *             fl_tune cached for the plan's shape class, else
- *             FL_ROWS_SLOTS_WIN where available, else FL_ROWS_SLOTS, else
- *             CSR lanes from the mean in-degree); FL_ROWS_SLOTS = one node
- *             per lane over the in-edge slot records (needs at most 256
- *             candidate slots per node); FL_ROWS_SLOTS_WIN = the same with
+ *             fl_tune cached for the plan's shape class, else FL_ROWS_SLOTS
+ *             where available, else CSR lanes from the mean in-degree);
+ *             FL_ROWS_SLOTS = one node per lane over the in-edge slot
+ *             records (needs at most 256 candidate slots per node);
+ *             FL_ROWS_SLOTS_WIN = the same with
  *             the slots of offset |off| <= 256 read from a per-wave window
  *             of x staged in LDS (also needs fewer than 2^29 raw
  *             configurations); 1, 2, 4, 8, 16, 32 or 64 = that many lanes
@@ -238,8 +238,10 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *batch);
  * written when the member finishes; `tag` is returned by fl_batch_collect.
  * The member holds 8 n_raw + 8 N + 24 ceil(N/256) + 80 bytes of device
  * memory of its own while it is in the batch.
- * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0 or
- * FL_ROWS_SLOTS, or a space the slot sweep cannot take: use fl_execute),
+ * Members always run the slot sweep (FL_ROWS_SLOTS).
+ * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0,
+ * FL_ROWS_SLOTS or FL_ROWS_SLOTS_WIN, or a space the slot sweep cannot
+ * take: use fl_execute),
  * FL_ENOMEM, FL_EHIP. */
 fl_status fl_batch_add(fl_ctx *ctx, fl_batch *batch, fl_plan *plan, const fl_params *params,
                        double *d_pagerank, int32_t *d_minima, int64_t tag);

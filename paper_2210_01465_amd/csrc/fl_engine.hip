@@ -479,9 +479,7 @@ fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Re
     r.p = prm->p;
     r.tol = prm->tol_l1 > 0.0 ? prm->tol_l1 : 2e-7;
     r.max_iter = prm->max_iter > 0 ? prm->max_iter : 1000;
-    r.lanes = prm->row_mapping ? prm->row_mapping
-                               : (window_ok(p) ? FL_ROWS_SLOTS_WIN
-                                               : (p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e)));
+    r.lanes = prm->row_mapping ? prm->row_mapping : (p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e));
     return FL_OK;
 }
 
@@ -1133,11 +1131,7 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     bm.k_slots = p->sl.k;
     bm.words = p->sl.words;
     bm.x_bytes = x_bytes_of(p);
-    if (window_ok(p)) {   // the batched sweep always reads window slots from LDS
-        bm.win_t = p->sl.win_t;
-        bm.win_lo = p->sl.win_lo;
-        bm.win_hi = p->sl.win_hi;
-    }
+
     bm.n_tiles = tiles_of(p);
     bm.max_iter = r.max_iter;
     b->members.push_back(m);
@@ -1303,8 +1297,7 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         for (int32_t j = 0; j < n_fin; ++j) {
             fl_batch::Member &m = b->members[fin_index[j]];
             const PrState &hs = b->h_states[j];
-            fill_summary(m.plan, hs, window_ok(m.plan) ? FL_ROWS_SLOTS_WIN : FL_ROWS_SLOTS,
-                         hs.done == 1 ? FL_OK : FL_ENOCONV, &m.sum);
+            fill_summary(m.plan, hs, FL_ROWS_SLOTS, hs.done == 1 ? FL_OK : FL_ENOCONV, &m.sum);
             m.phase = 2;
         }
     }

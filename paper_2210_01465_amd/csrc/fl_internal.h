@@ -132,8 +132,7 @@ struct BatchMember {
     double *out_pagerank;      // caller's outputs
     int32_t *out_minima;
     double d, tol, threshold;
-    int32_t n, m, k_slots, words, x_bytes, n_tiles, max_iter;
-    int32_t win_t, win_lo, win_hi;   // window slots (see PrArgs)
+    int32_t n, m, k_slots, words, x_bytes, n_tiles, max_iter, pad;
 };
 
 struct TileRef {

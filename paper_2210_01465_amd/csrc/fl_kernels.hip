@@ -149,6 +149,15 @@ struct Record {
     __device__ __forceinline__ int32_t out_deg() const { return (int32_t)((w[W - 1] >> 24) & 0xffu); }
 };
 
+// Bits [lo, hi) of a 32-bit word, clipped to [0, 32).
+__device__ __forceinline__ uint32_t bit_range32(int32_t lo, int32_t hi) {
+    lo = max(lo, 0);
+    hi = min(hi, 32);
+    if (hi <= lo) return 0u;
+    const uint32_t upto = hi >= 32 ? ~0u : ((1u << hi) - 1u);
+    return upto & ~((1u << lo) - 1u);
+}
+
 // Slot bits of batch b (slots 32b .. 32b+31) that name real slots: the last
 // record word also carries out_deg and the raw index above slot k.
 __device__ __forceinline__ uint32_t batch_mask(int b, int k) {
@@ -846,12 +855,13 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
 // nodes per wave.  For every candidate slot whose in-edge bit is set, gather
 // x at raw index i + off[s] (x lives in raw-index space, so neither col_idx
 // nor an index remap is read).  A slot no lane of the wave needs is skipped
-// with a scalar branch on the wave's presence word; the other lanes' loads of
-// that slot get an out-of-range buffer offset and return 0, so the 32 loads
-// of a batch issue back to back with no per-lane branching.  Slots run in
-// ascending raw-index order, the order of the CSR rows, so the FP32 sum
-// equals the one-lane-per-row CSR sweep's bit for bit.  The plain and the
-// batched sweep both run this routine, so their results agree bit for bit.
+// with a scalar branch on the wave's presence word; for the others, lanes
+// whose bit is clear skip the load under the execution mask (measured
+// cheaper in the texture path than issuing it with an out-of-range offset,
+// which costs address cycles for every lane).  Slots run in ascending
+// raw-index order, the order of the CSR rows, so the FP32 sum equals the
+// one-lane-per-row CSR sweep's bit for bit.  The plain and the batched sweep
+// both run this routine, so their results agree bit for bit.
 struct SweepTile {
     const uint64_t *rec;
     const_ptr<uint64_t> presence;  // per wave of 64 nodes
@@ -906,7 +916,7 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
             const int32_t hi = __builtin_amdgcn_readlane(i, last);
             base = ((lo - q.win_t) >> 2) << 2;                // floor to a multiple of 4
             const int32_t len = hi + q.win_t + 1 - base;
-            use_win = len <= kWinCap;
+            use_win = __builtin_amdgcn_readfirstlane((int32_t)(len <= kWinCap)) != 0;
             if (use_win) {
                 // negative positions wrap to offsets >= 2^31 and load 0; the
                 // x buffers hold whole 16-byte groups up to x_bytes
@@ -935,30 +945,43 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
         // paths and spill them to scratch; the per-slot tests below skip an
         // empty batch's loads just as well)
         const uint32_t bits = r.word32(b) & batch_mask(b, q.k_slots);
-        const uint32_t nbits = ~bits;
+        // window slots of this batch (uniform): read from LDS, the others gathered
+        const uint32_t inwin = use_win ? bit_range32(q.win_lo - 32 * b, q.win_hi - 32 * b) : 0u;
+        const uint32_t gl = any & ~inwin, wl = any & inwin;
         float val[32];
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
             val[u] = 0.0f;
-            if ((any >> u) & 1u) {
-                const int sl = 32 * b + u;
-                if (WIN && use_win && sl >= q.win_lo && sl < q.win_hi) {
-                    // in [0, len) for every lane whose bit is set
-                    const bool on = (bits >> u) & 1u;
-                    const int32_t idx = on ? i + q.off[sl] - base : 0;
-                    const float xv = row[idx];
-                    val[u] = on ? xv : 0.0f;
-                } else if (BUF) {
-                    // out-of-range offset (the load returns 0) where this lane's bit is clear
-                    const uint32_t byte = ((nbits << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)q.off[32 * b + u]);
-                    val[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, byte, 0, 0));
+            if ((gl >> u) & 1u) {
+                if (BUF) {
+                    // lanes without the in-edge skip the load (execution mask)
+                    if ((bits >> u) & 1u)
+                        val[u] = __int_as_float(
+                            __builtin_amdgcn_raw_buffer_load_b32(xr, i4 + 4u * (uint32_t)q.off[32 * b + u], 0, 0));
                 } else {
                     val[u] = ((bits >> u) & 1u) ? q.x_in[i + q.off[32 * b + u]] : 0.0f;
                 }
             }
         }
+        if constexpr (WIN) {
+            // separate registers, so the LDS reads wait for none of the gathers
+            float lv[32];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) acc += val[u];
+            for (int u = 0; u < 32; ++u) {
+                lv[u] = 0.0f;
+                if ((wl >> u) & 1u) {
+                    const bool on = (bits >> u) & 1u;
+                    const int32_t idx = on ? i + q.off[32 * b + u] - base : 0;   // in [0, len) where on
+                    const float xv = row[idx];
+                    lv[u] = on ? xv : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 32; ++u) acc += ((inwin >> u) & 1u) ? lv[u] : val[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < 32; ++u) acc += val[u];
+        }
     }
     double ps = 0.0, pr = 0.0, pk = 0.0;
     if (active) {
@@ -1037,10 +1060,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchMember *__res
         q.n = m->n;
         q.k_slots = m->k_slots;
         q.x_bytes = m->x_bytes;
-        q.win_t = m->win_t;
-        q.win_lo = m->win_lo;
-        q.win_hi = m->win_hi;
-        sweep_tile<W, BUF, BUF>(q, tile);
+        q.win_t = 0;
+        q.win_lo = q.win_hi = 0;
+        sweep_tile<W, BUF, false>(q, tile);
     }
 }
 
