@@ -11,13 +11,14 @@ value = FFG+PageRank edges traversed per second over the timed steps,
         sum(E * iterations) / wall time, in GTEPS.
 roofline = the PageRank sweep kernel: its algorithmic bytes per launch
         ((20 + 8 W) N + 4 E for the slot sweep with W record words per node,
-        20 N + 8 E for the CSR sweep) over its mean duration, from a pair of
-        HIP events around every sweep launch on the engine's stream during
-        the timed steps (launches after convergence, which exit at once, are
-        not counted), against 8 TB/s HBM.  traffic = HBM bytes per launch
-        from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by the same
-        counters on a plain copy (see --traffic-from), or null when the
-        kernel source changed since they were taken.
+        20 N + 8 E for the CSR sweep) over its mean duration, from pairs of
+        HIP events on the engine's stream around sweep launches of the timed
+        steps (every 8th launch by default, so that the events barely slow
+        the steps; launches after convergence, which exit at once, are not
+        counted), against 8 TB/s HBM.  traffic = HBM bytes per launch from
+        rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by the same counters
+        on a plain copy (see --traffic-from), or null when the kernel source
+        changed since they were taken.
 cpu_baseline = the FP64 oracle on the same space at the same tolerance,
         single-threaded on the host.
 """
@@ -208,11 +209,13 @@ def main():
     ap.add_argument("--traffic-from", metavar="DIR",
                     help="write the sweep kernel's HBM traffic record from the rocprofv3 --pmc "
                          "runs under DIR (no GPU needed) and exit")
-    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true, true>")
+    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true, false>")
     ap.add_argument("--traffic-copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--traffic-command", default="")
     ap.add_argument("--no-sweep-events", action="store_true",
-                    help="time the steps without per-sweep events (roofline then from chunk events)")
+                    help="time the steps without sweep events (roofline then from chunk events)")
+    ap.add_argument("--sweep-event-every", type=int, default=8,
+                    help="bracket every n-th sweep launch with HIP events during the timed steps")
     args = ap.parse_args()
 
     if args.traffic_from:
@@ -272,7 +275,7 @@ def main():
     for _ in range(args.warmup):
         step()
     if not args.no_sweep_events:
-        api.profile(ctx, True)
+        api.profile(ctx, args.sweep_event_every)
     torch.cuda.synchronize()
     infos, timings = [], []
     t0 = time.perf_counter()
@@ -282,7 +285,7 @@ def main():
         timings.append(t)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    api.profile(ctx, False)
+    api.profile(ctx, 0)
     print(f"[bench] {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
 
     info = infos[-1]
@@ -292,7 +295,7 @@ def main():
     if args.no_sweep_events:        # chunk time over launches: includes the step kernels
         avg_launch_s = sum(t["iterate_ms"] for t in timings) / 1e3 / sum(t["launches"] for t in timings)
     else:                           # sweep kernels that did work, each between its own events
-        avg_launch_s = sum(t["sweep_ms"] for t in timings) / 1e3 / sum(t["iterations"] for t in timings)
+        avg_launch_s = sum(t["sweep_ms"] for t in timings) / 1e3 / sum(t["sweeps_timed"] for t in timings)
     if info["row_mapping"] in (-1, -2):   # slot sweeps: records, y in/out, x out; x gathers
         bytes_per_launch = (20 + 8 * info["mask_words"]) * N + 4 * E
         buf = 16 * ((n_raw + 3) // 4) < 2 ** 31
@@ -330,7 +333,9 @@ def main():
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": round(avg_launch_s * 1e6, 3),
                      "timing": "chunk events / launches" if args.no_sweep_events
-                               else "per-sweep HIP events, working launches"},
+                               else f"HIP events around every {args.sweep_event_every}th sweep launch "
+                                    f"of the timed steps ({sum(t['sweeps_timed'] for t in timings)} "
+                                    f"working launches)"},
         "phases_ms": {k: round(float(np.mean([t[k] for t in timings])), 4)
                       for k in ("build_ms", "pagerank_ms", "iterate_ms", "sweep_ms", "score_ms")},
         "analysis_pct_hbm_alg": round(alg_bytes / step_s / (HBM_PEAK_GBS * 1e9), 4),

@@ -125,9 +125,11 @@ typedef struct {
     double score_ms;     /* output of the ranks, minima and C_p */
     int32_t iterations;  /* iteration kernels that did work */
     int32_t launches;    /* iteration kernels launched (extra ones exit at once) */
-    double sweep_ms;     /* device time of the sweep kernels that did work (the
-                            edge gathers alone), summed; measured only while
-                            fl_profile is on for the context, else 0 */
+    double sweep_ms;     /* device time of the timed sweep kernels that did
+                            work (the edge gathers alone), summed; measured
+                            only while fl_profile is on, else 0 */
+    int32_t sweeps_timed; /* number of sweeps summed in sweep_ms */
+    int32_t reserved;
 } fl_timing;
 
 typedef struct fl_ctx fl_ctx;
@@ -191,11 +193,13 @@ fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *plan, int32_t *d_valid_raw,
 fl_status fl_tune(fl_ctx *ctx, fl_plan *plan, const fl_params *params, int32_t sweeps, int32_t *best,
                   double *us_per_sweep);
 
-/* Sweep profiling: while `enable` is non-zero, fl_execute brackets every
- * sweep kernel with a pair of HIP events on the context's stream and reports
- * the summed device time of the sweeps that did work in fl_timing.sweep_ms.
- * Costs a few microseconds of host time per iteration; off by default. */
-fl_status fl_profile(fl_ctx *ctx, int32_t enable);
+/* Sweep profiling: while `every` > 0, fl_execute brackets every every-th
+ * sweep kernel launch of an analysis (the 0th, every-th, ...) with a pair of
+ * HIP events on the context's stream and reports the summed device time of
+ * those that did work in fl_timing.sweep_ms (count in sweeps_timed).  Each
+ * timed sweep costs a few microseconds of device time for the events;
+ * every = 0 (the default) turns it off.  FL_EINVAL for every < 0. */
+fl_status fl_profile(fl_ctx *ctx, int32_t every);
 
 /* Phase timings of the plan's last build and execute (see fl_timing). */
 fl_status fl_plan_timing(fl_ctx *ctx, const fl_plan *plan, fl_timing *out);

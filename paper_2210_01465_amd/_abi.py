@@ -49,7 +49,8 @@ class fl_timing(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("pagerank_ms", ctypes.c_double),
                 ("iterate_ms", ctypes.c_double), ("score_ms", ctypes.c_double),
                 ("iterations", ctypes.c_int32),
-                ("launches", ctypes.c_int32), ("sweep_ms", ctypes.c_double)]
+                ("launches", ctypes.c_int32), ("sweep_ms", ctypes.c_double),
+                ("sweeps_timed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -231,9 +231,10 @@ def tune(plan: Plan, damping: float = 0.85, sweeps: int = 4) -> dict:
             "us_per_sweep": {lay: float(t) for lay, t in zip(TUNE_LAYOUTS, times) if t >= 0}}
 
 
-def profile(ctx: Context, enable: bool = True) -> None:
-    """Time every sweep kernel with HIP events (fl_profile); see plan_timing's sweep_ms."""
-    _check(ctx, _abi.load().fl_profile(ctx.handle, int(bool(enable))), "fl_profile")
+def profile(ctx: Context, every: int = 1) -> None:
+    """Time every every-th sweep kernel with HIP events (fl_profile; 0 = off);
+    see plan_timing's sweep_ms and sweeps_timed."""
+    _check(ctx, _abi.load().fl_profile(ctx.handle, int(every)), "fl_profile")
 
 
 def plan_timing(plan: Plan) -> dict:

@@ -95,7 +95,7 @@ struct fl_ctx {
     std::string err;
     DevicePool pool;
     std::map<uint64_t, int> tuned;  // shape class -> sweep layout chosen by fl_tune
-    bool profile = false;           // bracket every sweep kernel with events (fl_profile)
+    int32_t profile_every = 0;      // bracket every n-th sweep kernel with events (fl_profile), 0 = off
     std::vector<hipEvent_t> sweep_ev;  // 2 per launch of the longest chunk so far
     BuildSizes *h_sizes = nullptr;  // pinned
     PrState *h_state = nullptr;     // pinned
@@ -849,8 +849,9 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     int chunk = 16;
     double iterate_ms = 0.0, sweep_ms = 0.0;
     PrState *hs = ctx->h_state;
+    int sampled = 0;
     for (;;) {
-        if (ctx->profile && (int)ctx->sweep_ev.size() < 2 * chunk) {
+        if (ctx->profile_every > 0 && (int)ctx->sweep_ev.size() < 2 * chunk) {
             for (int j = (int)ctx->sweep_ev.size(); j < 2 * chunk; ++j) {
                 hipEvent_t e;
                 FL_HIP(hipEventCreate(&e));
@@ -859,9 +860,10 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
         }
         FL_HIP(hipEventRecord(p->ev[5], s));
         for (int j = 0; j < chunk; ++j) {
-            if (ctx->profile) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j], s));
+            const bool timed = ctx->profile_every > 0 && (launches + j) % ctx->profile_every == 0;
+            if (timed) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j], s));
             FL_HIP(fl::launch_pr_sweep(a, p->sl, lanes, grid, s));
-            if (ctx->profile) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j + 1], s));
+            if (timed) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j + 1], s));
             FL_HIP(fl::launch_pr_step(a, grid, s));
         }
         FL_HIP(hipEventRecord(p->ev[6], s));
@@ -870,9 +872,12 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
         FL_HIP(hipMemcpyAsync(hs, p->state, sizeof(PrState), hipMemcpyDeviceToHost, s));
         FL_HIP(hipStreamSynchronize(s));
         iterate_ms += elapsed(p->ev[5], p->ev[6]);
-        if (ctx->profile)   // launches past the converged iteration exit at once: not counted
+        if (ctx->profile_every > 0)   // launches past the converged iteration exit at once: not counted
             for (int j = 0; j < chunk && before + j < hs->worked; ++j)
-                sweep_ms += elapsed(ctx->sweep_ev[2 * j], ctx->sweep_ev[2 * j + 1]);
+                if ((before + j) % ctx->profile_every == 0) {
+                    sweep_ms += elapsed(ctx->sweep_ev[2 * j], ctx->sweep_ev[2 * j + 1]);
+                    ++sampled;
+                }
         if (hs->done) break;
         const double rate = (hs->resid_prev > 0.0) ? hs->resid / hs->resid_prev : 1.0;
         if (rate > 0.0 && rate < 0.999 && hs->resid > r.tol) {
@@ -896,6 +901,7 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     p->timing.score_ms = elapsed(p->ev[3], p->ev[4]);
     p->timing.iterate_ms = iterate_ms;
     p->timing.sweep_ms = sweep_ms;
+    p->timing.sweeps_timed = sampled;
     p->timing.iterations = hs->worked;
     p->timing.launches = launches;
     const fl_status result = hs->done == 1 ? FL_OK : FL_ENOCONV;
@@ -919,10 +925,11 @@ fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *p, int32_t *d_valid_raw, in
     return FL_OK;
 }
 
-fl_status fl_profile(fl_ctx *ctx, int32_t enable) {
+fl_status fl_profile(fl_ctx *ctx, int32_t every) {
     if (!ctx) return FL_EINVAL;
     ctx->err.clear();
-    ctx->profile = enable != 0;
+    if (every < 0) return fail(ctx, FL_EINVAL, "every must be >= 0");
+    ctx->profile_every = every;
     return FL_OK;
 }
 

@@ -691,17 +691,19 @@ __device__ void finish_step(PrState *st, const double *__restrict__ partials, in
     constexpr int B = kFinishBlock, kRound = 3 * B;
     const int64_t total = 3 * (int64_t)count;
     double r[3] = {0.0, 0.0, 0.0};   // r[q]: component (threadIdx.x + q B) mod 3
-    for (int64_t e0 = 0; e0 < total; e0 += 4 * kRound) {
-        double v[4][3];
+    // 24 loads in flight per thread: one round covers 8192 tiles (2 M nodes)
+    constexpr int kU = 8;
+    for (int64_t e0 = 0; e0 < total; e0 += kU * kRound) {
+        double v[kU][3];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kU; ++u)
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int64_t e = e0 + u * kRound + q * B + threadIdx.x;
                 v[u][q] = e < total ? partials[e] : 0.0;
             }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kU; ++u)
 #pragma unroll
             for (int q = 0; q < 3; ++q) r[q] += v[u][q];
     }

@@ -50,7 +50,7 @@ def test_struct_layouts_match_header():
     # fl_params: 3 doubles + 2 int32; fl_summary: 4 int64 + 6 int32 + 5 doubles
     assert ctypes.sizeof(_abi.fl_params) == 32
     assert ctypes.sizeof(_abi.fl_summary) == 4 * 8 + 6 * 4 + 5 * 8
-    assert ctypes.sizeof(_abi.fl_timing) == 4 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(_abi.fl_timing) == 4 * 8 + 2 * 4 + 8 + 2 * 4
 
 
 def test_null_context_is_rejected():
