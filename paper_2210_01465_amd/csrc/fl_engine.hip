@@ -389,7 +389,7 @@ void build_degree(fl_ctx *ctx, Build &b) {
     if (p->sl.words > 0) {
         p->rec = pool_alloc<uint64_t>(ctx, (int64_t)n * p->sl.words);
         p->presence = pool_alloc<uint64_t>(ctx, ((int64_t)n + 63) / 64 * p->sl.words);
-        p->d_off = pool_alloc<int32_t>(ctx, fl::kMaxSlots);   // whole batches of 32 (read as vectors)
+        p->d_off = pool_alloc<int32_t>(ctx, std::max(p->sl.k, 1));
     }
     if (!b.in_deg || !b.tile_e || !b.tile_eoff || !b.tile_m || !b.tile_moff || !p->out_deg || !p->row_ptr ||
         !p->minima || (p->sl.words > 0 && (!p->rec || !p->presence || !p->d_off)))
@@ -397,7 +397,7 @@ void build_degree(fl_ctx *ctx, Build &b) {
     hipStream_t s = ctx->stream;
     hipError_t he = hipSuccess;
     if (p->sl.words > 0 && p->sl.k > 0)
-        he = hipMemcpyAsync(p->d_off, p->sl.off, sizeof(int32_t) * fl::kMaxSlots, hipMemcpyHostToDevice, s);
+        he = hipMemcpyAsync(p->d_off, p->sl.off, sizeof(int32_t) * p->sl.k, hipMemcpyHostToDevice, s);
     if (he == hipSuccess) he = fl::launch_degree(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, n, b.in_deg, p->out_deg,
                                       p->rec, p->presence, b.tile_e, b.tile_m, b.tile_eoff, b.tile_moff,
                                       b.d_sizes, s);

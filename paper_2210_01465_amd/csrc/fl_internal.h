@@ -46,10 +46,10 @@ struct SpaceDesc {
 // raw index.  words = 0 when k + 40 > 64 * kMaxWords (then only the generic
 // kernels and the CSR sweep are used).
 struct SlotTable {
-    alignas(64) int32_t off[kMaxSlots];  // first and 64-byte aligned: kernels read batches of 16 as one vector
     int32_t k;
     int32_t words;
     int32_t win_t, win_lo, win_hi;  // slots [win_lo, win_hi) have |off| <= win_t <= kWinMaxOff (0: none)
+    int32_t off[kMaxSlots];
     int16_t delta[kMaxSlots];
     uint8_t dim[kMaxSlots];
     // Parameter k's slots form two contiguous runs in slot order (every

@@ -35,7 +35,6 @@ __device__ __forceinline__ bool bad_fitness(float f) { return !(f != f) && !(f >
 // words in SGPRs instead of a VGPR per value.
 template <typename T>
 using const_ptr = const __attribute__((address_space(4))) T *;
-typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
 template <typename T>
 __device__ __forceinline__ const_ptr<T> to_const(const T *p) {
     return (const_ptr<T>)p;
@@ -362,19 +361,16 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
         const uint32_t exb = (b & 1) ? (uint32_t)(ex[b >> 1] >> 32) : (uint32_t)ex[b >> 1];
         const uint32_t any = __builtin_amdgcn_readfirstlane(wave_or(exb));
         const uint32_t nex = ~exb;
-        const i32x16 oa = reinterpret_cast<const i32x16 *>(sl.off)[2 * b];
-        const i32x16 ob = reinterpret_cast<const i32x16 *>(sl.off)[2 * b + 1];
         float fc[32];
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
             fc[u] = 0.0f;
-            const int32_t o = u < 16 ? oa[u & 15] : ob[u & 15];
             if ((any >> u) & 1u) {
                 if (BUF) {
-                    const uint32_t byte = ((nex << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)o);
+                    const uint32_t byte = ((nex << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)sl.off[32 * b + u]);
                     fc[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(fr, byte, 0, 0));
                 } else {
-                    fc[u] = ((exb >> u) & 1u) ? fit[(int32_t)i + o] : 0.0f;
+                    fc[u] = ((exb >> u) & 1u) ? fit[(int32_t)i + sl.off[32 * b + u]] : 0.0f;
                 }
             }
         }
@@ -552,19 +548,16 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(SlotTable sl, const int32
         const uint32_t any = (b & 1) ? (uint32_t)(pq >> 32) : (uint32_t)pq;
         const uint32_t bits = r.word32(b) & batch_mask(b, sl.k);
         const uint32_t nbits = ~bits;
-        const i32x16 oa = reinterpret_cast<const i32x16 *>(sl.off)[2 * b];
-        const i32x16 ob = reinterpret_cast<const i32x16 *>(sl.off)[2 * b + 1];
         int32_t src[32];
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
             src[u] = 0;
-            const int32_t o = u < 16 ? oa[u & 15] : ob[u & 15];
             if ((any >> u) & 1u) {
                 if (BUF) {
-                    const uint32_t byte = ((nbits << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)o);
+                    const uint32_t byte = ((nbits << (31 - u)) & 0x80000000u) | (i4 + 4u * (uint32_t)sl.off[32 * b + u]);
                     src[u] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rr, byte, 0, 0);
                 } else {
-                    src[u] = ((bits >> u) & 1u) ? remap[i + o] : 0;
+                    src[u] = ((bits >> u) & 1u) ? remap[i + sl.off[32 * b + u]] : 0;
                 }
             }
         }
@@ -957,33 +950,40 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
         // window slots of this batch (uniform): read from LDS, the others gathered
         const uint32_t inwin = use_win ? bit_range32(q.win_lo - 32 * b, q.win_hi - 32 * b) : 0u;
         const uint32_t gl = any & ~inwin, wl = any & inwin;
-        // the batch's 32 slot offsets in two 16-dword scalar loads (the
-        // table holds whole batches), so no gather waits on its own offset
-        const i32x16 oa = reinterpret_cast<const_ptr<i32x16>>(q.off)[2 * b];
-        const i32x16 ob = reinterpret_cast<const_ptr<i32x16>>(q.off)[2 * b + 1];
-        // one pass over the batch: gathers into val[], window reads into
-        // lv[] (separate registers, so an LDS read waits for no gather)
-        float val[32], lv[32];
+        float val[32];
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
             val[u] = 0.0f;
-            lv[u] = 0.0f;
-            const int32_t o = u < 16 ? oa[u & 15] : ob[u & 15];
             if ((gl >> u) & 1u) {
                 if (BUF) {
                     // lanes without the in-edge skip the load (execution mask)
                     if ((bits >> u) & 1u)
-                        val[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, i4 + 4u * (uint32_t)o, 0, 0));
+                        val[u] = __int_as_float(
+                            __builtin_amdgcn_raw_buffer_load_b32(xr, i4 + 4u * (uint32_t)q.off[32 * b + u], 0, 0));
                 } else {
-                    val[u] = ((bits >> u) & 1u) ? q.x_in[i + o] : 0.0f;
+                    val[u] = ((bits >> u) & 1u) ? q.x_in[i + q.off[32 * b + u]] : 0.0f;
                 }
             }
-            if (WIN && ((wl >> u) & 1u)) {
-                if ((bits >> u) & 1u) lv[u] = row[i + o - base];   // in [0, len) where the bit is set
-            }
         }
+        if constexpr (WIN) {
+            // separate registers, so the LDS reads wait for none of the gathers
+            float lv[32];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) acc += (WIN && ((inwin >> u) & 1u)) ? lv[u] : val[u];
+            for (int u = 0; u < 32; ++u) {
+                lv[u] = 0.0f;
+                if ((wl >> u) & 1u) {
+                    const bool on = (bits >> u) & 1u;
+                    const int32_t idx = on ? i + q.off[32 * b + u] - base : 0;   // in [0, len) where on
+                    const float xv = row[idx];
+                    lv[u] = on ? xv : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 32; ++u) acc += ((inwin >> u) & 1u) ? lv[u] : val[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < 32; ++u) acc += val[u];
+        }
     }
     double ps = 0.0, pr = 0.0, pk = 0.0;
     if (active) {
