@@ -151,7 +151,7 @@ def batched_leg(ctx, damping, p, tol, repeats: int = 3):
             "all_ok": all(r.info["status"] == 0 for r in res)}
 
 
-def serving_leg(ctx, large_space, large_fit, seconds: float, rate: float = 1000.0, warm: float = 0.5):
+def serving_leg(ctx, large_space, large_fit, seconds: float, rate: float = 1000.0, warm: float = 2.0):
     """Poisson stream (rate per second, seed 5) of analyses: 98 % drawn
     uniformly from the 234 batched spaces, 2 % the large space; damping
     uniform on {0.8, 0.85, 0.9}, p = 0.05.  Served with continuous batching,
@@ -183,7 +183,7 @@ def serving_leg(ctx, large_space, large_fit, seconds: float, rate: float = 1000.
     backend.close()
     for cached in list(srv.cache.values()):
         cached[0].close()
-    return {"rate_per_s": rate, "seconds": seconds, "requests": len(reqs),
+    return {"rate_per_s": rate, "seconds": seconds, "warmup_s": warm, "requests": len(reqs),
             "served": served, "one_at_a_time": plain,
             "cache_hits": int(srv.stats["cache_hits"]), "ffg_builds": int(srv.stats["built"])}
 
@@ -201,8 +201,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched leg (234 spaces in one fl_analyze_batch vs one at a time)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serving-seconds", type=float, default=2.0,
-                    help="measured length of the Poisson request stream (after 0.5 s warm-up)")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="measured length of the Poisson request stream (after 2 s of warm-up)")
+    ap.add_argument("--serving-warmup", type=float, default=2.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes five times "
                          "(calibrates the HBM byte counters of a profiler)")
@@ -350,7 +351,7 @@ def main():
 
     if not args.no_serving:
         print("[bench] serving leg", file=sys.stderr, flush=True)
-        out["serving"] = serving_leg(ctx, space, fit, args.serving_seconds)
+        out["serving"] = serving_leg(ctx, space, fit, args.serving_seconds, warm=args.serving_warmup)
 
     ref = None
     if not args.no_cpu_baseline:

@@ -108,7 +108,7 @@ typedef struct {
     int32_t n_slots;     /* candidate neighbour slots per node (2 per neighbour offset) */
     int32_t mask_words;  /* 64-bit words of a node record (0: too many slots, CSR sweep only) */
     int32_t status;      /* fl_status of this analysis (batched calls) */
-    int32_t reserved;
+    int32_t n_plateau;   /* local minima with a neighbour of equal fitness */
     double residual_l1;  /* ||r_k - r_{k-1}||_1 of the last iteration */
     double f_opt;        /* minimum valid fitness */
     double score;        /* C_p */
@@ -192,6 +192,24 @@ fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *plan, int32_t *d_valid_raw,
  * earlier fl_execute calls are not touched.  Synchronises the stream. */
 fl_status fl_tune(fl_ctx *ctx, fl_plan *plan, const fl_params *params, int32_t sweeps, int32_t *best,
                   double *us_per_sweep);
+
+/* C_p curve (Sec. VII-B, eq. 3; the paper plots C_p for p = 0, 1, ..., 15 %):
+ * scores[j] = C_p for p = p_values[j] (fractions >= 0), from the ranks
+ * d_pagerank (double[N], device) that fl_execute wrote for this plan.  One
+ * launch for all proportions; the thresholds (1 + p) f_opt and the rank
+ * sums are FP64, as in fl_execute.  p_values and scores are host arrays of
+ * n_p entries, 1 <= n_p <= 4096.  Errors: FL_EINVAL (bad argument, p < 0 or
+ * not finite), FL_EHIP.  Synchronises the stream. */
+fl_status fl_score_curve(fl_ctx *ctx, const fl_plan *plan, const double *d_pagerank, int32_t n_p,
+                         const double *p_values, double *scores);
+
+/* Naive metric (Sec. VII-A): the fraction of optimal fitness f_opt / f(m) of
+ * every local minimum m.  d_ratio (device double[M], may be NULL) receives
+ * it in ascending node id of the minima; hist (host int64[n_bins], may be
+ * NULL) the number of minima in each of n_bins equal bins of [0, 1], bin
+ * min(floor(ratio * n_bins), n_bins - 1), computed in FP64.  1 <= n_bins <=
+ * 65536.  Errors: FL_EINVAL, FL_ENOMEM, FL_EHIP.  Synchronises the stream. */
+fl_status fl_naive_metric(fl_ctx *ctx, const fl_plan *plan, double *d_ratio, int32_t n_bins, int64_t *hist);
 
 /* Sweep profiling: while `every` > 0, fl_execute brackets every every-th
  * sweep kernel launch of an analysis (the 0th, every-th, ...) with a pair of

@@ -37,7 +37,7 @@ class fl_summary(ctypes.Structure):
                 ("n_minima", ctypes.c_int64), ("iterations", ctypes.c_int32),
                 ("row_mapping", ctypes.c_int32), ("n_slots", ctypes.c_int32),
                 ("mask_words", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("residual_l1", ctypes.c_double),
+                ("n_plateau", ctypes.c_int32), ("residual_l1", ctypes.c_double),
                 ("f_opt", ctypes.c_double), ("score", ctypes.c_double),
                 ("mass_minima", ctypes.c_double), ("mass_near", ctypes.c_double)]
 
@@ -69,6 +69,9 @@ PROTOTYPES = {
     "fl_plan_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "fl_plan_timing": (ctypes.c_int, [_P, _P, ctypes.POINTER(fl_timing)]),
     "fl_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "fl_score_curve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "fl_naive_metric": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "fl_plan_destroy": (ctypes.c_int, [_P, _P]),
     "fl_analyze": (ctypes.c_int, [_P, ctypes.POINTER(fl_space), _P, ctypes.c_int,
                                   ctypes.POINTER(fl_params), _P, _P, _P,

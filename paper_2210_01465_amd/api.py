@@ -10,6 +10,8 @@ points without the ``fl_`` prefix:
     plan_export / plan_timing          fl_plan_export / fl_plan_timing
     tune                               fl_tune          (autotune the sweep layout)
     profile                            fl_profile       (per-sweep device timing)
+    score_curve                        fl_score_curve   (C_p for many p)
+    naive_metric                       fl_naive_metric  (f_opt / f over the minima)
     plan_destroy                       fl_plan_destroy
     analyze                            fl_analyze       (one shot)
     Batch / batch_create               fl_batch_create / _add / _step / _collect / _timing / _destroy
@@ -229,6 +231,32 @@ def tune(plan: Plan, damping: float = 0.85, sweeps: int = 4) -> dict:
     _check(plan.ctx, rc, "fl_tune")
     return {"best": int(best.value),
             "us_per_sweep": {lay: float(t) for lay, t in zip(TUNE_LAYOUTS, times) if t >= 0}}
+
+
+def score_curve(plan: Plan, pagerank: torch.Tensor, p_values=tuple(j / 100 for j in range(16))) -> list:
+    """C_p for every proportion in p_values (fl_score_curve), from the ranks
+    that execute() returned for this plan.  Default: p = 0, 1, ..., 15 %."""
+    ps = [float(x) for x in p_values]
+    n = len(ps)
+    if pagerank.dtype != torch.float64 or pagerank.numel() < plan.n_valid or not pagerank.is_cuda:
+        raise ValueError("pagerank must be the float64 device tensor execute() returned")
+    pa = (ctypes.c_double * max(n, 1))(*ps)
+    out = (ctypes.c_double * max(n, 1))()
+    rc = _abi.load().fl_score_curve(plan.ctx.handle, plan.handle, ctypes.c_void_p(pagerank.data_ptr()), n, pa, out)
+    _check(plan.ctx, rc, "fl_score_curve")
+    return [float(out[j]) for j in range(n)]
+
+
+def naive_metric(plan: Plan, n_bins: int = 20):
+    """f_opt / f(m) for every local minimum (device float64 tensor, ascending
+    node id) and its histogram over n_bins equal bins of [0, 1] (fl_naive_metric)."""
+    dev = torch.device("cuda", plan.ctx.device)
+    ratio = torch.empty(max(plan.n_minima, 1), dtype=torch.float64, device=dev)
+    hist = (ctypes.c_int64 * max(int(n_bins), 1))()
+    rc = _abi.load().fl_naive_metric(plan.ctx.handle, plan.handle, ctypes.c_void_p(ratio.data_ptr()),
+                                     int(n_bins), hist)
+    _check(plan.ctx, rc, "fl_naive_metric")
+    return ratio[:plan.n_minima], [int(hist[j]) for j in range(int(n_bins))]
 
 
 def profile(ctx: Context, every: int = 1) -> None:

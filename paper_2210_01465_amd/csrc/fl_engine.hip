@@ -106,6 +106,7 @@ struct fl_plan {
     SpaceDesc sp{};
     int adjacent = 0;
     int64_t n_raw = 0, n = 0, e = 0, m = 0;
+    int32_t n_plateau = 0;
     float f_opt = 0.0f;
     // FFG, kept for fl_execute / fl_plan_export
     int32_t *valid_raw = nullptr;
@@ -413,6 +414,7 @@ void build_fill(fl_ctx *ctx, Build &b) {
     if (e >= (int64_t(1) << 31)) return build_fail(b, FL_EOVERFLOW, "edge count %lld >= 2^31", (long long)e);
     p->e = e;
     p->m = b.h_sizes->n_minima;
+    p->n_plateau = b.h_sizes->n_plateau;
     p->col_idx = pool_alloc<int32_t>(ctx, e);
     if (!p->col_idx) return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
@@ -436,6 +438,7 @@ void fill_sizes(const fl_plan *p, fl_summary *sizes) {
     sizes->n_valid = p->n;
     sizes->n_edges = p->e;
     sizes->n_minima = p->m;
+    sizes->n_plateau = p->n_plateau;
     sizes->n_slots = p->sl.k;
     sizes->mask_words = p->sl.words;
     sizes->f_opt = (double)p->f_opt;
@@ -922,6 +925,69 @@ fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *p, int32_t *d_valid_raw, in
     if (d_row_ptr) FL_HIP(hipMemcpyAsync(d_row_ptr, p->row_ptr, 4 * (p->n + 1), hipMemcpyDeviceToDevice, s));
     if (d_col_idx && p->e > 0) FL_HIP(hipMemcpyAsync(d_col_idx, p->col_idx, 4 * p->e, hipMemcpyDeviceToDevice, s));
     if (d_out_deg) FL_HIP(hipMemcpyAsync(d_out_deg, p->out_deg, 4 * p->n, hipMemcpyDeviceToDevice, s));
+    return FL_OK;
+}
+
+fl_status fl_score_curve(fl_ctx *ctx, const fl_plan *p, const double *d_pagerank, int32_t n_p,
+                         const double *p_values, double *scores) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!p || p->ctx != ctx || !d_pagerank || !p_values || !scores) return fail(ctx, FL_EINVAL, "bad argument");
+    if (n_p < 1 || n_p > 4096) return fail(ctx, FL_EINVAL, "n_p must be in [1, 4096]");
+    for (int32_t j = 0; j < n_p; ++j)
+        if (!(p_values[j] >= 0.0) || !isfinite(p_values[j])) return fail(ctx, FL_EINVAL, "p must be finite and >= 0");
+    FL_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    double *h = nullptr;   // thresholds, then num/den pairs
+    if (hipHostMalloc((void **)&h, sizeof(double) * 3 * (size_t)n_p, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, FL_ENOMEM, "pinned allocation failed");
+    }
+    double *d = pool_alloc<double>(ctx, 3 * (int64_t)n_p);
+    if (!d) {
+        (void)hipHostFree(h);
+        return fail(ctx, FL_ENOMEM, "device allocation failed");
+    }
+    for (int32_t j = 0; j < n_p; ++j) h[j] = (1.0 + p_values[j]) * (double)p->f_opt;
+    hipError_t e = hipMemcpyAsync(d, h, sizeof(double) * n_p, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = fl::launch_score_curve(d_pagerank, p->minima, (int32_t)p->m, p->fit_c, d, n_p, d + n_p, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + n_p, d + n_p, sizeof(double) * 2 * n_p, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        for (int32_t j = 0; j < n_p; ++j) scores[j] = h[n_p + 2 * j] / h[n_p + 2 * j + 1];
+    ctx->pool.release(d);
+    (void)hipHostFree(h);
+    if (e != hipSuccess) return fail(ctx, FL_EHIP, "C_p curve: %s", hipGetErrorString(e));
+    return FL_OK;
+}
+
+fl_status fl_naive_metric(fl_ctx *ctx, const fl_plan *p, double *d_ratio, int32_t n_bins, int64_t *hist) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!p || p->ctx != ctx) return fail(ctx, FL_EINVAL, "bad plan");
+    if (n_bins < 1 || n_bins > 65536) return fail(ctx, FL_EINVAL, "n_bins must be in [1, 65536]");
+    FL_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    double *ratio = d_ratio ? d_ratio : pool_alloc<double>(ctx, std::max<int64_t>(p->m, 1));
+    uint32_t *dh = pool_alloc<uint32_t>(ctx, n_bins);
+    uint32_t *hh = nullptr;
+    if (!ratio || !dh ||
+        hipHostMalloc((void **)&hh, sizeof(uint32_t) * (size_t)n_bins, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        if (!d_ratio) ctx->pool.release(ratio);
+        ctx->pool.release(dh);
+        return fail(ctx, FL_ENOMEM, "allocation failed");
+    }
+    hipError_t e = fl::launch_naive(p->minima, (int32_t)p->m, p->fit_c, p->f_opt, ratio, n_bins, dh, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hh, dh, sizeof(uint32_t) * n_bins, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && hist)
+        for (int32_t j = 0; j < n_bins; ++j) hist[j] = hh[j];
+    if (!d_ratio) ctx->pool.release(ratio);
+    ctx->pool.release(dh);
+    (void)hipHostFree(hh);
+    if (e != hipSuccess) return fail(ctx, FL_EHIP, "naive metric: %s", hipGetErrorString(e));
     return FL_OK;
 }
 

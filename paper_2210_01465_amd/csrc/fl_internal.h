@@ -66,6 +66,8 @@ struct BuildSizes {
     float f_opt;         // minimum valid fitness
     int32_t n_minima;
     int64_t n_edges;
+    int32_t n_plateau;   // minima with a neighbour of equal fitness
+    int32_t pad;
 };
 
 // Power-iteration state, device resident.  The stored iterate y_k is the
@@ -166,6 +168,14 @@ hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const Slo
 hipError_t launch_pr_output(const PrArgs &a, double *pagerank, hipStream_t stream);
 hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m,
                         const float *fit_c, double threshold, PrState *st, hipStream_t stream);
+// C_p for n thresholds: num[j], den[j] = rank sums over minima below
+// thresholds[j] and over all minima (one workgroup per threshold).
+hipError_t launch_score_curve(const double *pagerank, const int32_t *minima, int32_t m, const float *fit_c,
+                              const double *thresholds, int32_t n, double *num_den, hipStream_t stream);
+// f_opt / f(m) for every minimum, and a histogram of it over n_bins equal
+// bins of [0, 1] (hist zeroed here).
+hipError_t launch_naive(const int32_t *minima, int32_t m, const float *fit_c, float f_opt, double *ratio,
+                        int32_t n_bins, uint32_t *hist, hipStream_t stream);
 
 // Batched power iteration.  `tiles` lists the tiles to work on; `members`
 // lists member indices for the per-member kernels.  The sweep kernel reads

@@ -255,6 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_scan(const int32_t *__restri
         sizes->n_valid = n_valid;
         sizes->n_bad = bad;
         sizes->f_opt = mn;
+        sizes->n_plateau = 0;   // counted by the degree pass
     }
 }
 
@@ -330,7 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
                                                          uint64_t *__restrict__ rec,
                                                          uint64_t *__restrict__ presence,
                                                          int64_t *__restrict__ tile_e,
-                                                         int32_t *__restrict__ tile_m) {
+                                                         int32_t *__restrict__ tile_m,
+                                                         BuildSizes *__restrict__ sizes) {
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < n;
     const uint32_t i = active ? (uint32_t)valid_raw[v] : 0u;
@@ -355,6 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
     const __amdgpu_buffer_rsrc_t fr = __builtin_amdgcn_make_buffer_rsrc((void *)fit, (short)0, fit_bytes, 0x00020000);
     const uint32_t i4 = 4u * i;
     int32_t dout = 0;
+    bool tie = false;
 #pragma unroll
     for (int b = 0; b < 2 * W; ++b) {
         if (32 * b >= sl.k) break;
@@ -381,6 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
             // or better (out-edge; 0 marks a slot the node does not have)
             if ((fc[u] > fv) & (fc[u] < INFINITY)) inb |= 1u << u;
             dout += (fc[u] < fv) & (fc[u] > 0.0f);
+            tie |= fc[u] == fv;   // a valid neighbour of equal fitness (0, NaN, inf never equal fv)
         }
         m[b >> 1] |= (b & 1) ? ((uint64_t)inb << 32) : (uint64_t)inb;
     }
@@ -405,9 +409,11 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
     }
     const int64_t te = block_sum((int64_t)din);
     const int32_t tm = block_sum((int32_t)(v < n && dout == 0));
+    const int32_t tp = block_sum((int32_t)(v < n && dout == 0 && tie));
     if (threadIdx.x == 0) {
         tile_e[blockIdx.x] = te;
         tile_m[blockIdx.x] = tm;
+        if (tp > 0) atomicAdd(&sizes->n_plateau, tp);
     }
 }
 
@@ -419,9 +425,11 @@ __global__ __launch_bounds__(kBlock) void k_degree_generic(SpaceDesc sp, const f
                                                            int32_t *__restrict__ in_deg,
                                                            int32_t *__restrict__ out_deg,
                                                            int64_t *__restrict__ tile_e,
-                                                           int32_t *__restrict__ tile_m) {
+                                                           int32_t *__restrict__ tile_m,
+                                                           BuildSizes *__restrict__ sizes) {
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
     int32_t din = 0, dout = 0;
+    bool tie = false;
     if (v < n) {
         const uint32_t i = (uint32_t)valid_raw[v];
         const float fv = fit[i];
@@ -434,6 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_degree_generic(SpaceDesc sp, const f
                 const float hi = xk + 1 < r ? fit[row + (xk + 1) * st] : NAN;
                 din += ((lo > fv) & (lo < INFINITY)) + ((hi > fv) & (hi < INFINITY));
                 dout += (lo < fv) + (hi < fv);
+                tie |= (lo == fv) | (hi == fv);
             } else {
                 for (uint32_t a0 = 0; a0 < r; a0 += 8) {
                     float fc[8];
@@ -446,6 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_degree_generic(SpaceDesc sp, const f
                     for (int u = 0; u < 8; ++u) {
                         din += (fc[u] > fv) & (fc[u] < INFINITY);
                         dout += (fc[u] < fv);
+                        tie |= fc[u] == fv;
                     }
                 }
             }
@@ -455,9 +465,11 @@ __global__ __launch_bounds__(kBlock) void k_degree_generic(SpaceDesc sp, const f
     }
     const int64_t te = block_sum((int64_t)din);
     const int32_t tm = block_sum((int32_t)(v < n && dout == 0));
+    const int32_t tp = block_sum((int32_t)(v < n && dout == 0 && tie));
     if (threadIdx.x == 0) {
         tile_e[blockIdx.x] = te;
         tile_m[blockIdx.x] = tm;
+        if (tp > 0) atomicAdd(&sizes->n_plateau, tp);
     }
 }
 
@@ -1129,6 +1141,47 @@ __global__ __launch_bounds__(kBlock) void k_batch_score(const BatchMember *__res
     }
 }
 
+// C_p curve (Sec. VII-B, eq. 3, for many p): workgroup j sums the ranks of
+// the minima with (double) f <= thresholds[j] and of all minima, in FP64.
+__global__ __launch_bounds__(kBlock) void k_score_curve(const double *__restrict__ pagerank,
+                                                        const int32_t *__restrict__ minima, int32_t m,
+                                                        const float *__restrict__ fit_c,
+                                                        const double *__restrict__ thresholds,
+                                                        double *__restrict__ num_den) {
+    const double t = thresholds[blockIdx.x];
+    double num = 0.0, den = 0.0;
+    for (int32_t j = threadIdx.x; j < m; j += kBlock) {
+        const int32_t v = minima[j];
+        const double r = pagerank[v];
+        den += r;
+        if ((double)fit_c[v] <= t) num += r;
+    }
+    num = block_sum(num);
+    den = block_sum(den);
+    if (threadIdx.x == 0) {
+        num_den[2 * blockIdx.x] = num;
+        num_den[2 * blockIdx.x + 1] = den;
+    }
+}
+
+// Fraction of optimal fitness f_opt / f(m) of every local minimum, and its
+// histogram over n_bins equal bins of [0, 1] (integer counts, exact).
+__global__ __launch_bounds__(kBlock) void k_naive(const int32_t *__restrict__ minima, int32_t m,
+                                                  const float *__restrict__ fit_c, float f_opt,
+                                                  double *__restrict__ ratio, int32_t n_bins,
+                                                  uint32_t *__restrict__ hist) {
+    for (int32_t j = blockIdx.x * kBlock + threadIdx.x; j < m; j += gridDim.x * kBlock) {
+        const double q = (double)f_opt / (double)fit_c[minima[j]];
+        ratio[j] = q;
+        const int32_t bin = min((int32_t)floor(q * (double)n_bins), n_bins - 1);
+        atomicAdd(&hist[bin], 1u);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int32_t n, uint32_t value) {
+    for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) p[j] = value;
+}
+
 __global__ void k_batch_states(const BatchMember *__restrict__ members, const int32_t *__restrict__ member_ids,
                                int32_t n_members, PrState *__restrict__ states_out) {
     const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1241,9 +1294,10 @@ hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent,
         }
         SpaceDesc d = sp;
         SlotTable t = sl;
-        void *args[] = {(void *)&d, (void *)&t, (void *)&fit, (void *)&fit_bytes, (void *)&valid_raw, (void *)&n,
-                        (void *)&in_deg, (void *)&out_deg, (void *)&rec, (void *)&presence, (void *)&tile_e,
-                        (void *)&tile_m};
+        void *args[] = {(void *)&d,      (void *)&t,       (void *)&fit,      (void *)&fit_bytes,
+                        (void *)&valid_raw, (void *)&n,    (void *)&in_deg,   (void *)&out_deg,
+                        (void *)&rec,    (void *)&presence, (void *)&tile_e, (void *)&tile_m,
+                        (void *)&sizes};
         hipError_t e = hipLaunchKernel(fn, dim3(tiles), dim3(kBlock), args, 0, stream);
         if (e != hipSuccess) return e;
     }
@@ -1252,10 +1306,10 @@ hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent,
         case 0:
             if (adjacent)
                 hipLaunchKernelGGL(k_degree_generic<true>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
-                                   n, in_deg, out_deg, tile_e, tile_m);
+                                   n, in_deg, out_deg, tile_e, tile_m, sizes);
             else
                 hipLaunchKernelGGL(k_degree_generic<false>, dim3(tiles), dim3(kBlock), 0, stream, sp, fit, valid_raw,
-                                   n, in_deg, out_deg, tile_e, tile_m);
+                                   n, in_deg, out_deg, tile_e, tile_m, sizes);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1355,6 +1409,23 @@ hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m
                         const float *fit_c, double threshold, PrState *st, hipStream_t stream) {
     hipLaunchKernelGGL(k_score, dim3(1), dim3(kBlock), 0, stream, pagerank, minima, m, fit_c,
                        threshold, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_score_curve(const double *pagerank, const int32_t *minima, int32_t m, const float *fit_c,
+                              const double *thresholds, int32_t n, double *num_den, hipStream_t stream) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_score_curve, dim3(n), dim3(kBlock), 0, stream, pagerank, minima, m, fit_c, thresholds,
+                           num_den);
+    return hipGetLastError();
+}
+
+hipError_t launch_naive(const int32_t *minima, int32_t m, const float *fit_c, float f_opt, double *ratio,
+                        int32_t n_bins, uint32_t *hist, hipStream_t stream) {
+    hipLaunchKernelGGL(k_fill_u32, dim3((n_bins + 255) / 256), dim3(256), 0, stream, hist, n_bins, 0u);
+    if (m > 0)
+        hipLaunchKernelGGL(k_naive, dim3(std::min<int32_t>((m + kBlock - 1) / kBlock, 1024)), dim3(kBlock), 0,
+                           stream, minima, m, fit_c, f_opt, ratio, n_bins, hist);
     return hipGetLastError();
 }
 

@@ -286,6 +286,8 @@ def latency_summary(done: list, since: float = 0.0) -> dict:
     if lat.size == 0:
         return {"n": 0}
     span = max(d.finish for d in done) - min(d.arrival for d in done)
+    edges = sum(float(d.info.get("n_edges", 0)) * float(d.info.get("iterations", 0)) for d in done)
     return {"n": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-            "throughput_per_s": float(len(done) / span) if span > 0 else None}
+            "throughput_per_s": float(len(done) / span) if span > 0 else None,
+            "gteps": float(edges / span / 1e9) if span > 0 else None}
