@@ -67,6 +67,8 @@ def load(path: str = LIB) -> ctypes.CDLL:
     lib.flo_score.argtypes = [P, P, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)]
     lib.flo_score.restype = ctypes.c_double
+    lib.flo_dag_rank.argtypes = [P, ctypes.c_double, P, i64p]
+    lib.flo_dag_rank.restype = ctypes.c_int
     _lib_cache[path] = lib
     return lib
 
@@ -119,6 +121,16 @@ class Graph:
         if rc not in (OK, ENOCONV) or (check and rc != OK):
             raise OracleError(rc, "flo_pagerank")
         return r, int(it.value), float(res.value)
+
+    def dag_rank(self, damping: float = 0.85):
+        """Exact PageRank by forward substitution in descending fitness order
+        (valid for damping in (0, 1]); returns (r, longest path length)."""
+        r = np.empty(self.N, dtype=np.float64)
+        depth = ctypes.c_int64()
+        rc = self._lib.flo_dag_rank(self._handle, damping, _ptr(r), ctypes.byref(depth))
+        if rc != 0:
+            raise OracleError(rc, "flo_dag_rank")
+        return r, int(depth.value)
 
     def score(self, centrality: np.ndarray, p: float):
         c = np.ascontiguousarray(centrality, dtype=np.float64)

@@ -367,6 +367,68 @@ int flo_pagerank(const flo_graph *g, double d, double tol, int64_t max_iter,
 }
 
 /*
+ * Exact PageRank of the FFG without iteration (Sec. VII-B), for damping
+ * d in (0, 1].  Both the teleport and the sink term of G are multiples of
+ * the all-ones vector, so the stationary vector is r = u / sum(u) with
+ * (I - d P) u = 1, i.e. u(w) = 1 + d * sum_{u->w} u(u) / out_deg(u).  Every
+ * edge goes from higher to lower fitness, so nodes in order of descending
+ * fitness have all their in-neighbours before them: one forward
+ * substitution in that order solves the system.  *depth receives the length
+ * of the longest path (edges) of the FFG.  At d = 1, u(m) / N for a sink m
+ * is the probability that a descent from a uniformly random start, moving
+ * to a uniformly random better neighbour until none exists, ends in m.
+ */
+static const float *g_sort_f;
+
+static int by_fitness_desc(const void *a, const void *b)
+{
+    float fa = g_sort_f[*(const int64_t *)a], fb = g_sort_f[*(const int64_t *)b];
+    if (fa > fb) return -1;
+    if (fa < fb) return 1;
+    int64_t ia = *(const int64_t *)a, ib = *(const int64_t *)b;
+    return (ia > ib) - (ia < ib);
+}
+
+int flo_dag_rank(const flo_graph *g, double d, double *r, int64_t *depth)
+{
+    if (!(d > 0.0 && d <= 1.0))
+        return FLO_EINVAL;
+    const int64_t N = g->N;
+    int64_t *order = malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+    int64_t *level = calloc((size_t)(N > 0 ? N : 1), sizeof(int64_t));
+    if (!order || !level) { free(order); free(level); return FLO_ENOMEM; }
+    for (int64_t v = 0; v < N; ++v)
+        order[v] = v;
+    g_sort_f = g->f;
+    qsort(order, (size_t)N, sizeof(int64_t), by_fitness_desc);
+    int64_t deepest = 0;
+    for (int64_t j = 0; j < N; ++j) {
+        int64_t w = order[j];
+        flo_sum acc = {0, 0};
+        for (int64_t e = g->in_ptr[w]; e < g->in_ptr[w + 1]; ++e) {
+            int64_t u = g->in_src[e];
+            sum_add(&acc, r[u] / (double)g->out_deg[u]);
+            if (level[u] + 1 > level[w])
+                level[w] = level[u] + 1;
+        }
+        r[w] = 1.0 + d * sum_get(&acc);
+        if (level[w] > deepest)
+            deepest = level[w];
+    }
+    flo_sum total = {0, 0};
+    for (int64_t v = 0; v < N; ++v)
+        sum_add(&total, r[v]);
+    double t = sum_get(&total);
+    for (int64_t v = 0; v < N; ++v)
+        r[v] /= t;
+    free(order);
+    free(level);
+    if (depth)
+        *depth = deepest;
+    return FLO_OK;
+}
+
+/*
  * p-proportion of centrality (Sec. VII-B, eq. 3):
  *   C_p = sum_{x in L_p} c(x) / sum_{x in L} c(x),
  * L the local minima, L_p those with fitness <= (1+p) f_opt.

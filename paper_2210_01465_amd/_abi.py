@@ -66,6 +66,8 @@ PROTOTYPES = {
                                       ctypes.POINTER(_P), ctypes.POINTER(fl_summary)]),
     "fl_execute": (ctypes.c_int, [_P, _P, ctypes.POINTER(fl_params), _P, _P,
                                   ctypes.POINTER(fl_summary)]),
+    "fl_execute_exact": (ctypes.c_int, [_P, _P, ctypes.POINTER(fl_params), _P, _P,
+                                  ctypes.POINTER(fl_summary)]),
     "fl_plan_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "fl_plan_timing": (ctypes.c_int, [_P, _P, ctypes.POINTER(fl_timing)]),
     "fl_profile": (ctypes.c_int, [_P, ctypes.c_int32]),

@@ -7,6 +7,7 @@ points without the ``fl_`` prefix:
     create / destroy / last_error      fl_create / fl_destroy / fl_last_error
     plan_create                        fl_plan_create   (build the FFG)
     execute                            fl_execute       (PageRank, minima, C_p)
+    execute(exact=True)                fl_execute_exact (exact sweeps, damping in (0, 1])
     plan_export / plan_timing          fl_plan_export / fl_plan_timing
     tune                               fl_tune          (autotune the sweep layout)
     profile                            fl_profile       (per-sweep device timing)
@@ -170,8 +171,9 @@ def _params(damping, p, tol, max_iter, row_mapping):
 
 def execute(plan: Plan, damping: float = 0.85, p: float = 0.05, tol: float = 0.0,
             max_iter: int = 0, row_mapping: int = 0, pagerank: torch.Tensor | None = None,
-            minima: torch.Tensor | None = None, allow_noconv: bool = False):
-    """PageRank, local minima and C_p on a plan (fl_execute).
+            minima: torch.Tensor | None = None, allow_noconv: bool = False, exact: bool = False):
+    """PageRank, local minima and C_p on a plan (fl_execute; with exact=True
+    fl_execute_exact, which also accepts damping 1).
 
     Returns (pagerank float64[N], minima int32[M], summary dict).  Output
     tensors may be passed in (sizes N and M, on the context's device)."""
@@ -189,10 +191,11 @@ def execute(plan: Plan, damping: float = 0.85, p: float = 0.05, tol: float = 0.0
         raise ValueError("minima must be a contiguous int32 tensor of >= M entries")
     prm = _params(damping, p, tol, max_iter, row_mapping)
     out = _abi.fl_summary()
-    rc = _abi.load().fl_execute(ctx.handle, plan.handle, ctypes.byref(prm),
-                                ctypes.c_void_p(pagerank.data_ptr()),
-                                ctypes.c_void_p(minima.data_ptr()), ctypes.byref(out))
-    _check(ctx, rc, "fl_execute", allow=(_abi.FL_ENOCONV,) if allow_noconv else ())
+    fn = _abi.load().fl_execute_exact if exact else _abi.load().fl_execute
+    rc = fn(ctx.handle, plan.handle, ctypes.byref(prm), ctypes.c_void_p(pagerank.data_ptr()),
+            ctypes.c_void_p(minima.data_ptr()), ctypes.byref(out))
+    _check(ctx, rc, "fl_execute_exact" if exact else "fl_execute",
+           allow=(_abi.FL_ENOCONV,) if allow_noconv else ())
     info = out.as_dict()
     info["status"] = rc
     return pagerank[:plan.n_valid], minima[:plan.n_minima], info

@@ -465,9 +465,10 @@ struct Resolved {
     int lanes;  // FL_ROWS_SLOTS, FL_ROWS_SLOTS_WIN or CSR lanes
 };
 
-fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Resolved &r) {
+fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Resolved &r, bool exact = false) {
     const double d = prm->damping;
-    if (!(d > 0.0 && d < 1.0)) return fail(ctx, FL_EINVAL, "damping must be in (0,1)");
+    if (exact ? !(d > 0.0 && d <= 1.0) : !(d > 0.0 && d < 1.0))
+        return fail(ctx, FL_EINVAL, exact ? "damping must be in (0,1]" : "damping must be in (0,1)");
     if (!(prm->p >= 0.0) || !isfinite(prm->p)) return fail(ctx, FL_EINVAL, "p must be finite and >= 0");
     if (!(prm->tol_l1 >= 0.0) || !isfinite(prm->tol_l1)) return fail(ctx, FL_EINVAL, "tol_l1 must be finite and >= 0");
     if (prm->max_iter < 0) return fail(ctx, FL_EINVAL, "max_iter must be >= 0");
@@ -481,7 +482,8 @@ fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Re
     r.d = d;
     r.p = prm->p;
     r.tol = prm->tol_l1 > 0.0 ? prm->tol_l1 : 2e-7;
-    r.max_iter = prm->max_iter > 0 ? prm->max_iter : 1000;
+    // the exact sweeps settle after (longest path + 1) <= N sweeps
+    r.max_iter = prm->max_iter > 0 ? prm->max_iter : (exact ? (int32_t)std::min<int64_t>(p->n + 2, INT32_MAX) : 1000);
     r.lanes = prm->row_mapping ? prm->row_mapping : (p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e));
     return FL_OK;
 }
@@ -820,14 +822,16 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
     return FL_OK;
 }
 
-fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pagerank,
-                     int32_t *d_minima, fl_summary *out) {
+namespace {
+
+fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pagerank, int32_t *d_minima,
+                       fl_summary *out, bool exact) {
     if (!ctx) return FL_EINVAL;
     ctx->err.clear();
     if (!p || !prm || !d_pagerank || (!d_minima && p->m > 0)) return fail(ctx, FL_EINVAL, "null argument");
     if (p->ctx != ctx) return fail(ctx, FL_EINVAL, "plan belongs to another context");
     Resolved r;
-    fl_status st = resolve_params(ctx, p, prm, r);
+    fl_status st = resolve_params(ctx, p, prm, r, exact);
     if (st != FL_OK) return st;
     int lanes = r.lanes;
     if (prm->row_mapping == 0) {
@@ -840,6 +844,7 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     int grid = 0, init_grid = 0;
     st = prepare_pr(ctx, p, r, lanes, a, grid, init_grid);
     if (st != FL_OK) return st;
+    a.exact = exact ? 1 : 0;
 
     FL_HIP(hipEventRecord(p->ev[2], s));
     FL_HIP(hipMemsetAsync(p->state, 0, sizeof(PrState), s));
@@ -883,7 +888,9 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
                 }
         if (hs->done) break;
         const double rate = (hs->resid_prev > 0.0) ? hs->resid / hs->resid_prev : 1.0;
-        if (rate > 0.0 && rate < 0.999 && hs->resid > r.tol) {
+        if (exact) {
+            chunk = 64;   // the sweeps end abruptly (exact fixed point): no decay to follow
+        } else if (rate > 0.0 && rate < 0.999 && hs->resid > r.tol) {
             const double more = ceil(log(r.tol / hs->resid) / log(rate));
             chunk = (int)std::min(64.0, std::max(2.0, more + 1.0));
         } else {
@@ -912,6 +919,18 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pa
     if (result != FL_OK)
         return fail(ctx, FL_ENOCONV, "no convergence after %d iterations (residual %.3e)", hs->k, hs->resid);
     return FL_OK;
+}
+
+}  // namespace
+
+fl_status fl_execute(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pagerank, int32_t *d_minima,
+                     fl_summary *out) {
+    return execute_impl(ctx, p, prm, d_pagerank, d_minima, out, false);
+}
+
+fl_status fl_execute_exact(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pagerank, int32_t *d_minima,
+                           fl_summary *out) {
+    return execute_impl(ctx, p, prm, d_pagerank, d_minima, out, true);
 }
 
 fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *p, int32_t *d_valid_raw, int32_t *d_row_ptr,

@@ -115,6 +115,7 @@ struct PrArgs {
     int32_t x_bytes;        // bytes of each x buffer (n_raw rounded up to 4 floats) when < 2^31, else 0
     int32_t win_t;          // windowed slot sweep: slots [win_lo, win_hi) have |off| <= win_t; 0 = off
     int32_t win_lo, win_hi;
+    int32_t exact;          // 1: Jacobi sweeps u <- 1 + d P u to an exact fixed point (s = c = 1)
 };
 
 // One member of a batch: an FFG with its own power iteration, run together

@@ -699,7 +699,7 @@ __device__ __forceinline__ void write_partials(double *partials, int32_t j, doub
 // a round fixed at (threadIdx.x + q kFinishBlock) mod 3.  first: the triples
 // come from the initial iterate.
 __device__ void finish_step(PrState *st, const double *__restrict__ partials, int32_t count, double d, double tol,
-                            int32_t max_iter, int32_t n, bool first) {
+                            int32_t max_iter, int32_t n, bool first, bool exact = false) {
     constexpr int B = kFinishBlock, kRound = 3 * B;
     const int64_t total = 3 * (int64_t)count;
     double r[3] = {0.0, 0.0, 0.0};   // r[q]: component (threadIdx.x + q B) mod 3
@@ -725,6 +725,34 @@ __device__ void finish_step(PrState *st, const double *__restrict__ partials, in
     double s1 = c0 == 1 ? r[0] : (c0 == 0 ? r[1] : r[2]);
     double s2 = c0 == 2 ? r[0] : (c0 == 1 ? r[1] : r[2]);
     block_sum3<B>(s0, s1, s2);
+    if (exact && threadIdx.x == 0) {
+        // Jacobi sweeps y' = d P y + 1 (the sweep computes s d acc + c with
+        // s = c = 1); a sweep that changes no value ends them, and s then
+        // scales the fixed point to sum 1 for the output
+        st->sigma = s0;
+        st->sink = s2;
+        st->c = 1.0;
+        if (first) {
+            st->s = 1.0;
+            st->k = 0;
+            st->done = 0;
+            st->worked = 0;
+            st->resid = 0.0;
+            st->resid_prev = 0.0;
+        } else {
+            st->resid_prev = st->resid;
+            st->resid = s1;
+            st->k += 1;
+            st->worked += 1;
+            st->s = 1.0;
+            if (s1 == 0.0)
+                st->done = 1;
+            else if (st->k >= max_iter)
+                st->done = 2;
+            if (st->done) st->s = 1.0 / s0;
+        }
+        return;
+    }
     if (threadIdx.x == 0) {
         const double s = 1.0 / s0;
         st->sigma = s0;
@@ -754,7 +782,7 @@ __device__ void finish_step(PrState *st, const double *__restrict__ partials, in
 template <bool FIRST>
 __global__ __launch_bounds__(kFinishBlock) void k_pr_finish(PrArgs a, int32_t count) {
     if (!FIRST && a.st->done) return;
-    finish_step(a.st, a.partials, count, a.d, a.tol, a.max_iter, a.n, FIRST);
+    finish_step(a.st, a.partials, count, a.d, a.tol, a.max_iter, a.n, FIRST, a.exact != 0);
 }
 
 // Initial iterate r = 1/N of one tile of kBlock nodes, with its partial sums.

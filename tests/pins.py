@@ -216,6 +216,57 @@ def check_dag_identity(lib, spaces, nbs=("hamming",), d=0.85):
             assert np.abs(r - ref).sum() <= 1e-12, (s.name, nb, np.abs(r - ref).sum())
 
 
+def _absorption(g, target):
+    """Probability that a descent from node v, moving to a uniformly random
+    strictly better neighbour until none exists, stops in a node of
+    ``target``; by dynamic programming over ascending fitness (the
+    definition written out, no matrix algebra)."""
+    out = [[] for _ in range(g.N)]
+    for w in range(g.N):
+        for e in range(g.row_ptr[w], g.row_ptr[w + 1]):
+            out[int(g.col_idx[e])].append(w)      # edge col_idx[e] -> w
+    q = np.zeros(g.N)
+    tgt = np.zeros(g.N, dtype=bool)
+    tgt[list(target)] = True
+    for v in np.argsort(g.fit, kind="stable"):   # better nodes first
+        q[v] = float(tgt[v]) if not out[v] else sum(q[w] for w in out[v]) / len(out[v])
+    return q
+
+
+def _longest_path(g):
+    level = np.zeros(g.N, dtype=np.int64)
+    for w in np.argsort(-g.fit, kind="stable"):   # worse nodes first
+        a, b = g.row_ptr[w], g.row_ptr[w + 1]
+        if b > a:
+            level[w] = 1 + level[g.col_idx[a:b]].max()
+    return int(level.max()) if g.N else 0
+
+
+def check_dag_rank(lib, cases=None):
+    """The oracle's exact rank (forward substitution in descending fitness)
+    against the Jacobi sweep u <- 1 + d P u of brute.dag_pagerank at
+    d = 0.5, 0.85 and 1, against the oracle's power iteration at d < 1, its
+    reported depth against the longest path, and at d = 1 its C_p against the
+    probability that a uniformly started random descent ends in L_p."""
+    for radix, f in (cases or small_cases()):
+        if not np.any(np.isfinite(f) & (f > 0)):
+            continue
+        for nb in ("hamming", "adjacent"):
+            g = oracle.build_graph(radix, f, NB[nb], lib_path=lib)
+            for d in (0.5, 0.85, 1.0):
+                r, depth = g.dag_rank(d)
+                ref = dag_pagerank(g.N, g.row_ptr, g.col_idx, g.out_deg, d)
+                assert np.abs(r - ref).sum() <= 1e-12, (radix, nb, d)
+                if d < 1.0:
+                    rp, _, _ = g.pagerank(d, 1e-13, MAX_ITER)
+                    assert np.abs(r - rp).sum() <= 1e-11, (radix, nb, d)
+            assert depth == _longest_path(g), (radix, nb)
+            for p in (0.0, 0.05, 0.3):
+                near = [int(m) for m in g.minima if float(g.fit[m]) <= (1.0 + p) * g.f_opt]
+                prob = _absorption(g, near).mean()
+                assert abs(g.score(r, p)[0] - prob) <= 1e-12, (radix, nb, p)
+
+
 def check_grid_degrees(lib, spaces, nbs=("hamming", "adjacent")):
     """Per-node in/out degree, E and minima against whole-array comparisons."""
     for s in spaces:
@@ -318,7 +369,7 @@ def check_errors(lib):
 
 QUICK = [check_paper_sizes, check_adjacent_example, check_neighbours_product_order,
          check_ffg_bruteforce, check_pagerank_dense, check_closed_forms,
-         check_separable_minima, check_score_brute, check_metamorphic, check_errors]
+         check_separable_minima, check_score_brute, check_dag_rank, check_metamorphic, check_errors]
 
 
 def run_quick(lib):

@@ -43,6 +43,11 @@ MUTANTS = {
     "rows_by_raw_position_of_target": [("g->in_src[fill[w]++] = u;", "g->in_src[fill[w]++] = w;")],
     "f_opt_is_first_node": [("if ((double)g->f[v] < g->f_opt)", "if (v == 0)")],
     "zero_fitness_accepted": [("if (!isnan(v) && !(v > 0.0f))", "if (!isnan(v) && v < 0.0f)")],
+    "dag_ascending_order": [("if (fa > fb) return -1;\n    if (fa < fb) return 1;",
+                             "if (fa < fb) return -1;\n    if (fa > fb) return 1;")],
+    "dag_without_one": [("r[w] = 1.0 + d * sum_get(&acc);", "r[w] = (w == 0) + d * sum_get(&acc);")],
+    "dag_divide_by_in_degree": [("sum_add(&acc, r[u] / (double)g->out_deg[u]);",
+                                 "sum_add(&acc, r[u] / (double)(g->in_ptr[w + 1] - g->in_ptr[w]));")],
 }
 
 
