@@ -174,13 +174,14 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *plan, const fl_params *params,
 /* Exact PageRank without a tolerance (Sec. VII-B): every FFG edge lowers the
  * fitness, so P is nilpotent and the stationary vector is r = u / sum(u)
  * with u = 1 + d P u.  Jacobi sweeps u <- 1 + d P u (the same sweep kernels
- * as fl_execute) reach u exactly after (longest path + 1) sweeps, detected by
- * a sweep that changes no value; r, the minima and C_p are then written as
- * by fl_execute.  damping may be 1: then u(m) / N for a minimum m is the
+ * as fl_execute) stop changing after at most (longest path + 1) sweeps
+ * (sooner when d^k of distant ancestors falls below FP32 resolution),
+ * detected by a sweep that changes no value; r, the minima and C_p are then
+ * written as by fl_execute.  damping may be 1: then u(m) / N for a minimum m is the
  * probability that a descent from a uniformly random start, moving to a
  * uniformly random better neighbour, ends in m, and C_p is the probability
  * that it ends within (1 + p) f_opt.  tol_l1 is ignored; max_iter 0 means
- * N + 2; summary.iterations = sweeps run (longest path + 2).  Errors as
+ * N + 2; summary.iterations = sweeps run (at most longest path + 2).  Errors as
  * fl_execute (FL_EINVAL for damping outside (0, 1]). */
 fl_status fl_execute_exact(fl_ctx *ctx, fl_plan *plan, const fl_params *params, double *d_pagerank,
                            int32_t *d_minima, fl_summary *out);
