@@ -175,7 +175,8 @@ fl_status fl_execute(fl_ctx *ctx, fl_plan *plan, const fl_params *params,
  * fitness, so P is nilpotent and the stationary vector is r = u / sum(u)
  * with u = 1 + d P u.  Jacobi sweeps u <- 1 + d P u (the same sweep kernels
  * as fl_execute) stop changing after at most (longest path + 1) sweeps
- * (sooner when d^k of distant ancestors falls below FP32 resolution),
+ * (sooner where the weight of a distant ancestor, d^k times the product
+ * of 1/out_deg along the path, falls below FP32 resolution),
  * detected by a sweep that changes no value; r, the minima and C_p are then
  * written as by fl_execute.  damping may be 1: then u(m) / N for a minimum m is the
  * probability that a descent from a uniformly random start, moving to a

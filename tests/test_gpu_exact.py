@@ -59,10 +59,9 @@ def test_exact_matches_oracle(ctx, nb, damping):
         assert l1 <= 1e-5, (s.name, nb, damping, l1)
         assert abs(info["score"] - g.score(r, 0.05)[0]) <= 1e-5
         # settles after at most (longest path + 1) sweeps, seen by one more
-        # sweep; sooner when d^k of far ancestors falls below FP32 resolution
+        # sweep; sooner where the weight of a distant ancestor (d^k times the
+        # product of 1/out_deg along the path) falls below FP32 resolution
         assert info["iterations"] <= depth + 2, (info["iterations"], depth)
-        if damping == 1.0:
-            assert info["iterations"] >= depth + 1, (info["iterations"], depth)
         assert info["residual_l1"] == 0.0
 
 
