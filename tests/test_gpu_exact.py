@@ -73,7 +73,7 @@ def test_exact_agrees_with_power_iteration_and_layouts(ctx):
     fit = torch.from_numpy(s.fitness_raw).cuda()
     plan = api.plan_create(ctx, s.radix, fit, "hamming")
     try:
-        ref, _, _ = api.execute(plan, 0.85, 0.05, tol=1e-9, max_iter=5000)
+        ref, _, _ = api.execute(plan, 0.85, 0.05)   # FP32 sweeps, stopped at 2e-7
         ref = ref.cpu().numpy()
         outs = {}
         for lay in (-1, 1, 8):
