@@ -258,8 +258,11 @@ def serve_plain(backend, requests, clock: Callable[[], float] | None = None,
     t0 = clock() if start is None else start
     done = []
     for req in sorted(requests):
-        while clock() - t0 < req.arrival:
-            sleep(min(req.arrival - (clock() - t0), 0.001))
+        while True:
+            wait = req.arrival - (clock() - t0)
+            if wait <= 0:
+                break
+            sleep(min(wait, 0.001))
         plan, _ = backend.build(req)
         pr, mins, info = backend.plain(plan, req)
         backend.release(plan)
