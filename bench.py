@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--traffic-from", metavar="DIR",
                     help="write the sweep kernel's HBM traffic record from the rocprofv3 --pmc "
                          "runs under DIR (no GPU needed) and exit")
-    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true, false>")
+    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true>")
     ap.add_argument("--traffic-copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--traffic-command", default="")
     ap.add_argument("--no-sweep-events", action="store_true",
@@ -297,11 +297,10 @@ def main():
         avg_launch_s = sum(t["iterate_ms"] for t in timings) / 1e3 / sum(t["launches"] for t in timings)
     else:                           # sweep kernels that did work, each between its own events
         avg_launch_s = sum(t["sweep_ms"] for t in timings) / 1e3 / sum(t["sweeps_timed"] for t in timings)
-    if info["row_mapping"] in (-1, -2):   # slot sweeps: records, y in/out, x out; x gathers
+    if info["row_mapping"] == -1:   # slot sweep: records, y in/out, x out; x gathers
         bytes_per_launch = (20 + 8 * info["mask_words"]) * N + 4 * E
         buf = 16 * ((n_raw + 3) // 4) < 2 ** 31
-        kernel = (f"k_pr_iter_slots<{info['mask_words']}, {'true' if buf else 'false'}, "
-                  f"{'true' if info['row_mapping'] == -2 else 'false'}>")
+        kernel = f"k_pr_iter_slots<{info['mask_words']}, {'true' if buf else 'false'}>"
     else:                           # CSR sweep: row_ptr, out_deg, y in/out, x out, col_idx, x gathers
         bytes_per_launch = 20 * N + 8 * E
         kernel = f"k_pr_iter_csr<{info['row_mapping']}>"

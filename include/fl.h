@@ -79,16 +79,12 @@ typedef struct {
  *             where available, else CSR lanes from the mean in-degree);
  *             FL_ROWS_SLOTS = one node per lane over the in-edge slot
  *             records (needs at most 256 candidate slots per node);
- *             FL_ROWS_SLOTS_WIN = the same with
- *             the slots of offset |off| <= 256 read from a per-wave window
- *             of x staged in LDS (also needs fewer than 2^29 raw
- *             configurations); 1, 2, 4, 8, 16, 32 or 64 = that many lanes
- *             per row over the CSR.  Every layout sums a row's terms in the
- *             same order: the slot layouts and the one-lane CSR layout give
- *             the same ranks bit for bit. */
+ *             1, 2, 4, 8, 16, 32 or 64 = that many lanes per row over the
+ *             CSR.  Every layout sums a row's terms in the same order: the
+ *             slot layout and the one-lane CSR layout give the same ranks
+ *             bit for bit. */
 #define FL_ROWS_SLOTS (-1)
-#define FL_ROWS_SLOTS_WIN (-2)
-#define FL_TUNE_LAYOUTS 9
+#define FL_TUNE_LAYOUTS 8
 typedef struct {
     double damping;
     double p;
@@ -196,10 +192,9 @@ fl_status fl_execute_exact(fl_ctx *ctx, fl_plan *plan, const fl_params *params, 
 fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *plan, int32_t *d_valid_raw,
                          int32_t *d_row_ptr, int32_t *d_col_idx, int32_t *d_out_deg);
 
-/* Autotuner: time every sweep layout the plan allows (the windowed and the
- * plain slot sweep, then the CSR sweep with 1, 2, 4, 8, 16, 32, 64 lanes
- * per row) for `sweeps` forced power-iteration sweeps each (HIP events,
- * after one warm-up sweep), store the fastest in the context's tuning cache
+/* Autotuner: time every sweep layout the plan allows (the slot sweep, then
+ * the CSR sweep with 1, 2, 4, 8, 16, 32, 64 lanes per row) for `sweeps`
+ * forced power-iteration sweeps each (HIP events, after one warm-up sweep), store the fastest in the context's tuning cache
  * under the plan's shape class (node-record width, neighbourhood, log2 N,
  * mean in-degree) and return it in *best.  us_per_sweep (may be NULL)
  * receives FL_TUNE_LAYOUTS times in microseconds in that layout order, -1
@@ -277,9 +272,8 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *batch);
  * The member holds 8 n_raw + 8 N + 24 ceil(N/256) + 80 bytes of device
  * memory of its own while it is in the batch.
  * Members always run the slot sweep (FL_ROWS_SLOTS).
- * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0,
- * FL_ROWS_SLOTS or FL_ROWS_SLOTS_WIN, or a space the slot sweep cannot
- * take: use fl_execute),
+ * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0 or
+ * FL_ROWS_SLOTS, or a space the slot sweep cannot take: use fl_execute),
  * FL_ENOMEM, FL_EHIP. */
 fl_status fl_batch_add(fl_ctx *ctx, fl_batch *batch, fl_plan *plan, const fl_params *params,
                        double *d_pagerank, int32_t *d_minima, int64_t tag);

@@ -218,14 +218,14 @@ def plan_export(plan: Plan) -> dict:
     return t
 
 
-ROWS_SLOTS, ROWS_SLOTS_WIN = -1, -2
-TUNE_LAYOUTS = (ROWS_SLOTS_WIN, ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64)
+ROWS_SLOTS = -1
+TUNE_LAYOUTS = (ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64)
 
 
 def tune(plan: Plan, damping: float = 0.85, sweeps: int = 4) -> dict:
     """Autotune the sweep layout for the plan's shape class (fl_tune).
     Returns {"best": layout, "us_per_sweep": {layout: us}} (-1 slot sweep,
-    -2 windowed slot sweep, else CSR lanes per row)."""
+    else CSR lanes per row)."""
     best = ctypes.c_int32()
     times = (ctypes.c_double * len(TUNE_LAYOUTS))()
     prm = _params(damping, 0.05, 0.0, 0, 0)

@@ -125,7 +125,9 @@ struct fl_plan {
     double *partials = nullptr;
     PrState *state = nullptr;
     int pr_grid = 0;
-    int32_t *d_off = nullptr;   // slot offsets in device memory (read by the slot sweep)
+    int32_t *d_off = nullptr;   // 2 k_pad entries in device memory, read by the slot sweep:
+                                // raw-index offsets, then byte offsets from the most negative
+    int32_t h_off[2 * (fl::kMaxSlots + 64)] = {};   // host source of d_off
     // timing
     hipEvent_t ev[7] = {};  // build 0-1, pagerank 2-3, score 4, iteration chunk 5-6
     bool have_events = false;
@@ -193,6 +195,11 @@ void set_magic(SpaceDesc &sp) {
 // Candidate slots sorted by raw-index offset: Hamming gives parameter k the
 // deltas +-1 .. +-(radix_k - 1), adjacent +-1.  A node record holds the slot
 // bits plus 40 bits of out_deg and raw index, in at most fl::kMaxWords words.
+// Slots rounded up to whole batches of 32 (the lane-mask table's row length).
+// Stride of the two halves of the device offset table: the sweep reads whole
+// batches of offsets (up to 64 past the last slot), so k rounded up to 64, plus 64.
+int32_t k_pad_of(const fl::SlotTable &sl) { return (sl.k + 63) / 64 * 64 + 64; }
+
 fl::SlotTable make_slots(const SpaceDesc &sp, bool adjacent) {
     fl::SlotTable t{};
     int64_t total = 0;
@@ -214,18 +221,11 @@ fl::SlotTable make_slots(const SpaceDesc &sp, bool adjacent) {
         }
     }
     std::sort(slots.begin(), slots.end(), [](const Slot &x, const Slot &y) { return x.off < y.off; });
-    t.win_lo = -1;
     for (size_t s = 0; s < slots.size(); ++s) {
         t.off[s] = (int32_t)slots[s].off;
         t.delta[s] = (int16_t)slots[s].delta;
         t.dim[s] = (uint8_t)slots[s].dim;
-        if (std::llabs(slots[s].off) <= fl::kWinMaxOff) {   // contiguous: the slots are sorted by offset
-            if (t.win_lo < 0) t.win_lo = (int32_t)s;
-            t.win_hi = (int32_t)s + 1;
-            t.win_t = std::max<int32_t>(t.win_t, (int32_t)std::llabs(slots[s].off));
-        }
     }
-    if (t.win_lo < 0) t.win_lo = t.win_hi = t.win_t = 0;
     // runs of each parameter's slots (checked: a space where they were not
     // contiguous would take the generic kernels)
     for (int k = 0; k < sp.n; ++k) {
@@ -390,15 +390,22 @@ void build_degree(fl_ctx *ctx, Build &b) {
     if (p->sl.words > 0) {
         p->rec = pool_alloc<uint64_t>(ctx, (int64_t)n * p->sl.words);
         p->presence = pool_alloc<uint64_t>(ctx, ((int64_t)n + 63) / 64 * p->sl.words);
-        p->d_off = pool_alloc<int32_t>(ctx, std::max(p->sl.k, 1));
+        p->d_off = pool_alloc<int32_t>(ctx, 2 * k_pad_of(p->sl));
     }
     if (!b.in_deg || !b.tile_e || !b.tile_eoff || !b.tile_m || !b.tile_moff || !p->out_deg || !p->row_ptr ||
         !p->minima || (p->sl.words > 0 && (!p->rec || !p->presence || !p->d_off)))
         return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
     hipError_t he = hipSuccess;
-    if (p->sl.words > 0 && p->sl.k > 0)
-        he = hipMemcpyAsync(p->d_off, p->sl.off, sizeof(int32_t) * p->sl.k, hipMemcpyHostToDevice, s);
+    if (p->sl.words > 0 && p->sl.k > 0) {
+        const int32_t kp = k_pad_of(p->sl);
+        for (int32_t j = 0; j < p->sl.k; ++j) {
+            p->h_off[j] = p->sl.off[j];
+            // meaningful only where the buffer-load sweep runs (4 span + 64 < 2^31)
+            p->h_off[kp + j] = (int32_t)(uint32_t)(4 * ((int64_t)p->sl.off[j] - p->sl.off[0]));
+        }
+        he = hipMemcpyAsync(p->d_off, p->h_off, sizeof(int32_t) * 2 * kp, hipMemcpyHostToDevice, s);
+    }
     if (he == hipSuccess) he = fl::launch_degree(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, n, b.in_deg, p->out_deg,
                                       p->rec, p->presence, b.tile_e, b.tile_m, b.tile_eoff, b.tile_moff,
                                       b.d_sizes, s);
@@ -445,24 +452,23 @@ void fill_sizes(const fl_plan *p, fl_summary *sizes) {
 }
 
 // Analysis parameters with the defaults applied.
-// Bytes of an x buffer in raw-index space (n_raw rounded up to whole 16-byte
-// groups) when buffer loads can address it with room for the out-of-range
-// offset bit, else 0.
+// Bytes the slot sweep's buffer loads span: its descriptor starts at the most
+// negative slot offset below x, and the loads reach the end of x plus the
+// largest offset; 0 when that does not fit a signed 32-bit offset (the
+// sweep then uses plain loads).
 int32_t x_bytes_of(const fl_plan *p) {
-    const int64_t b = 4 * ((p->n_raw + 3) / 4 * 4);
+    if (p->sl.k <= 0) return 0;
+    const int64_t span = (p->n_raw + 3) / 4 * 4 + (int64_t)p->sl.off[p->sl.k - 1] - (int64_t)p->sl.off[0];
+    const int64_t b = 4 * span + 64;
     return b < (int64_t(1) << 31) ? (int32_t)b : 0;
 }
 
-bool is_slot_layout(int lanes) { return lanes == FL_ROWS_SLOTS || lanes == FL_ROWS_SLOTS_WIN; }
-
-// The windowed slot sweep is available: records, buffer-addressable x, and
-// at least one slot within the window reach.
-bool window_ok(const fl_plan *p) { return p->sl.words > 0 && x_bytes_of(p) > 0 && p->sl.win_t > 0; }
+bool is_slot_layout(int lanes) { return lanes == FL_ROWS_SLOTS; }
 
 struct Resolved {
     double d, p, tol;
     int32_t max_iter;
-    int lanes;  // FL_ROWS_SLOTS, FL_ROWS_SLOTS_WIN or CSR lanes
+    int lanes;  // FL_ROWS_SLOTS or CSR lanes
 };
 
 fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Resolved &r, bool exact = false) {
@@ -473,12 +479,10 @@ fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Re
     if (!(prm->tol_l1 >= 0.0) || !isfinite(prm->tol_l1)) return fail(ctx, FL_EINVAL, "tol_l1 must be finite and >= 0");
     if (prm->max_iter < 0) return fail(ctx, FL_EINVAL, "max_iter must be >= 0");
     if (prm->row_mapping != 0 && !is_slot_layout(prm->row_mapping) && !valid_lanes(prm->row_mapping))
-        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS, FL_ROWS_SLOTS_WIN or a power of two <= 64");
+        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS or a power of two <= 64");
     if (is_slot_layout(prm->row_mapping) && p->sl.words == 0)
         return fail(ctx, FL_EINVAL, "the slot sweep needs at most %d candidate slots (space has %d)",
                     fl::kMaxSlots, p->sl.k);
-    if (prm->row_mapping == FL_ROWS_SLOTS_WIN && !window_ok(p))
-        return fail(ctx, FL_EINVAL, "the windowed slot sweep needs a raw index space below 2^29 configurations");
     r.d = d;
     r.p = prm->p;
     r.tol = prm->tol_l1 > 0.0 ? prm->tol_l1 : 2e-7;
@@ -495,7 +499,7 @@ fl_status ensure_pr_buffers(fl_ctx *ctx, fl_plan *p, bool slots) {
         p->state = pool_alloc<PrState>(ctx, 1);
         if (!p->y[0] || !p->y[1] || !p->state) return fail(ctx, FL_ENOMEM, "device allocation failed");
     }
-    const int64_t x_need = slots ? (p->n_raw + 3) / 4 * 4 : p->n;   // whole 16-byte groups (windowed sweep)
+    const int64_t x_need = slots ? (p->n_raw + 3) / 4 * 4 : p->n;   // raw-index space, whole 16-byte groups
     if (x_need > p->x_cap) {
         for (int j = 0; j < 2; ++j) {
             ctx->pool.release(p->x[j]);
@@ -545,7 +549,7 @@ uint64_t shape_key(const fl_plan *p) {
 }
 
 // Grid, buffers and arguments of the power iteration of plan p in layout
-// `lanes` (FL_ROWS_SLOTS, FL_ROWS_SLOTS_WIN or CSR lanes per row).
+// `lanes` (FL_ROWS_SLOTS or CSR lanes per row).
 fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrArgs &a, int &grid,
                      int &init_grid) {
     const int kind = is_slot_layout(lanes) ? fl::kSweepSlots : fl::kSweepCsr;
@@ -553,11 +557,6 @@ fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrAr
     a.kind = kind;
     a.adjacent = p->adjacent;
     a.x_bytes = kind == fl::kSweepSlots ? x_bytes_of(p) : 0;
-    if (lanes == FL_ROWS_SLOTS_WIN) {
-        a.win_t = p->sl.win_t;
-        a.win_lo = p->sl.win_lo;
-        a.win_hi = p->sl.win_hi;
-    }
     // persistent grid: every workgroup resident at once (occupancy query), a
     // multiple of the XCD count so each XCD gets the same number of them
     int per_cu = 0;
@@ -580,6 +579,7 @@ fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrAr
     a.valid_raw = p->valid_raw;
     a.rec = p->rec;
     a.presence = p->presence;
+    a.k_pad = k_pad_of(p->sl);
     a.off = p->d_off;
     a.k_slots = p->sl.k;
     a.y[0] = p->y[0];
@@ -1071,14 +1071,13 @@ fl_status fl_tune(fl_ctx *ctx, fl_plan *p, const fl_params *prm, int32_t sweeps,
     r.max_iter = sweeps + 1;
     FL_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    const int layouts[FL_TUNE_LAYOUTS] = {FL_ROWS_SLOTS_WIN, FL_ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64};
+    const int layouts[FL_TUNE_LAYOUTS] = {FL_ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64};
     double best_us = 0.0;
     *best = 0;
     for (int j = 0; j < FL_TUNE_LAYOUTS; ++j) {
         if (us_per_sweep) us_per_sweep[j] = -1.0;
         const int lanes = layouts[j];
         if (lanes == FL_ROWS_SLOTS && p->sl.words == 0) continue;
-        if (lanes == FL_ROWS_SLOTS_WIN && !window_ok(p)) continue;
         PrArgs a;
         int grid = 0, init_grid = 0;
         st = prepare_pr(ctx, p, r, lanes, a, grid, init_grid);
@@ -1202,6 +1201,7 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     memset(&bm, 0, sizeof bm);
     bm.rec = p->rec;
     bm.presence = p->presence;
+    bm.k_pad = k_pad_of(p->sl);
     bm.off = p->d_off;
     bm.valid_raw = p->valid_raw;
     bm.out_deg = p->out_deg;

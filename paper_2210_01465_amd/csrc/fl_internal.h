@@ -17,9 +17,7 @@ constexpr int kXcds = 8;                          // MI355X: 8 XCDs, workgroups 
 constexpr int kBatch = 16;                        // candidate slots whose loads are issued together
 constexpr int kMaxFinishGrid = 1024;              // workgroups of the batched step kernel (grid-stride)
 constexpr int kFinishBlock = 1024;                // threads of a step kernel workgroup (1 mod 3)
-constexpr int kWinCap = 1024;                     // floats of x a wave stages in LDS (windowed slot sweep)
 constexpr int kFillStage = 6144;                  // col_idx entries of a tile assembled in LDS by the fill
-constexpr int kWinMaxOff = 256;                   // largest |slot offset| served from the window
 
 // Mixed-radix description of a search space X = S_1 x ... x S_n, parameter 0
 // most significant: stride[i] = prod_{j>i} radix[j].  Digits are peeled off
@@ -48,7 +46,6 @@ struct SpaceDesc {
 struct SlotTable {
     int32_t k;
     int32_t words;
-    int32_t win_t, win_lo, win_hi;  // slots [win_lo, win_hi) have |off| <= win_t <= kWinMaxOff (0: none)
     int32_t off[kMaxSlots];
     int16_t delta[kMaxSlots];
     uint8_t dim[kMaxSlots];
@@ -90,7 +87,7 @@ struct PrState {
 // Row formats of the PageRank sweep.
 enum SweepKind : int32_t {
     kSweepCsr = 0,   // pull over the CSR, L lanes per row, x indexed by node id
-    kSweepSlots = 1  // pull over the in-edge slot masks, x indexed by raw index
+    kSweepSlots = 1  // pull over the records' in-edge slot bits, x indexed by raw index
 };
 
 struct PrArgs {
@@ -100,8 +97,10 @@ struct PrArgs {
     const int32_t *valid_raw;
     const uint64_t *rec;    // node records (SlotTable), slot sweep only
     const uint64_t *presence;  // per wave of 64 nodes: OR of their in-edge slot bits
-    const int32_t *off;     // slot raw-index offsets (device copy of SlotTable.off)
+    const int32_t *off;     // 2 k_pad entries: slot raw-index offsets (SlotTable.off, 0 past k_slots),
+                            // then the byte offsets 4 (off[s] - off[0]) of the buffer-load sweep
     int32_t k_slots;
+    int32_t k_pad;          // stride of off's two halves: k_slots rounded up to 64, plus 64
     float *y[2];            // ping-pong iterate (node ids), slot k&1 holds y_k
     float *x[2];            // y / out_deg (0 at sinks): node ids (CSR) or raw indices (slots)
     double *partials;       // 3 doubles per tile (slot sweep) or per workgroup (CSR sweep)
@@ -112,9 +111,8 @@ struct PrArgs {
     double tol;
     int32_t max_iter;
     int32_t adjacent;
-    int32_t x_bytes;        // bytes of each x buffer (n_raw rounded up to 4 floats) when < 2^31, else 0
-    int32_t win_t;          // windowed slot sweep: slots [win_lo, win_hi) have |off| <= win_t; 0 = off
-    int32_t win_lo, win_hi;
+    int32_t x_bytes;        // slot sweep: bytes its buffer loads span (x from the most negative slot
+                            // offset to the end plus the largest), when < 2^31; else 0 (plain loads)
     int32_t exact;          // 1: Jacobi sweeps u <- 1 + d P u to an exact fixed point (s = c = 1)
 };
 
@@ -123,7 +121,7 @@ struct PrArgs {
 struct BatchMember {
     const uint64_t *rec;       // node records
     const uint64_t *presence;  // per-wave slot presence
-    const int32_t *off;        // slot raw-index offsets (k_slots, ascending)
+    const int32_t *off;        // 2 k_pad entries, as in PrArgs
     const int32_t *valid_raw;
     const int32_t *out_deg;
     const int32_t *minima;
@@ -135,7 +133,7 @@ struct BatchMember {
     double *out_pagerank;      // caller's outputs
     int32_t *out_minima;
     double d, tol, threshold;
-    int32_t n, m, k_slots, words, x_bytes, n_tiles, max_iter, pad;
+    int32_t n, m, k_slots, k_pad, words, x_bytes, n_tiles, max_iter;
 };
 
 struct TileRef {

@@ -149,15 +149,6 @@ struct Record {
     __device__ __forceinline__ int32_t out_deg() const { return (int32_t)((w[W - 1] >> 24) & 0xffu); }
 };
 
-// Bits [lo, hi) of a 32-bit word, clipped to [0, 32).
-__device__ __forceinline__ uint32_t bit_range32(int32_t lo, int32_t hi) {
-    lo = max(lo, 0);
-    hi = min(hi, 32);
-    if (hi <= lo) return 0u;
-    const uint32_t upto = hi >= 32 ? ~0u : ((1u << hi) - 1u);
-    return upto & ~((1u << lo) - 1u);
-}
-
 // Slot bits of batch b (slots 32b .. 32b+31) that name real slots: the last
 // record word also carries out_deg and the raw index above slot k.
 __device__ __forceinline__ uint32_t batch_mask(int b, int k) {
@@ -896,38 +887,44 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
 // Slot sweep of one tile of kBlock nodes: one node per lane, 64 consecutive
 // nodes per wave.  For every candidate slot whose in-edge bit is set, gather
 // x at raw index i + off[s] (x lives in raw-index space, so neither col_idx
-// nor an index remap is read).  A slot no lane of the wave needs is skipped
-// with a scalar branch on the wave's presence word; for the others, lanes
-// whose bit is clear skip the load under the execution mask (measured
-// cheaper in the texture path than issuing it with an out-of-range offset,
-// which costs address cycles for every lane).  Slots run in ascending
-// raw-index order, the order of the CSR rows, so the FP32 sum equals the
-// one-lane-per-row CSR sweep's bit for bit.  The plain and the batched sweep
-// both run this routine, so their results agree bit for bit.
+// nor an index remap is read).  The wave's lanes that have slot s as an
+// in-edge are given by one 64-bit mask per (wave, slot), written by the
+// degree pass and read here through the scalar unit: a zero mask skips the
+// slot with a scalar branch, any other becomes the execution mask of the
+// slot's load directly, so a slot costs no per-lane bit test.  The slot's
+// offset goes into the load's scalar offset (the buffer base is moved down by
+// the most negative offset so that every scalar offset is >= 0), leaving
+// the zeroing of the register and the add as the only vector work per slot.
+// Slots run in ascending raw-index order, the order of the CSR rows, so the
+// FP32 sum equals the one-lane-per-row CSR sweep's bit for bit.  The plain
+// and the batched sweep both run this routine, so their results agree bit
+// for bit.
 struct SweepTile {
-    const uint64_t *rec;
-    const_ptr<uint64_t> presence;  // per wave of 64 nodes
-    const_ptr<int32_t> off;        // slot offsets
+    const uint64_t *rec;         // node records
+    const_ptr<int32_t> off;      // [k_pad] slot offsets, ascending (off[0] the most negative),
+                                 // then [k_pad] byte offsets 4 (off[s] - off[0])
     const float *y_in, *x_in;
     float *y_out, *x_out;
     double *partials;
     double s, c, sd;
-    int32_t n, k_slots, x_bytes;
-    int32_t win_t, win_lo, win_hi;  // window slots [win_lo, win_hi): |off| <= win_t (0: none)
+    int32_t n, k_slots, k_pad, x_bytes;
 };
 
-// With WIN, each wave first copies x[base, base + len) into its own LDS row,
-// where [base, base + len) covers its nodes' raw indices widened by win_t on
-// both sides (base rounded down to a multiple of 4, len <= kWinCap), using a
-// few dense 16-byte loads; the window slots then read x from LDS instead of
-// gathering it through the texture path.  A wave whose nodes span too wide a
-// raw range (it straddles a hole of excluded configurations) gathers every
-// slot as without WIN.  Values and their order of addition do not change, so
-// the result is the same bit for bit.
-template <int W, bool BUF, bool WIN>
+// Slots per batch of the slot sweep.  All loads of a batch are issued before
+// its first addition; because each load sits under its own execution-mask
+// branch, the compiler cannot count the loads in flight and waits for the
+// whole batch before adding, so a larger batch keeps more loads in flight per
+// wave.  48 (three scalar loads of 16 offsets) measured fastest: 32 drains
+// more often, 64 and 96 lower the occupancy (80 and 112 VGPRs).
+constexpr int kSweepBatch = 48;
+
+template <int W, bool BUF>
 __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
+    // descriptor based at x_in + off[0] (<= x_in), so every slot's byte offset
+    // 4 (off[s] - off[0]) is a non-negative scalar
+    const int32_t off0 = q.off[0];
     const __amdgpu_buffer_rsrc_t xr =
-        __builtin_amdgcn_make_buffer_rsrc((void *)q.x_in, (short)0, q.x_bytes, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)(q.x_in + off0), (short)0, q.x_bytes, 0x00020000);
     const int32_t v = tile * kBlock + threadIdx.x;
     const bool active = v < q.n;
     Record<W> r;
@@ -941,111 +938,77 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
     }
     const int32_t i = r.raw();
     const uint32_t i4 = 4u * (uint32_t)i;
-    // this wave's slot presence, loaded through the scalar unit; a wave past
-    // the last node (in the last tile) has no entry and skips
+    // a wave past the last node (in the last tile) has nothing to gather
     const int32_t first = __builtin_amdgcn_readfirstlane(tile * kBlock + (int32_t)(threadIdx.x & ~63u));
-    const_ptr<uint64_t> pw = q.presence + (int64_t)(first >> 6) * W;
     const bool live = first < q.n;
-    bool use_win = false;
-    int32_t base = 0;
-    float *row = nullptr;
-    if constexpr (WIN) {
-        __shared__ float win[kBlock / 64][kWinCap];
-        row = win[threadIdx.x >> 6];
-        if (live && q.win_t > 0) {
-            const int32_t last = min(63, q.n - 1 - first);   // highest lane holding a node
-            const int32_t lo = __builtin_amdgcn_readfirstlane(i);
-            const int32_t hi = __builtin_amdgcn_readlane(i, last);
-            base = ((lo - q.win_t) >> 2) << 2;                // floor to a multiple of 4
-            const int32_t len = hi + q.win_t + 1 - base;
-            use_win = __builtin_amdgcn_readfirstlane((int32_t)(len <= kWinCap)) != 0;
-            if (use_win) {
-                // negative positions wrap to offsets >= 2^31 and load 0; the
-                // x buffers hold whole 16-byte groups up to x_bytes
-                const int32_t n4 = (len + 3) >> 2;
-                for (int32_t j = (int32_t)(threadIdx.x & 63); j < n4; j += 64) {
-                    const uint32_t byte = 4u * (uint32_t)(base + 4 * j);
-                    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-                    const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(xr, byte, 0, 0);
-                    *reinterpret_cast<u32x4 *>(row + 4 * j) = t;
-                }
-                // the row is read by other lanes of this wave only
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-        }
-    }
+    const_ptr<int32_t> ob = q.off + q.k_pad;
+    // The test of a node's in-edge bit for slot s is one class comparison:
+    // its mask operand is a 10-bit field of the slot bits (slots 32j + 10t ..
+    // 32j + 10t + 9 of word32 j), and its value operand a float whose IEEE
+    // class is bit s mod 10 of the field (signalling NaN, quiet NaN, -inf,
+    // -normal, -denormal, -0, +0, +denormal, +normal, +inf), against an AND
+    // and a compare for a plain bit test.  The empty asm keeps the ten values
+    // in SGPRs instead of re-materialising them per slot.
+    uint32_t cls[10] = {0x7fa00000u, 0x7fc00000u, 0xff800000u, 0xbf800000u, 0x80000001u,
+                        0x80000000u, 0x00000000u, 0x00000001u, 0x3f800000u, 0x7f800000u};
+#pragma unroll
+    for (int j = 0; j < 10; ++j) asm("" : "+s"(cls[j]));
     float acc = 0.0f;
+    asm("" : "+v"(acc));   // keeps the first addition out of the first slot's branch
+    constexpr int kB = kSweepBatch;
 #pragma unroll
-    for (int b = 0; b < 2 * W; ++b) {
-        if (32 * b >= q.k_slots || !live) break;
-        const uint64_t pq = pw[b >> 1];
-        const uint32_t any = (b & 1) ? (uint32_t)(pq >> 32) : (uint32_t)pq;
-        // (no early exit for any == 0 here: a branch around the whole batch
-        // makes the compiler duplicate the unrolled batches into separate
-        // paths and spill them to scratch; the per-slot tests below skip an
-        // empty batch's loads just as well)
-        const uint32_t bits = r.word32(b) & batch_mask(b, q.k_slots);
-        // window slots of this batch (uniform): read from LDS, the others gathered
-        const uint32_t inwin = use_win ? bit_range32(q.win_lo - 32 * b, q.win_hi - 32 * b) : 0u;
-        const uint32_t gl = any & ~inwin, wl = any & inwin;
-        float val[32];
+    for (int b = 0; b < (64 * W + kB - 1) / kB; ++b) {
+        if (kB * b >= q.k_slots || !live) break;
+        float val[kB];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            val[u] = 0.0f;
-            if ((gl >> u) & 1u) {
-                if (BUF) {
+        for (int h = 0; h < kB / 16; ++h) {
+            // 16 offsets in one wide scalar load, ahead of the gathers (the
+            // table is padded past the last batch)
+            typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+            const i32x16 o = *(const __attribute__((address_space(4))) i32x16 *)(
+                (BUF ? ob : q.off) + kB * b + 16 * h);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int u = 16 * h + t, sl = kB * b + u;
+                val[u] = 0.0f;
+                if (sl < 64 * W) {
+                    // word32 of the slot; bits above slot k carry out_deg and
+                    // the raw index and are masked off
+                    const uint32_t wd = (uint32_t)(r.w[sl >> 6] >> (32 * ((sl >> 5) & 1))) &
+                                        batch_mask(sl >> 5, q.k_slots);
                     // lanes without the in-edge skip the load (execution mask)
-                    if ((bits >> u) & 1u)
-                        val[u] = __int_as_float(
-                            __builtin_amdgcn_raw_buffer_load_b32(xr, i4 + 4u * (uint32_t)q.off[32 * b + u], 0, 0));
-                } else {
-                    val[u] = ((bits >> u) & 1u) ? q.x_in[i + q.off[32 * b + u]] : 0.0f;
+                    if (__builtin_amdgcn_classf(__uint_as_float(cls[(sl & 31) % 10]),
+                                                (int)(wd >> (10 * ((sl & 31) / 10))))) {
+                        if (BUF)
+                            val[u] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, i4, (uint32_t)o[t], 0));
+                        else
+                            val[u] = q.x_in[i + o[t]];
+                    }
                 }
             }
         }
-        if constexpr (WIN) {
-            // separate registers, so the LDS reads wait for none of the gathers
-            float lv[32];
 #pragma unroll
-            for (int u = 0; u < 32; ++u) {
-                lv[u] = 0.0f;
-                if ((wl >> u) & 1u) {
-                    const bool on = (bits >> u) & 1u;
-                    const int32_t idx = on ? i + q.off[32 * b + u] - base : 0;   // in [0, len) where on
-                    const float xv = row[idx];
-                    lv[u] = on ? xv : 0.0f;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 32; ++u) acc += ((inwin >> u) & 1u) ? lv[u] : val[u];
-        } else {
-#pragma unroll
-            for (int u = 0; u < 32; ++u) acc += val[u];
-        }
+        for (int u = 0; u < kB; ++u) acc += val[u];
     }
     double ps = 0.0, pr = 0.0, pk = 0.0;
     if (active) {
         const float yf = (float)(q.sd * (double)acc + q.c);
-        const int32_t deg = r.out_deg();
         q.y_out[v] = yf;
-        q.x_out[i] = deg > 0 ? yf / (float)deg : 0.0f;
+        q.x_out[i] = r.out_deg() > 0 ? yf / (float)r.out_deg() : 0.0f;
         ps = (double)yf;
         pr = fabs((double)yf - q.s * (double)yin);
-        if (deg == 0) pk = (double)yf;
+        if (r.out_deg() == 0) pk = (double)yf;
     }
     write_partials(q.partials, tile, ps, pr, pk);
 }
 
-template <int W, bool BUF, bool WIN>
+template <int W, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     const PrState *st = a.st;
     if (st->done) return;
     const int32_t k = st->k;
     SweepTile q;
     q.rec = a.rec;
-    q.presence = to_const(a.presence);
     q.off = to_const(a.off);
     q.y_in = a.y[k & 1];
     q.x_in = a.x[k & 1];
@@ -1057,12 +1020,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     q.sd = q.s * a.d;
     q.n = a.n;
     q.k_slots = a.k_slots;
+    q.k_pad = a.k_pad;
     q.x_bytes = a.x_bytes;
-    q.win_t = a.win_t;
-    q.win_lo = a.win_lo;
-    q.win_hi = a.win_hi;
     const TileWalk w((a.n + kBlock - 1) / kBlock);
-    for (int32_t t = w.first; t < w.end; t += w.step) sweep_tile<W, BUF, WIN>(q, t);
+    for (int32_t t = w.first; t < w.end; t += w.step) sweep_tile<W, BUF>(q, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1089,7 +1050,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchMember *__res
         const int32_t k = st->k;
         SweepTile q;
         q.rec = m->rec;
-        q.presence = to_const(m->presence);
         q.off = to_const(m->off);
         q.y_in = m->y[k & 1];
         q.x_in = m->x[k & 1];
@@ -1101,10 +1061,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchMember *__res
         q.sd = q.s * m->d;
         q.n = m->n;
         q.k_slots = m->k_slots;
+        q.k_pad = m->k_pad;
         q.x_bytes = m->x_bytes;
-        q.win_t = 0;
-        q.win_lo = q.win_hi = 0;
-        sweep_tile<W, BUF, false>(q, tile);
+        sweep_tile<W, BUF>(q, tile);
     }
 }
 
@@ -1250,8 +1209,7 @@ __global__ __launch_bounds__(kBlock) void k_score(const double *__restrict__ pag
 // when the x vector's byte size leaves room for the out-of-range offset.
 template <int W>
 const void *slot_sweep_fn(const PrArgs &a) {
-    if (a.x_bytes == 0) return (const void *)k_pr_iter_slots<W, false, false>;
-    return a.win_t > 0 ? (const void *)k_pr_iter_slots<W, true, true> : (const void *)k_pr_iter_slots<W, true, false>;
+    return a.x_bytes > 0 ? (const void *)k_pr_iter_slots<W, true> : (const void *)k_pr_iter_slots<W, false>;
 }
 
 const void *slot_sweep_kernel(const PrArgs &a, int words) {

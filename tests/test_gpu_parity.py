@@ -101,13 +101,12 @@ def test_fuzz_parity(ctx, seed):
         check_parity(ctx, s, nb, damping=(0.5, 0.85, 0.9)[seed % 3], p=(0.0, 0.05, 0.15)[seed % 3])
 
 
-ROWS_SLOTS, ROWS_SLOTS_WIN = -1, -2
+ROWS_SLOTS = -1
 
 
-@pytest.mark.parametrize("lanes", [ROWS_SLOTS_WIN, ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lanes", [ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64])
 def test_every_row_mapping(ctx, lanes):
-    """Every sweep layout: the windowed and the plain slot sweep and the CSR
-    sweep with 1..64 lanes."""
+    """Every sweep layout: the slot sweep and the CSR sweep with 1..64 lanes."""
     for nb in ("hamming", "adjacent"):
         check_parity(ctx, synth.tiny(3), nb, row_mapping=lanes)
         check_parity(ctx, synth.fuzz_space(5, max_params=6, max_radix=8), nb, row_mapping=lanes)
@@ -115,12 +114,11 @@ def test_every_row_mapping(ctx, lanes):
 
 
 def test_slot_layouts_agree_bit_for_bit(ctx):
-    """The windowed slot sweep reads the same x values as the plain one and
-    adds them in the same order: identical ranks, also against the one-lane
-    CSR sweep.  The spaces cover waves whose window starts below raw index 0
-    or ends in the last 16-byte group, waves that straddle holes of excluded
-    configurations (no window), a last parameter with offsets up to the
-    window reach and beyond, and both neighbourhoods."""
+    """The slot sweep reads the same x values as the one-lane CSR sweep and
+    adds them in the same order: identical ranks.  The spaces cover waves
+    straddling holes of excluded configurations, slot offsets from 1 to far
+    beyond a wave's span, the most negative offset far below raw index 0,
+    record widths 2 to 5, and both neighbourhoods."""
     import torch
     from paper_2210_01465_amd import api
     rng = np.random.default_rng(17)
@@ -130,7 +128,7 @@ def test_slot_layouts_agree_bit_for_bit(ctx):
     for radix in ((3, 5, 2, 120), (60, 64), (120, 2), (2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3)):
         n_raw = int(np.prod(radix))
         f = np.where(rng.random(n_raw) < 0.3, np.nan, rng.lognormal(0.0, 0.5, n_raw))
-        spaces.append(_space(f"win{radix}", radix, f))
+        spaces.append(_space(f"slots{radix}", radix, f))
     for s in spaces:
         for nb in ("hamming", "adjacent"):
             say(f"layouts agree {s.name} radix={s.radix} nb={nb}")
@@ -140,16 +138,11 @@ def test_slot_layouts_agree_bit_for_bit(ctx):
                 if plan.sizes["mask_words"] == 0:
                     continue
                 outs = {}
-                for lay in (ROWS_SLOTS_WIN, ROWS_SLOTS, 1):
-                    try:
-                        pr, _, info = api.execute(plan, 0.85, 0.05, row_mapping=lay)
-                    except api.FLError:
-                        assert lay == ROWS_SLOTS_WIN   # window unavailable: must be refused, not wrong
-                        continue
+                for lay in (ROWS_SLOTS, 1):
+                    pr, _, info = api.execute(plan, 0.85, 0.05, row_mapping=lay)
                     outs[lay] = (pr.cpu().numpy(), info["iterations"])
-                ref = outs[ROWS_SLOTS]
-                for lay, (pr, it) in outs.items():
-                    assert it == ref[1] and np.array_equal(pr, ref[0]), (s.name, nb, lay)
+                assert outs[ROWS_SLOTS][1] == outs[1][1]
+                assert np.array_equal(outs[ROWS_SLOTS][0], outs[1][0]), (s.name, nb)
             finally:
                 plan.close()
 
@@ -258,7 +251,7 @@ def test_error_paths(ctx):
     plan = api.plan_create(ctx, (8,), ones)
     try:
         for kw in ({"damping": 0.0}, {"damping": 1.0}, {"damping": float("nan")},
-                   {"p": -0.1}, {"p": float("inf")}, {"row_mapping": 3}, {"row_mapping": -3},
+                   {"p": -0.1}, {"p": float("inf")}, {"row_mapping": 3}, {"row_mapping": -2},
                    {"max_iter": -1}):
             args = {"damping": 0.85, "p": 0.05}
             args.update(kw)
@@ -269,10 +262,9 @@ def test_error_paths(ctx):
         plan.close()
     wide = api.plan_create(ctx, (200,), torch.arange(1, 201, dtype=torch.float32, device="cuda"))
     try:
-        for lay in (ROWS_SLOTS, ROWS_SLOTS_WIN):
-            with pytest.raises(api.FLError) as e:
-                api.execute(wide, row_mapping=lay)
-            assert e.value.status == _abi.FL_EINVAL
+        with pytest.raises(api.FLError) as e:
+            api.execute(wide, row_mapping=ROWS_SLOTS)
+        assert e.value.status == _abi.FL_EINVAL
     finally:
         wide.close()
 

@@ -12,7 +12,7 @@ from paper_2210_01465_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = (-2, -1, 1, 2, 4, 8, 16, 32, 64)
+LAYOUTS = (-1, 1, 2, 4, 8, 16, 32, 64)
 
 
 def say(msg):
@@ -71,8 +71,7 @@ def test_tune_without_slot_records(api_mod):
         plan = api.plan_create(ctx, radix, torch.from_numpy(f).cuda(), "hamming")
         assert plan.sizes["mask_words"] == 0
         res = api.tune(plan, sweeps=2)
-        assert -1 not in res["us_per_sweep"] and -2 not in res["us_per_sweep"]
-        assert res["best"] in LAYOUTS[2:]
+        assert -1 not in res["us_per_sweep"] and res["best"] in LAYOUTS[1:]
         pr, mins, info = api.execute(plan, 0.85, 0.05)
         assert info["row_mapping"] == res["best"]
         o = oracle.analyze(radix, f, oracle.HAMMING, 0.85, 0.05)
