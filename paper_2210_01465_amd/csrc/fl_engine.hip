@@ -99,6 +99,7 @@ struct fl_ctx {
     std::vector<hipEvent_t> sweep_ev;  // 2 per launch of the longest chunk so far
     BuildSizes *h_sizes = nullptr;  // pinned
     PrState *h_state = nullptr;     // pinned
+    fl_batch *analyze_batch = nullptr;  // kept by fl_analyze_batch between calls (empty between calls)
 };
 
 struct fl_plan {
@@ -127,10 +128,10 @@ struct fl_plan {
     int pr_grid = 0;
     int32_t *d_off = nullptr;   // 2 k_pad entries in device memory, read by the slot sweep:
                                 // raw-index offsets, then byte offsets from the most negative
-    int32_t h_off[2 * (fl::kMaxSlots + 64)] = {};   // host source of d_off
+                                // (written by the degree kernel)
     // timing
     hipEvent_t ev[7] = {};  // build 0-1, pagerank 2-3, score 4, iteration chunk 5-6
-    bool have_events = false;
+    bool have_events = false;   // created on first use (plans of fl_analyze_batch never time)
     fl_timing timing{};
 };
 
@@ -270,6 +271,9 @@ struct Build {
     fl_plan *p = nullptr;
     fl_status status = FL_OK;
     std::string err;
+    bool timed = true;              // record build events (fl_plan_create)
+    bool shared_sizes = false;      // d_sizes is a slot of a caller-owned array that the
+                                    // caller copies to h_sizes itself (fl_analyze_batch)
     BuildSizes *h_sizes = nullptr;  // pinned slot for this build's sizes
     const float *fit = nullptr;
     int32_t *remap = nullptr, *tile_cnt = nullptr, *tile_bad = nullptr, *tile_off = nullptr;
@@ -290,13 +294,27 @@ void build_fail(Build &b, fl_status st, const char *fmt, ...) {
 }
 
 void build_release_scratch(fl_ctx *ctx, Build &b) {
-    void *bufs[] = {b.remap, b.tile_cnt, b.tile_bad, b.tile_off, b.tile_min, b.d_sizes,
+    void *bufs[] = {b.remap, b.tile_cnt, b.tile_bad, b.tile_off, b.tile_min, b.shared_sizes ? nullptr : b.d_sizes,
                     b.in_deg, b.tile_m, b.tile_moff, b.tile_e, b.tile_eoff};
     for (void *x : bufs) ctx->pool.release(x);
     b.remap = b.tile_cnt = b.tile_bad = b.tile_off = b.in_deg = b.tile_m = b.tile_moff = nullptr;
     b.tile_min = nullptr;
     b.d_sizes = nullptr;
     b.tile_e = b.tile_eoff = nullptr;
+}
+
+// The plan's timing events, created on first use.
+hipError_t ensure_events(fl_plan *p) {
+    if (p->have_events) return hipSuccess;
+    for (int j = 0; j < 7; ++j) {
+        const hipError_t e = hipEventCreate(&p->ev[j]);
+        if (e != hipSuccess) {
+            for (int q = 0; q < j; ++q) (void)hipEventDestroy(p->ev[q]);
+            return e;
+        }
+    }
+    p->have_events = true;
+    return hipSuccess;
 }
 
 void build_abort(fl_ctx *ctx, Build &b) {
@@ -339,13 +357,10 @@ void build_begin(fl_ctx *ctx, Build &b, const fl_space *space, const float *fit,
     p->adjacent = (nb == FL_NB_ADJACENT);
     p->sl = make_slots(sp, p->adjacent);
     p->n_raw = n_raw;
-    for (auto &e : p->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            (void)hipGetLastError();
-            return build_fail(b, FL_EHIP, "hipEventCreate failed");
-        }
+    if (b.timed && ensure_events(p) != hipSuccess) {
+        (void)hipGetLastError();
+        return build_fail(b, FL_EHIP, "hipEventCreate failed");
     }
-    p->have_events = true;
 
     const int64_t c_tiles = (n_raw + fl::kCompactTile - 1) / fl::kCompactTile;
     b.remap = pool_alloc<int32_t>(ctx, n_raw);
@@ -353,18 +368,19 @@ void build_begin(fl_ctx *ctx, Build &b, const fl_space *space, const float *fit,
     b.tile_bad = pool_alloc<int32_t>(ctx, c_tiles);
     b.tile_off = pool_alloc<int32_t>(ctx, c_tiles);
     b.tile_min = pool_alloc<float>(ctx, c_tiles);
-    b.d_sizes = pool_alloc<BuildSizes>(ctx, 1);
+    if (!b.shared_sizes) b.d_sizes = pool_alloc<BuildSizes>(ctx, 1);
     p->valid_raw = pool_alloc<int32_t>(ctx, n_raw);
     p->fit_c = pool_alloc<float>(ctx, n_raw);
     if (!b.remap || !b.tile_cnt || !b.tile_bad || !b.tile_off || !b.tile_min || !b.d_sizes || !p->valid_raw ||
         !p->fit_c)
         return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
-    hipError_t he = hipEventRecord(p->ev[0], s);
+    hipError_t he = b.timed ? hipEventRecord(p->ev[0], s) : hipSuccess;
     if (he == hipSuccess)
         he = fl::launch_compact(fit, sp.n_raw, b.tile_cnt, b.tile_min, b.tile_bad, b.tile_off, b.remap,
                                 p->valid_raw, p->fit_c, b.d_sizes, s);
-    if (he == hipSuccess) he = hipMemcpyAsync(b.h_sizes, b.d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess && !b.shared_sizes)
+        he = hipMemcpyAsync(b.h_sizes, b.d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
     if (he != hipSuccess) build_fail(b, FL_EHIP, "compaction: %s", hipGetErrorString(he));
 }
 
@@ -396,20 +412,11 @@ void build_degree(fl_ctx *ctx, Build &b) {
         !p->minima || (p->sl.words > 0 && (!p->rec || !p->presence || !p->d_off)))
         return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
-    hipError_t he = hipSuccess;
-    if (p->sl.words > 0 && p->sl.k > 0) {
-        const int32_t kp = k_pad_of(p->sl);
-        for (int32_t j = 0; j < p->sl.k; ++j) {
-            p->h_off[j] = p->sl.off[j];
-            // meaningful only where the buffer-load sweep runs (4 span + 64 < 2^31)
-            p->h_off[kp + j] = (int32_t)(uint32_t)(4 * ((int64_t)p->sl.off[j] - p->sl.off[0]));
-        }
-        he = hipMemcpyAsync(p->d_off, p->h_off, sizeof(int32_t) * 2 * kp, hipMemcpyHostToDevice, s);
-    }
-    if (he == hipSuccess) he = fl::launch_degree(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, n, b.in_deg, p->out_deg,
-                                      p->rec, p->presence, b.tile_e, b.tile_m, b.tile_eoff, b.tile_moff,
-                                      b.d_sizes, s);
-    if (he == hipSuccess) he = hipMemcpyAsync(b.h_sizes, b.d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
+    hipError_t he = fl::launch_degree(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, n, b.in_deg, p->out_deg,
+                                      p->rec, p->presence, p->d_off, k_pad_of(p->sl), b.tile_e, b.tile_m,
+                                      b.tile_eoff, b.tile_moff, b.d_sizes, s);
+    if (he == hipSuccess && !b.shared_sizes)
+        he = hipMemcpyAsync(b.h_sizes, b.d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
     if (he != hipSuccess) build_fail(b, FL_EHIP, "degree count: %s", hipGetErrorString(he));
 }
 
@@ -428,14 +435,14 @@ void build_fill(fl_ctx *ctx, Build &b) {
     hipError_t he = fl::launch_fill(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, b.remap, p->rec, p->presence,
                                     (int32_t)p->n, (int32_t)e, b.in_deg, p->out_deg, b.tile_eoff, b.tile_moff,
                                     p->row_ptr, p->col_idx, p->minima, s);
-    if (he == hipSuccess) he = hipEventRecord(p->ev[1], s);
+    if (he == hipSuccess && b.timed) he = hipEventRecord(p->ev[1], s);
     if (he != hipSuccess) build_fail(b, FL_EHIP, "CSR fill: %s", hipGetErrorString(he));
 }
 
 // Stage 4 (after the stream has drained): release scratch, record timing.
 void build_end(fl_ctx *ctx, Build &b) {
     build_release_scratch(ctx, b);
-    if (b.status != FL_OK) return;
+    if (b.status != FL_OK || !b.timed) return;
     b.p->timing.build_ms = elapsed(b.p->ev[0], b.p->ev[1]);
 }
 
@@ -779,6 +786,7 @@ fl_status fl_destroy(fl_ctx *ctx) {
     if (!ctx) return FL_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->analyze_batch) (void)fl_batch_destroy(ctx, ctx->analyze_batch);
     ctx->pool.release_all();
     for (hipEvent_t e : ctx->sweep_ev) (void)hipEventDestroy(e);
     (void)hipHostFree(ctx->h_sizes);
@@ -845,6 +853,7 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
     st = prepare_pr(ctx, p, r, lanes, a, grid, init_grid);
     if (st != FL_OK) return st;
     a.exact = exact ? 1 : 0;
+    FL_HIP(ensure_events(p));
 
     FL_HIP(hipEventRecord(p->ev[2], s));
     FL_HIP(hipMemsetAsync(p->state, 0, sizeof(PrState), s));
@@ -1070,6 +1079,7 @@ fl_status fl_tune(fl_ctx *ctx, fl_plan *p, const fl_params *prm, int32_t sweeps,
     r.tol = 0.0;                // every timed sweep does work
     r.max_iter = sweeps + 1;
     FL_HIP(hipSetDevice(ctx->device));
+    FL_HIP(ensure_events(p));
     hipStream_t s = ctx->stream;
     const int layouts[FL_TUNE_LAYOUTS] = {FL_ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64};
     double best_us = 0.0;
@@ -1454,35 +1464,76 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
     FL_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     // build every FFG with one synchronisation per stage
+    // (untimed builds; every build's sizes in one device array, copied to the
+    // host in one transfer per stage)
     std::vector<Build> builds((size_t)n_spaces);
-    BuildSizes *h_sizes = nullptr;
-    if (n_spaces > 0 &&
-        hipHostMalloc((void **)&h_sizes, sizeof(BuildSizes) * n_spaces, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ctx, FL_ENOMEM, "pinned allocation failed");
+    BuildSizes *h_sizes = nullptr, *d_sizes = nullptr;
+    if (n_spaces > 0) {
+        if (hipHostMalloc((void **)&h_sizes, sizeof(BuildSizes) * n_spaces, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, FL_ENOMEM, "pinned allocation failed");
+        }
+        d_sizes = pool_alloc<BuildSizes>(ctx, n_spaces);
+        if (!d_sizes) {
+            (void)hipHostFree(h_sizes);
+            return fail(ctx, FL_ENOMEM, "device allocation failed");
+        }
     }
+    auto stage_sync = [&]() -> hipError_t {
+        hipError_t e = n_spaces > 0 ? hipMemcpyAsync(h_sizes, d_sizes, sizeof(BuildSizes) * n_spaces,
+                                                     hipMemcpyDeviceToHost, s)
+                                    : hipSuccess;
+        const hipError_t e2 = hipStreamSynchronize(s);
+        return e != hipSuccess ? e : e2;
+    };
     for (int32_t j = 0; j < n_spaces; ++j) {
+        builds[j].timed = false;
+        builds[j].shared_sizes = true;
         builds[j].h_sizes = h_sizes + j;
+        builds[j].d_sizes = d_sizes + j;
         build_begin(ctx, builds[j], &spaces[j], d_fitness_raw[j], nb[j]);
     }
-    (void)hipStreamSynchronize(s);
-    for (auto &bd : builds) build_degree(ctx, bd);
-    (void)hipStreamSynchronize(s);
-    for (auto &bd : builds) build_fill(ctx, bd);
-    hipError_t he = hipStreamSynchronize(s);
+    hipError_t he = stage_sync();
+    if (he == hipSuccess)
+        for (auto &bd : builds) build_degree(ctx, bd);
+    if (he == hipSuccess) he = stage_sync();
+    if (he == hipSuccess)
+        for (auto &bd : builds) build_fill(ctx, bd);
+    const hipError_t hf = hipStreamSynchronize(s);
+    if (he == hipSuccess) he = hf;
     for (auto &bd : builds) {
         if (he != hipSuccess && bd.status == FL_OK) build_fail(bd, FL_EHIP, "%s", hipGetErrorString(he));
         build_end(ctx, bd);
     }
     (void)hipHostFree(h_sizes);
+    ctx->pool.release(d_sizes);
     fl_status worst = FL_OK;
     std::vector<fl_status> status((size_t)n_spaces, FL_OK);
     // PageRank: batchable spaces together, the others one at a time
-    fl_batch *b = nullptr;
-    fl_status st = fl_batch_create(ctx, &b);
+    // (the context keeps one batch for this between calls: its tables and
+    // captured graph are reused; it is empty between calls)
+    fl_status st = FL_OK;
+    if (!ctx->analyze_batch) st = fl_batch_create(ctx, &ctx->analyze_batch);
     if (st != FL_OK) {
+        ctx->analyze_batch = nullptr;
         for (auto &bd : builds) build_abort(ctx, bd);
         return st;
+    }
+    fl_batch *b = ctx->analyze_batch;
+    {
+        // room for every space that may join, reserved once
+        int32_t cap = 0;
+        int64_t tiles = 0;
+        for (auto &bd : builds)
+            if (bd.status == FL_OK && bd.p->sl.words > 0 && x_bytes_of(bd.p) > 0) {
+                ++cap;
+                tiles += tiles_of(bd.p);
+            }
+        if (cap > 0) st = batch_reserve(b, (int)b->members.size() + cap, tiles);
+        if (st != FL_OK) {
+            for (auto &bd : builds) build_abort(ctx, bd);
+            return st;
+        }
     }
     int32_t in_batch = 0;
     for (int32_t j = 0; j < n_spaces; ++j) {
@@ -1528,7 +1579,10 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
         } while (got == 64);
     }
     const std::string msg = ctx->err;
-    fl_batch_destroy(ctx, b);
+    if (st != FL_OK || !b->members.empty()) {   // not drained: start afresh next time
+        fl_batch_destroy(ctx, b);
+        ctx->analyze_batch = nullptr;
+    }
     for (auto &bd : builds)
         if (bd.p) fl_plan_destroy(ctx, bd.p);
     ctx->err = msg;

@@ -148,8 +148,9 @@ hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, fl
                           hipStream_t stream);
 hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                          const int32_t *valid_raw, int32_t n, int32_t *in_deg, int32_t *out_deg,
-                         uint64_t *rec, uint64_t *presence, int64_t *tile_e, int32_t *tile_m,
-                         int64_t *tile_eoff, int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream);
+                         uint64_t *rec, uint64_t *presence, int32_t *off_table, int32_t k_pad,
+                         int64_t *tile_e, int32_t *tile_m, int64_t *tile_eoff, int32_t *tile_moff,
+                         BuildSizes *sizes, hipStream_t stream);
 hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                        const int32_t *valid_raw, const int32_t *remap, const uint64_t *rec,
                        const uint64_t *presence, int32_t n, int32_t n_edges, const int32_t *in_deg,

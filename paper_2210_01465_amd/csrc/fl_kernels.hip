@@ -321,9 +321,19 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
                                                          int32_t *__restrict__ out_deg,
                                                          uint64_t *__restrict__ rec,
                                                          uint64_t *__restrict__ presence,
+                                                         int32_t *__restrict__ off_table, int32_t k_pad,
                                                          int64_t *__restrict__ tile_e,
                                                          int32_t *__restrict__ tile_m,
                                                          BuildSizes *__restrict__ sizes) {
+    if (blockIdx.x == 0) {
+        // the sweep's offset table: raw offsets, then byte offsets from the
+        // most negative (meaningful where the buffer-load sweep runs), 0 past k
+        for (int32_t j = threadIdx.x; j < k_pad; j += kBlock) {
+            const bool real = j < sl.k;
+            off_table[j] = real ? sl.off[j] : 0;
+            off_table[k_pad + j] = real ? (int32_t)(4u * ((uint32_t)sl.off[j] - (uint32_t)sl.off[0])) : 0;
+        }
+    }
     const int32_t v = blockIdx.x * kBlock + threadIdx.x;
     const bool active = v < n;
     const uint32_t i = active ? (uint32_t)valid_raw[v] : 0u;
@@ -1262,8 +1272,9 @@ static const void *degree_slots_kernel(bool buf) {
 
 hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                          const int32_t *valid_raw, int32_t n, int32_t *in_deg, int32_t *out_deg,
-                         uint64_t *rec, uint64_t *presence, int64_t *tile_e, int32_t *tile_m,
-                         int64_t *tile_eoff, int32_t *tile_moff, BuildSizes *sizes, hipStream_t stream) {
+                         uint64_t *rec, uint64_t *presence, int32_t *off_table, int32_t k_pad,
+                         int64_t *tile_e, int32_t *tile_m, int64_t *tile_eoff, int32_t *tile_moff,
+                         BuildSizes *sizes, hipStream_t stream) {
     const int32_t tiles = (n + kBlock - 1) / kBlock;
     if (sl.words > 0) {
         // buffer loads of the fitness need 4 n_raw < 2^31 (room for the out-of-range bit)
@@ -1282,8 +1293,8 @@ hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent,
         SlotTable t = sl;
         void *args[] = {(void *)&d,      (void *)&t,       (void *)&fit,      (void *)&fit_bytes,
                         (void *)&valid_raw, (void *)&n,    (void *)&in_deg,   (void *)&out_deg,
-                        (void *)&rec,    (void *)&presence, (void *)&tile_e, (void *)&tile_m,
-                        (void *)&sizes};
+                        (void *)&rec,    (void *)&presence, (void *)&off_table, (void *)&k_pad,
+                        (void *)&tile_e, (void *)&tile_m,   (void *)&sizes};
         hipError_t e = hipLaunchKernel(fn, dim3(tiles), dim3(kBlock), args, 0, stream);
         if (e != hipSuccess) return e;
     }
