@@ -100,6 +100,12 @@ struct fl_ctx {
     BuildSizes *h_sizes = nullptr;  // pinned
     PrState *h_state = nullptr;     // pinned
     fl_batch *analyze_batch = nullptr;  // kept by fl_analyze_batch between calls (empty between calls)
+    // pinned tables of the segmented build (fl_analyze_batch), grown on demand
+    fl::SegBuild *h_segs = nullptr;
+    fl::SegTile *h_seg_tiles = nullptr;
+    int32_t *h_seg_ids = nullptr;
+    int32_t seg_cap = 0;
+    int64_t seg_tile_cap = 0;
 };
 
 struct fl_plan {
@@ -274,6 +280,9 @@ struct Build {
     bool timed = true;              // record build events (fl_plan_create)
     bool shared_sizes = false;      // d_sizes is a slot of a caller-owned array that the
                                     // caller copies to h_sizes itself (fl_analyze_batch)
+    bool defer = false;             // allocate only: the caller launches the stage's kernels for
+                                    // many builds at once (segmented build; slot spaces and
+                                    // compaction only, the generic kernels still launch here)
     BuildSizes *h_sizes = nullptr;  // pinned slot for this build's sizes
     const float *fit = nullptr;
     int32_t *remap = nullptr, *tile_cnt = nullptr, *tile_bad = nullptr, *tile_off = nullptr;
@@ -376,7 +385,7 @@ void build_begin(fl_ctx *ctx, Build &b, const fl_space *space, const float *fit,
         return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
     hipError_t he = b.timed ? hipEventRecord(p->ev[0], s) : hipSuccess;
-    if (he == hipSuccess)
+    if (he == hipSuccess && !b.defer)
         he = fl::launch_compact(fit, sp.n_raw, b.tile_cnt, b.tile_min, b.tile_bad, b.tile_off, b.remap,
                                 p->valid_raw, p->fit_c, b.d_sizes, s);
     if (he == hipSuccess && !b.shared_sizes)
@@ -412,6 +421,7 @@ void build_degree(fl_ctx *ctx, Build &b) {
         !p->minima || (p->sl.words > 0 && (!p->rec || !p->presence || !p->d_off)))
         return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
+    if (b.defer && p->sl.words > 0) return;
     hipError_t he = fl::launch_degree(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, n, b.in_deg, p->out_deg,
                                       p->rec, p->presence, p->d_off, k_pad_of(p->sl), b.tile_e, b.tile_m,
                                       b.tile_eoff, b.tile_moff, b.d_sizes, s);
@@ -432,6 +442,7 @@ void build_fill(fl_ctx *ctx, Build &b) {
     p->col_idx = pool_alloc<int32_t>(ctx, e);
     if (!p->col_idx) return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
+    if (b.defer && p->sl.words > 0) return;
     hipError_t he = fl::launch_fill(p->sp, p->sl, p->adjacent, b.fit, p->valid_raw, b.remap, p->rec, p->presence,
                                     (int32_t)p->n, (int32_t)e, b.in_deg, p->out_deg, b.tile_eoff, b.tile_moff,
                                     p->row_ptr, p->col_idx, p->minima, s);
@@ -708,6 +719,37 @@ void batch_free_tables(fl_batch *b) {
 
 // Member table, id lists and state snapshots for `cap` members and `tiles`
 // tiles (three regions each).  Only called between steps.
+// Pinned segment tables of the segmented build: room for `segs` spaces and
+// `tiles` tile entries (grown, never shrunk; freed with the context).
+fl_status seg_tables_reserve(fl_ctx *ctx, int32_t segs, int64_t tiles) {
+    if (segs > ctx->seg_cap) {
+        (void)hipHostFree(ctx->h_segs);
+        (void)hipHostFree(ctx->h_seg_ids);
+        ctx->h_segs = nullptr;
+        ctx->h_seg_ids = nullptr;
+        ctx->seg_cap = 0;
+        const int32_t cap = std::max(segs, 64);
+        if (hipHostMalloc((void **)&ctx->h_segs, sizeof(fl::SegBuild) * cap, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->h_seg_ids, sizeof(int32_t) * cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return FL_ENOMEM;
+        }
+        ctx->seg_cap = cap;
+    }
+    if (tiles > ctx->seg_tile_cap) {
+        const int64_t cap = std::max<int64_t>(tiles, 2 * ctx->seg_tile_cap + 4096);
+        (void)hipHostFree(ctx->h_seg_tiles);
+        ctx->h_seg_tiles = nullptr;
+        ctx->seg_tile_cap = 0;
+        if (hipHostMalloc((void **)&ctx->h_seg_tiles, sizeof(fl::SegTile) * cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return FL_ENOMEM;
+        }
+        ctx->seg_tile_cap = cap;
+    }
+    return FL_OK;
+}
+
 fl_status batch_reserve(fl_batch *b, int cap, int64_t tiles) {
     fl_ctx *ctx = b->ctx;
     if (cap <= b->capacity && tiles <= b->tile_cap) return FL_OK;
@@ -787,6 +829,9 @@ fl_status fl_destroy(fl_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->analyze_batch) (void)fl_batch_destroy(ctx, ctx->analyze_batch);
+    (void)hipHostFree(ctx->h_segs);
+    (void)hipHostFree(ctx->h_seg_tiles);
+    (void)hipHostFree(ctx->h_seg_ids);
     ctx->pool.release_all();
     for (hipEvent_t e : ctx->sweep_ev) (void)hipEventDestroy(e);
     (void)hipHostFree(ctx->h_sizes);
@@ -1464,21 +1509,36 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
     FL_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     // build every FFG with one synchronisation per stage
-    // (untimed builds; every build's sizes in one device array, copied to the
-    // host in one transfer per stage)
+    // Segmented build: every stage runs for all spaces in one launch (the
+    // node-tile stages once per record width and buffer form) from a table of
+    // per-space descriptors; the host synchronises once per stage to size the
+    // next one.  Untimed builds; every build's sizes sit in one device array,
+    // copied to the host in one transfer per stage.  Spaces with more than
+    // kMaxSlots candidate slots launch their own generic degree and fill
+    // kernels inside the same stages.
     std::vector<Build> builds((size_t)n_spaces);
     BuildSizes *h_sizes = nullptr, *d_sizes = nullptr;
+    fl::SegBuild *d_segs = nullptr;
+    int32_t *d_ids = nullptr;
+    fl::SegTile *d_tiles = nullptr;
     if (n_spaces > 0) {
         if (hipHostMalloc((void **)&h_sizes, sizeof(BuildSizes) * n_spaces, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return fail(ctx, FL_ENOMEM, "pinned allocation failed");
         }
         d_sizes = pool_alloc<BuildSizes>(ctx, n_spaces);
-        if (!d_sizes) {
+        d_segs = pool_alloc<fl::SegBuild>(ctx, n_spaces);
+        d_ids = pool_alloc<int32_t>(ctx, n_spaces);
+        if (!d_sizes || !d_segs || !d_ids || seg_tables_reserve(ctx, n_spaces, 0) != FL_OK) {
             (void)hipHostFree(h_sizes);
-            return fail(ctx, FL_ENOMEM, "device allocation failed");
+            ctx->pool.release(d_sizes);
+            ctx->pool.release(d_segs);
+            ctx->pool.release(d_ids);
+            return fail(ctx, FL_ENOMEM, "allocation failed");
         }
     }
+    fl::SegBuild *hs = ctx->h_segs;
+    int32_t *hid = ctx->h_seg_ids;
     auto stage_sync = [&]() -> hipError_t {
         hipError_t e = n_spaces > 0 ? hipMemcpyAsync(h_sizes, d_sizes, sizeof(BuildSizes) * n_spaces,
                                                      hipMemcpyDeviceToHost, s)
@@ -1486,19 +1546,139 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
         const hipError_t e2 = hipStreamSynchronize(s);
         return e != hipSuccess ? e : e2;
     };
+    // upload the descriptor table, the id list and `nt` tiles (device tile
+    // buffer regrown from the pool when needed)
+    int64_t d_tile_cap = 0;
+    auto upload = [&](int32_t n_ids, int64_t nt) -> hipError_t {
+        if (nt > d_tile_cap) {
+            ctx->pool.release(d_tiles);
+            d_tiles = pool_alloc<fl::SegTile>(ctx, nt);
+            d_tile_cap = d_tiles ? nt : 0;
+            if (!d_tiles) return hipErrorOutOfMemory;
+        }
+        hipError_t e = hipMemcpyAsync(d_segs, hs, sizeof(fl::SegBuild) * n_spaces, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && n_ids > 0)
+            e = hipMemcpyAsync(d_ids, hid, sizeof(int32_t) * n_ids, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && nt > 0)
+            e = hipMemcpyAsync(d_tiles, ctx->h_seg_tiles, sizeof(fl::SegTile) * nt, hipMemcpyHostToDevice, s);
+        return e;
+    };
+    auto buf_of = [](const fl_plan *p) { return 4 * p->n_raw < (int64_t(1) << 31); };
+    // stage 1: compaction
+    int64_t c_total = 0;
     for (int32_t j = 0; j < n_spaces; ++j) {
-        builds[j].timed = false;
-        builds[j].shared_sizes = true;
-        builds[j].h_sizes = h_sizes + j;
-        builds[j].d_sizes = d_sizes + j;
-        build_begin(ctx, builds[j], &spaces[j], d_fitness_raw[j], nb[j]);
+        Build &bd = builds[j];
+        bd.timed = false;
+        bd.shared_sizes = true;
+        bd.defer = true;
+        bd.h_sizes = h_sizes + j;
+        bd.d_sizes = d_sizes + j;
+        build_begin(ctx, bd, &spaces[j], d_fitness_raw[j], nb[j]);
+        if (bd.status == FL_OK) c_total += (bd.p->n_raw + fl::kCompactTile - 1) / fl::kCompactTile;
     }
-    hipError_t he = stage_sync();
-    if (he == hipSuccess)
-        for (auto &bd : builds) build_degree(ctx, bd);
+    hipError_t he = seg_tables_reserve(ctx, n_spaces, c_total) == FL_OK ? hipSuccess : hipErrorOutOfMemory;
+    int32_t n_ids = 0;
+    int64_t nt = 0;
+    for (int32_t j = 0; j < n_spaces && he == hipSuccess; ++j) {
+        Build &bd = builds[j];
+        if (bd.status != FL_OK) continue;
+        const fl_plan *p = bd.p;
+        fl::SegBuild &g = hs[j];
+        memset(&g, 0, sizeof g);
+        g.sp = p->sp;
+        g.sl = p->sl;
+        g.fit = bd.fit;
+        g.tile_cnt = bd.tile_cnt;
+        g.tile_bad = bd.tile_bad;
+        g.tile_off = bd.tile_off;
+        g.tile_min = bd.tile_min;
+        g.remap = bd.remap;
+        g.valid_raw = p->valid_raw;
+        g.fit_c = p->fit_c;
+        g.sizes = bd.d_sizes;
+        g.c_tiles = (int32_t)((p->n_raw + fl::kCompactTile - 1) / fl::kCompactTile);
+        hid[n_ids++] = j;
+        for (int32_t t = 0; t < g.c_tiles; ++t) ctx->h_seg_tiles[nt++] = {j, t};
+    }
+    if (he == hipSuccess) he = upload(n_ids, nt);
+    if (he == hipSuccess) he = fl::launch_seg_compact(d_segs, d_tiles, (int32_t)nt, d_ids, n_ids, s);
     if (he == hipSuccess) he = stage_sync();
-    if (he == hipSuccess)
+    // stages 2 and 3 run the slot builds grouped by (record width, buffer form)
+    int64_t group_begin[fl::kMaxWords + 1][2] = {}, group_count[fl::kMaxWords + 1][2] = {};
+    auto group_tiles = [&]() -> hipError_t {
+        int64_t total = 0;
+        for (auto &bd : builds)
+            if (bd.status == FL_OK && bd.p->sl.words > 0) total += tiles_of(bd.p);
+        if (seg_tables_reserve(ctx, n_spaces, total) != FL_OK) return hipErrorOutOfMemory;
+        nt = 0;
+        n_ids = 0;
+        for (int w = 1; w <= fl::kMaxWords; ++w)
+            for (int q = 0; q < 2; ++q) {
+                group_begin[w][q] = nt;
+                for (int32_t j = 0; j < n_spaces; ++j) {
+                    const Build &bd = builds[j];
+                    if (bd.status != FL_OK || bd.p->sl.words != w || (int)buf_of(bd.p) != q) continue;
+                    for (int32_t t = 0; t < tiles_of(bd.p); ++t) ctx->h_seg_tiles[nt++] = {j, t};
+                    hid[n_ids++] = j;
+                }
+                group_count[w][q] = nt - group_begin[w][q];
+            }
+        return hipSuccess;
+    };
+    // stage 2: degree count (allocations in build_degree; generic spaces launch there)
+    if (he == hipSuccess) {
+        for (auto &bd : builds) build_degree(ctx, bd);
+        he = group_tiles();
+    }
+    for (int32_t j = 0; j < n_spaces && he == hipSuccess; ++j) {
+        const Build &bd = builds[j];
+        if (bd.status != FL_OK || bd.p->sl.words == 0) continue;
+        const fl_plan *p = bd.p;
+        fl::SegBuild &g = hs[j];
+        g.n = (int32_t)p->n;
+        g.n_tiles = tiles_of(p);
+        g.in_deg = bd.in_deg;
+        g.out_deg = p->out_deg;
+        g.rec = p->rec;
+        g.presence = p->presence;
+        g.off_table = p->d_off;
+        g.k_pad = k_pad_of(p->sl);
+        g.tile_e = bd.tile_e;
+        g.tile_eoff = bd.tile_eoff;
+        g.tile_m = bd.tile_m;
+        g.tile_moff = bd.tile_moff;
+        g.fit_bytes = buf_of(p) ? (int32_t)(4 * p->n_raw) : 0;
+        g.remap_bytes = g.fit_bytes;
+    }
+    if (he == hipSuccess) he = upload(n_ids, nt);
+    for (int w = 1; w <= fl::kMaxWords && he == hipSuccess; ++w)
+        for (int q = 0; q < 2 && he == hipSuccess; ++q)
+            if (group_count[w][q] > 0)
+                he = fl::launch_seg_degree(d_segs, d_tiles + group_begin[w][q], (int32_t)group_count[w][q], w,
+                                           q != 0, s);
+    if (he == hipSuccess) he = fl::launch_seg_degree_scan(d_segs, d_ids, n_ids, s);
+    if (he == hipSuccess) he = stage_sync();
+    // stage 3: CSR fill (col_idx allocated in build_fill; generic spaces launch there)
+    if (he == hipSuccess) {
         for (auto &bd : builds) build_fill(ctx, bd);
+        he = group_tiles();
+    }
+    for (int32_t j = 0; j < n_spaces && he == hipSuccess; ++j) {
+        const Build &bd = builds[j];
+        if (bd.status != FL_OK || bd.p->sl.words == 0) continue;
+        const fl_plan *p = bd.p;
+        fl::SegBuild &g = hs[j];
+        g.n_edges = (int32_t)p->e;
+        g.row_ptr = p->row_ptr;
+        g.col_idx = p->col_idx;
+        g.minima = p->minima;
+    }
+    if (he == hipSuccess) he = upload(n_ids, nt);
+    for (int w = 1; w <= fl::kMaxWords && he == hipSuccess; ++w)
+        for (int q = 0; q < 2 && he == hipSuccess; ++q)
+            if (group_count[w][q] > 0)
+                he = fl::launch_seg_fill(d_segs, d_tiles + group_begin[w][q], (int32_t)group_count[w][q], w,
+                                         q != 0, s);
     const hipError_t hf = hipStreamSynchronize(s);
     if (he == hipSuccess) he = hf;
     for (auto &bd : builds) {
@@ -1507,6 +1687,9 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
     }
     (void)hipHostFree(h_sizes);
     ctx->pool.release(d_sizes);
+    ctx->pool.release(d_segs);
+    ctx->pool.release(d_ids);
+    ctx->pool.release(d_tiles);
     fl_status worst = FL_OK;
     std::vector<fl_status> status((size_t)n_spaces, FL_OK);
     // PageRank: batchable spaces together, the others one at a time

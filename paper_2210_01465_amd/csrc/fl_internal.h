@@ -67,6 +67,35 @@ struct BuildSizes {
     int32_t pad;
 };
 
+// One space of a segmented build: every space of a batch runs each build
+// stage in the same launch (the node-tile stages once per record width and
+// buffer form), each workgroup finding its space and tile in a tile list.
+// Fields are filled stage by stage as the sizes become known on the host.
+struct SegBuild {
+    SpaceDesc sp;
+    SlotTable sl;
+    const float *fit;
+    // compaction (sizes known from n_raw)
+    int32_t *tile_cnt, *tile_bad, *tile_off;
+    float *tile_min;
+    int32_t *remap, *valid_raw;
+    float *fit_c;
+    BuildSizes *sizes;
+    // degree pass (after the compaction: N)
+    int32_t *in_deg, *out_deg;
+    uint64_t *rec, *presence;
+    int32_t *off_table;
+    int64_t *tile_e, *tile_eoff;
+    int32_t *tile_m, *tile_moff;
+    // CSR fill (after the degree pass: E)
+    int32_t *row_ptr, *col_idx, *minima;
+    int32_t c_tiles, n_tiles, n, n_edges, k_pad, fit_bytes, remap_bytes, pad;
+};
+struct SegTile {
+    int32_t seg, tile;
+};
+
+
 // Power-iteration state, device resident.  The stored iterate y_k is the
 // normalised rank vector up to the factor s = 1/sum(y_k).
 struct PrState {
@@ -146,6 +175,15 @@ hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, fl
                           int32_t *tile_bad, int32_t *tile_off, int32_t *remap,
                           int32_t *valid_raw, float *fit_c, BuildSizes *sizes,
                           hipStream_t stream);
+// Segmented build stages (see SegBuild): `tiles` lists (space, tile) pairs,
+// `ids` the spaces of the one-workgroup-per-space scans.
+hipError_t launch_seg_compact(const SegBuild *segs, const SegTile *tiles, int32_t n_tiles, const int32_t *ids,
+                              int32_t n_ids, hipStream_t stream);
+hipError_t launch_seg_degree(const SegBuild *segs, const SegTile *tiles, int32_t n_tiles, int words, bool buf,
+                             hipStream_t stream);
+hipError_t launch_seg_degree_scan(const SegBuild *segs, const int32_t *ids, int32_t n_ids, hipStream_t stream);
+hipError_t launch_seg_fill(const SegBuild *segs, const SegTile *tiles, int32_t n_tiles, int words, bool buf,
+                           hipStream_t stream);
 hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent, const float *fit,
                          const int32_t *valid_raw, int32_t n, int32_t *in_deg, int32_t *out_deg,
                          uint64_t *rec, uint64_t *presence, int32_t *off_table, int32_t k_pad,

@@ -40,6 +40,13 @@ __device__ __forceinline__ const_ptr<T> to_const(const T *p) {
     return (const_ptr<T>)p;
 }
 
+// The first (here: only) argument of a kernel, in place in the kernel-argument
+// segment: explicit arguments start at its offset 0.
+template <class T>
+__device__ __forceinline__ const_ptr<T> kernel_arg() {
+    return (const_ptr<T>)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll
@@ -200,11 +207,10 @@ __device__ __forceinline__ int bits_below(const Record<W> &r, int s) {
 // Compaction: valid points in ascending raw order (Sec. III-B; failed and
 // constraint-violating configurations are excluded, Sec. V), f_opt.
 
-__global__ __launch_bounds__(kBlock) void k_compact_count(const float *__restrict__ fit, int32_t n_raw,
-                                                          int32_t *__restrict__ tile_cnt,
-                                                          float *__restrict__ tile_min,
-                                                          int32_t *__restrict__ tile_bad) {
-    const int64_t base = (int64_t)blockIdx.x * kCompactTile;
+__device__ __forceinline__ void compact_count(const float *__restrict__ fit, int32_t n_raw, int32_t tile,
+                                              int32_t *__restrict__ tile_cnt, float *__restrict__ tile_min,
+                                              int32_t *__restrict__ tile_bad) {
+    const int64_t base = (int64_t)tile * kCompactTile;
     int32_t cnt = 0, bad = 0;
     float mn = INFINITY;
 #pragma unroll
@@ -222,17 +228,23 @@ __global__ __launch_bounds__(kBlock) void k_compact_count(const float *__restric
     bad = block_sum(bad);
     mn = block_min(mn);
     if (threadIdx.x == 0) {
-        tile_cnt[blockIdx.x] = cnt;
-        tile_bad[blockIdx.x] = bad;
-        tile_min[blockIdx.x] = mn;
+        tile_cnt[tile] = cnt;
+        tile_bad[tile] = bad;
+        tile_min[tile] = mn;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact_scan(const int32_t *__restrict__ tile_cnt,
-                                                         const float *__restrict__ tile_min,
-                                                         const int32_t *__restrict__ tile_bad,
-                                                         int32_t n_tiles, int32_t *__restrict__ tile_off,
-                                                         BuildSizes *__restrict__ sizes) {
+__global__ __launch_bounds__(kBlock) void k_compact_count(const float *__restrict__ fit, int32_t n_raw,
+                                                          int32_t *__restrict__ tile_cnt,
+                                                          float *__restrict__ tile_min,
+                                                          int32_t *__restrict__ tile_bad) {
+    compact_count(fit, n_raw, blockIdx.x, tile_cnt, tile_min, tile_bad);
+}
+
+__device__ __forceinline__ void compact_scan(const int32_t *__restrict__ tile_cnt,
+                                             const float *__restrict__ tile_min,
+                                             const int32_t *__restrict__ tile_bad, int32_t n_tiles,
+                                             int32_t *__restrict__ tile_off, BuildSizes *__restrict__ sizes) {
     const int32_t n_valid = scan_tiles(tile_cnt, tile_off, n_tiles);
     int32_t bad = 0;
     float mn = INFINITY;
@@ -250,13 +262,19 @@ __global__ __launch_bounds__(kBlock) void k_compact_scan(const int32_t *__restri
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact_write(const float *__restrict__ fit, int32_t n_raw,
-                                                          const int32_t *__restrict__ tile_off,
-                                                          int32_t *__restrict__ remap,
-                                                          int32_t *__restrict__ valid_raw,
-                                                          float *__restrict__ fit_c) {
+__global__ __launch_bounds__(kBlock) void k_compact_scan(const int32_t *__restrict__ tile_cnt,
+                                                         const float *__restrict__ tile_min,
+                                                         const int32_t *__restrict__ tile_bad,
+                                                         int32_t n_tiles, int32_t *__restrict__ tile_off,
+                                                         BuildSizes *__restrict__ sizes) {
+    compact_scan(tile_cnt, tile_min, tile_bad, n_tiles, tile_off, sizes);
+}
+
+__device__ __forceinline__ void compact_write(const float *__restrict__ fit, int32_t n_raw, int32_t tile,
+                                              const int32_t *__restrict__ tile_off, int32_t *__restrict__ remap,
+                                              int32_t *__restrict__ valid_raw, float *__restrict__ fit_c) {
     // blocked: thread t owns raw indices base + t*8 .. base + t*8 + 7
-    const int64_t base = (int64_t)blockIdx.x * kCompactTile + (int64_t)threadIdx.x * kCompactItems;
+    const int64_t base = (int64_t)tile * kCompactTile + (int64_t)threadIdx.x * kCompactItems;
     float f[kCompactItems];
     int32_t s = 0;
 #pragma unroll
@@ -266,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_write(const float *__restric
         s += valid_fitness(f[j]);
     }
     int32_t tot;
-    int32_t id = tile_off[blockIdx.x] + block_excl_scan(s, &tot);
+    int32_t id = tile_off[tile] + block_excl_scan(s, &tot);
 #pragma unroll
     for (int j = 0; j < kCompactItems; ++j) {
         const int64_t i = base + j;
@@ -280,6 +298,14 @@ __global__ __launch_bounds__(kBlock) void k_compact_write(const float *__restric
             remap[i] = -1;
         }
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_write(const float *__restrict__ fit, int32_t n_raw,
+                                                          const int32_t *__restrict__ tile_off,
+                                                          int32_t *__restrict__ remap,
+                                                          int32_t *__restrict__ valid_raw,
+                                                          float *__restrict__ fit_c) {
+    compact_write(fit, n_raw, blockIdx.x, tile_off, remap, valid_raw, fit_c);
 }
 
 // ---------------------------------------------------------------------------
@@ -313,19 +339,18 @@ __device__ __forceinline__ void set_bits(uint64_t (&m)[W], int32_t lo, int32_t h
 // a slot no lane of the wave has is skipped with a scalar branch, and lanes
 // without it get the out-of-range buffer offset (the load returns 0, which
 // no comparison below counts).
-template <int W, bool BUF>
-__global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable sl,
-                                                         const float *__restrict__ fit, int32_t fit_bytes,
-                                                         const int32_t *__restrict__ valid_raw, int32_t n,
-                                                         int32_t *__restrict__ in_deg,
-                                                         int32_t *__restrict__ out_deg,
-                                                         uint64_t *__restrict__ rec,
-                                                         uint64_t *__restrict__ presence,
-                                                         int32_t *__restrict__ off_table, int32_t k_pad,
-                                                         int64_t *__restrict__ tile_e,
-                                                         int32_t *__restrict__ tile_m,
-                                                         BuildSizes *__restrict__ sizes) {
-    if (blockIdx.x == 0) {
+// SP and SL are SpaceDesc and SlotTable, either kernel arguments or entries
+// of a segment table in the constant address space (scalar loads either way).
+template <int W, bool BUF, class SP, class SL>
+__device__ __forceinline__ void degree_slots(const SP &sp, const SL &sl, int32_t tile,
+                                             const float *__restrict__ fit, int32_t fit_bytes,
+                                             const int32_t *__restrict__ valid_raw, int32_t n,
+                                             int32_t *__restrict__ in_deg, int32_t *__restrict__ out_deg,
+                                             uint64_t *__restrict__ rec, uint64_t *__restrict__ presence,
+                                             int32_t *__restrict__ off_table, int32_t k_pad,
+                                             int64_t *__restrict__ tile_e, int32_t *__restrict__ tile_m,
+                                             BuildSizes *__restrict__ sizes) {
+    if (tile == 0) {
         // the sweep's offset table: raw offsets, then byte offsets from the
         // most negative (meaningful where the buffer-load sweep runs), 0 past k
         for (int32_t j = threadIdx.x; j < k_pad; j += kBlock) {
@@ -334,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
             off_table[k_pad + j] = real ? (int32_t)(4u * ((uint32_t)sl.off[j] - (uint32_t)sl.off[0])) : 0;
         }
     }
-    const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+    const int32_t v = tile * kBlock + threadIdx.x;
     const bool active = v < n;
     const uint32_t i = active ? (uint32_t)valid_raw[v] : 0u;
     const float fv = active ? fit[i] : 0.0f;
@@ -412,10 +437,20 @@ __global__ __launch_bounds__(kBlock) void k_degree_slots(SpaceDesc sp, SlotTable
     const int32_t tm = block_sum((int32_t)(v < n && dout == 0));
     const int32_t tp = block_sum((int32_t)(v < n && dout == 0 && tie));
     if (threadIdx.x == 0) {
-        tile_e[blockIdx.x] = te;
-        tile_m[blockIdx.x] = tm;
+        tile_e[tile] = te;
+        tile_m[tile] = tm;
         if (tp > 0) atomicAdd(&sizes->n_plateau, tp);
     }
+}
+
+// One space: the descriptor is the kernel's only argument, read in place in
+// the kernel-argument segment (a by-value table passed on by reference would
+// otherwise be copied to private memory).
+template <int W, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_degree_slots([[maybe_unused]] SegBuild arg) {
+    const_ptr<SegBuild> g = kernel_arg<SegBuild>();
+    degree_slots<W, BUF>(g->sp, g->sl, blockIdx.x, g->fit, g->fit_bytes, g->valid_raw, g->n, g->in_deg,
+                         g->out_deg, g->rec, g->presence, g->off_table, g->k_pad, g->tile_e, g->tile_m, g->sizes);
 }
 
 // Generic count for spaces with more than kMaxSlots candidate slots: walks the
@@ -474,17 +509,23 @@ __global__ __launch_bounds__(kBlock) void k_degree_generic(SpaceDesc sp, const f
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_degree_scan(const int64_t *__restrict__ tile_e,
-                                                        const int32_t *__restrict__ tile_m,
-                                                        int32_t n_tiles, int64_t *__restrict__ tile_eoff,
-                                                        int32_t *__restrict__ tile_moff,
-                                                        BuildSizes *__restrict__ sizes) {
+__device__ __forceinline__ void degree_scan(const int64_t *__restrict__ tile_e, const int32_t *__restrict__ tile_m,
+                                            int32_t n_tiles, int64_t *__restrict__ tile_eoff,
+                                            int32_t *__restrict__ tile_moff, BuildSizes *__restrict__ sizes) {
     const int64_t e = scan_tiles(tile_e, tile_eoff, n_tiles);
     const int32_t m = scan_tiles(tile_m, tile_moff, n_tiles);
     if (threadIdx.x == 0) {
         sizes->n_edges = e;
         sizes->n_minima = m;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_degree_scan(const int64_t *__restrict__ tile_e,
+                                                        const int32_t *__restrict__ tile_m,
+                                                        int32_t n_tiles, int64_t *__restrict__ tile_eoff,
+                                                        int32_t *__restrict__ tile_moff,
+                                                        BuildSizes *__restrict__ sizes) {
+    degree_scan(tile_e, tile_m, n_tiles, tile_eoff, tile_moff, sizes);
 }
 
 // ---------------------------------------------------------------------------
@@ -495,12 +536,12 @@ __global__ __launch_bounds__(kBlock) void k_degree_scan(const int64_t *__restric
 // from 0 to x_k - 1; above i, parameters n-1..0 with a rising from x_k + 1.
 
 // Shared prologue: row_ptr and minima for the workgroup's nodes.
-__device__ __forceinline__ void fill_rows(int32_t v, int32_t n, int32_t n_edges, int32_t din, int32_t sink,
-                                          const int64_t *tile_eoff, const int32_t *tile_moff,
+__device__ __forceinline__ void fill_rows(int32_t tile, int32_t v, int32_t n, int32_t n_edges, int32_t din,
+                                          int32_t sink, const int64_t *tile_eoff, const int32_t *tile_moff,
                                           int32_t *row_ptr, int32_t *minima, int32_t &e_off) {
     int32_t tot;
-    e_off = (int32_t)tile_eoff[blockIdx.x] + block_excl_scan(din, &tot);
-    const int32_t m_off = tile_moff[blockIdx.x] + block_excl_scan(sink, &tot);
+    e_off = (int32_t)tile_eoff[tile] + block_excl_scan(din, &tot);
+    const int32_t m_off = tile_moff[tile] + block_excl_scan(sink, &tot);
     if (v < n) {
         row_ptr[v] = e_off;
         if (v == n - 1) row_ptr[n] = n_edges;
@@ -516,26 +557,24 @@ __device__ __forceinline__ void fill_rows(int32_t v, int32_t n, int32_t n_edges,
 // as in the sweep.  The tile's rows are one contiguous range of col_idx; when
 // it fits, it is assembled in LDS and written out with coalesced stores
 // instead of one scattered 4-byte store per edge.
-template <int W, bool BUF>
-__global__ __launch_bounds__(kBlock) void k_fill_slots(SlotTable sl, const int32_t *__restrict__ remap,
-                                                       int32_t remap_bytes, const uint64_t *__restrict__ rec,
-                                                       const uint64_t *__restrict__ presence, int32_t n,
-                                                       int32_t n_edges, const int32_t *__restrict__ in_deg,
-                                                       const int32_t *__restrict__ out_deg,
-                                                       const int64_t *__restrict__ tile_eoff,
-                                                       const int32_t *__restrict__ tile_moff,
-                                                       int32_t *__restrict__ row_ptr,
-                                                       int32_t *__restrict__ col_idx,
-                                                       int32_t *__restrict__ minima) {
+template <int W, bool BUF, class SL>
+__device__ __forceinline__ void fill_slots(const SL &sl, int32_t tile, int32_t n_tiles,
+                                           const int32_t *__restrict__ remap, int32_t remap_bytes,
+                                           const uint64_t *__restrict__ rec, const uint64_t *__restrict__ presence,
+                                           int32_t n, int32_t n_edges, const int32_t *__restrict__ in_deg,
+                                           const int32_t *__restrict__ out_deg,
+                                           const int64_t *__restrict__ tile_eoff,
+                                           const int32_t *__restrict__ tile_moff, int32_t *__restrict__ row_ptr,
+                                           int32_t *__restrict__ col_idx, int32_t *__restrict__ minima) {
     __shared__ int32_t stage[kFillStage];
-    const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+    const int32_t v = tile * kBlock + threadIdx.x;
     const bool active = v < n;
     const int32_t din = active ? in_deg[v] : 0;
     const int32_t sink = (active && out_deg[v] == 0) ? 1 : 0;
     int32_t e_off;
-    fill_rows(v, n, n_edges, din, sink, tile_eoff, tile_moff, row_ptr, minima, e_off);
-    const int64_t e_begin = tile_eoff[blockIdx.x];
-    const int64_t e_end = blockIdx.x + 1 < gridDim.x ? tile_eoff[blockIdx.x + 1] : (int64_t)n_edges;
+    fill_rows(tile, v, n, n_edges, din, sink, tile_eoff, tile_moff, row_ptr, minima, e_off);
+    const int64_t e_begin = tile_eoff[tile];
+    const int64_t e_end = tile + 1 < n_tiles ? tile_eoff[tile + 1] : (int64_t)n_edges;
     const int32_t count = (int32_t)(e_end - e_begin);
     const bool staged = count <= kFillStage;   // uniform over the workgroup
     const __amdgpu_buffer_rsrc_t rr =
@@ -549,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(SlotTable sl, const int32
     }
     const int32_t i = r.raw();
     const uint32_t i4 = 4u * (uint32_t)i;
-    const int32_t first = __builtin_amdgcn_readfirstlane(blockIdx.x * kBlock + (int32_t)(threadIdx.x & ~63u));
+    const int32_t first = __builtin_amdgcn_readfirstlane(tile * kBlock + (int32_t)(threadIdx.x & ~63u));
     const_ptr<uint64_t> pw = to_const(presence) + (int64_t)(first >> 6) * W;
     const bool live = first < n;
     int32_t pos = e_off;
@@ -591,6 +630,62 @@ __global__ __launch_bounds__(kBlock) void k_fill_slots(SlotTable sl, const int32
     }
 }
 
+template <int W, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_fill_slots([[maybe_unused]] SegBuild arg) {
+    const_ptr<SegBuild> g = kernel_arg<SegBuild>();
+    fill_slots<W, BUF>(g->sl, blockIdx.x, gridDim.x, g->remap, g->remap_bytes, g->rec, g->presence, g->n,
+                       g->n_edges, g->in_deg, g->out_deg, g->tile_eoff, g->tile_moff, g->row_ptr, g->col_idx,
+                       g->minima);
+}
+
+// ---------------------------------------------------------------------------
+// Segmented build: the same stages for every space of a batch in one launch.
+
+__global__ __launch_bounds__(kBlock) void k_seg_compact_count(const SegBuild *__restrict__ segs,
+                                                              const SegTile *__restrict__ tiles) {
+    const_ptr<SegTile> t = to_const(tiles) + blockIdx.x;
+    const_ptr<SegBuild> g = to_const(segs) + t->seg;
+    compact_count(g->fit, g->sp.n_raw, t->tile, g->tile_cnt, g->tile_min, g->tile_bad);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_compact_scan(const SegBuild *__restrict__ segs,
+                                                             const int32_t *__restrict__ ids) {
+    const_ptr<SegBuild> g = to_const(segs) + to_const(ids)[blockIdx.x];
+    compact_scan(g->tile_cnt, g->tile_min, g->tile_bad, g->c_tiles, g->tile_off, g->sizes);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_compact_write(const SegBuild *__restrict__ segs,
+                                                              const SegTile *__restrict__ tiles) {
+    const_ptr<SegTile> t = to_const(tiles) + blockIdx.x;
+    const_ptr<SegBuild> g = to_const(segs) + t->seg;
+    compact_write(g->fit, g->sp.n_raw, t->tile, g->tile_off, g->remap, g->valid_raw, g->fit_c);
+}
+
+template <int W, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_seg_degree(const SegBuild *__restrict__ segs,
+                                                       const SegTile *__restrict__ tiles) {
+    const_ptr<SegTile> t = to_const(tiles) + blockIdx.x;
+    const_ptr<SegBuild> g = to_const(segs) + t->seg;
+    degree_slots<W, BUF>(g->sp, g->sl, t->tile, g->fit, g->fit_bytes, g->valid_raw, g->n, g->in_deg, g->out_deg,
+                         g->rec, g->presence, g->off_table, g->k_pad, g->tile_e, g->tile_m, g->sizes);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_degree_scan(const SegBuild *__restrict__ segs,
+                                                            const int32_t *__restrict__ ids) {
+    const_ptr<SegBuild> g = to_const(segs) + to_const(ids)[blockIdx.x];
+    degree_scan(g->tile_e, g->tile_m, g->n_tiles, g->tile_eoff, g->tile_moff, g->sizes);
+}
+
+template <int W, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_seg_fill(const SegBuild *__restrict__ segs,
+                                                     const SegTile *__restrict__ tiles) {
+    const_ptr<SegTile> t = to_const(tiles) + blockIdx.x;
+    const_ptr<SegBuild> g = to_const(segs) + t->seg;
+    fill_slots<W, BUF>(g->sl, t->tile, g->n_tiles, g->remap, g->remap_bytes, g->rec, g->presence, g->n,
+                       g->n_edges, g->in_deg, g->out_deg, g->tile_eoff, g->tile_moff, g->row_ptr, g->col_idx,
+                       g->minima);
+}
+
 // Generic version for spaces with more than kMaxSlots candidate slots.
 template <bool ADJ>
 __global__ __launch_bounds__(kBlock) void k_fill_generic(SpaceDesc sp, const float *__restrict__ fit,
@@ -607,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_generic(SpaceDesc sp, const flo
     const int32_t din = v < n ? in_deg[v] : 0;
     const int32_t sink = (v < n && out_deg[v] == 0) ? 1 : 0;
     int32_t e_off;
-    fill_rows(v, n, n_edges, din, sink, tile_eoff, tile_moff, row_ptr, minima, e_off);
+    fill_rows(blockIdx.x, v, n, n_edges, din, sink, tile_eoff, tile_moff, row_ptr, minima, e_off);
     if (v >= n || din == 0) return;
     const uint32_t i = (uint32_t)valid_raw[v];
     const float fv = fit[i];
@@ -1265,6 +1360,67 @@ hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, fl
     return hipGetLastError();
 }
 
+hipError_t launch_seg_compact(const SegBuild *segs, const SegTile *tiles, int32_t n_tiles, const int32_t *ids,
+                              int32_t n_ids, hipStream_t stream) {
+    if (n_tiles <= 0 || n_ids <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_compact_count, dim3(n_tiles), dim3(kBlock), 0, stream, segs, tiles);
+    hipLaunchKernelGGL(k_seg_compact_scan, dim3(n_ids), dim3(kBlock), 0, stream, segs, ids);
+    hipLaunchKernelGGL(k_seg_compact_write, dim3(n_tiles), dim3(kBlock), 0, stream, segs, tiles);
+    return hipGetLastError();
+}
+
+template <int W>
+static const void *seg_degree_kernel(bool buf) {
+    return buf ? (const void *)k_seg_degree<W, true> : (const void *)k_seg_degree<W, false>;
+}
+
+template <int W>
+static const void *seg_fill_kernel(bool buf) {
+    return buf ? (const void *)k_seg_fill<W, true> : (const void *)k_seg_fill<W, false>;
+}
+
+static hipError_t launch_seg_tiles(const void *fn, const SegBuild *segs, const SegTile *tiles, int32_t n_tiles,
+                                   hipStream_t stream) {
+    if (!fn) return hipErrorInvalidValue;
+    if (n_tiles <= 0) return hipSuccess;
+    void *args[] = {(void *)&segs, (void *)&tiles};
+    return hipLaunchKernel(fn, dim3(n_tiles), dim3(kBlock), args, 0, stream);
+}
+
+hipError_t launch_seg_degree(const SegBuild *segs, const SegTile *tiles, int32_t n_tiles, int words, bool buf,
+                             hipStream_t stream) {
+    const void *fn = nullptr;
+    switch (words) {
+        case 1: fn = seg_degree_kernel<1>(buf); break;
+        case 2: fn = seg_degree_kernel<2>(buf); break;
+        case 3: fn = seg_degree_kernel<3>(buf); break;
+        case 4: fn = seg_degree_kernel<4>(buf); break;
+        case 5: fn = seg_degree_kernel<5>(buf); break;
+        default: break;
+    }
+    return launch_seg_tiles(fn, segs, tiles, n_tiles, stream);
+}
+
+hipError_t launch_seg_degree_scan(const SegBuild *segs, const int32_t *ids, int32_t n_ids, hipStream_t stream) {
+    if (n_ids <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_degree_scan, dim3(n_ids), dim3(kBlock), 0, stream, segs, ids);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_fill(const SegBuild *segs, const SegTile *tiles, int32_t n_tiles, int words, bool buf,
+                           hipStream_t stream) {
+    const void *fn = nullptr;
+    switch (words) {
+        case 1: fn = seg_fill_kernel<1>(buf); break;
+        case 2: fn = seg_fill_kernel<2>(buf); break;
+        case 3: fn = seg_fill_kernel<3>(buf); break;
+        case 4: fn = seg_fill_kernel<4>(buf); break;
+        case 5: fn = seg_fill_kernel<5>(buf); break;
+        default: break;
+    }
+    return launch_seg_tiles(fn, segs, tiles, n_tiles, stream);
+}
+
 template <int W>
 static const void *degree_slots_kernel(bool buf) {
     return buf ? (const void *)k_degree_slots<W, true> : (const void *)k_degree_slots<W, false>;
@@ -1289,12 +1445,23 @@ hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent,
             case 5: fn = degree_slots_kernel<5>(buf); break;
             default: return hipErrorInvalidValue;
         }
-        SpaceDesc d = sp;
-        SlotTable t = sl;
-        void *args[] = {(void *)&d,      (void *)&t,       (void *)&fit,      (void *)&fit_bytes,
-                        (void *)&valid_raw, (void *)&n,    (void *)&in_deg,   (void *)&out_deg,
-                        (void *)&rec,    (void *)&presence, (void *)&off_table, (void *)&k_pad,
-                        (void *)&tile_e, (void *)&tile_m,   (void *)&sizes};
+        SegBuild g{};
+        g.sp = sp;
+        g.sl = sl;
+        g.fit = fit;
+        g.fit_bytes = fit_bytes;
+        g.valid_raw = const_cast<int32_t *>(valid_raw);
+        g.n = n;
+        g.in_deg = in_deg;
+        g.out_deg = out_deg;
+        g.rec = rec;
+        g.presence = presence;
+        g.off_table = off_table;
+        g.k_pad = k_pad;
+        g.tile_e = tile_e;
+        g.tile_m = tile_m;
+        g.sizes = sizes;
+        void *args[] = {(void *)&g};
         hipError_t e = hipLaunchKernel(fn, dim3(tiles), dim3(kBlock), args, 0, stream);
         if (e != hipSuccess) return e;
     }
@@ -1339,10 +1506,22 @@ hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, c
             case 5: fn = fill_slots_kernel<5>(buf); break;
             default: return hipErrorInvalidValue;
         }
-        SlotTable t = sl;
-        void *args[] = {(void *)&t, (void *)&remap, (void *)&remap_bytes, (void *)&rec, (void *)&presence,
-                        (void *)&n, (void *)&n_edges, (void *)&in_deg, (void *)&out_deg, (void *)&tile_eoff,
-                        (void *)&tile_moff, (void *)&row_ptr, (void *)&col_idx, (void *)&minima};
+        SegBuild g{};
+        g.sl = sl;
+        g.remap = const_cast<int32_t *>(remap);
+        g.remap_bytes = remap_bytes;
+        g.rec = const_cast<uint64_t *>(rec);
+        g.presence = const_cast<uint64_t *>(presence);
+        g.n = n;
+        g.n_edges = n_edges;
+        g.in_deg = const_cast<int32_t *>(in_deg);
+        g.out_deg = const_cast<int32_t *>(out_deg);
+        g.tile_eoff = const_cast<int64_t *>(tile_eoff);
+        g.tile_moff = const_cast<int32_t *>(tile_moff);
+        g.row_ptr = row_ptr;
+        g.col_idx = col_idx;
+        g.minima = minima;
+        void *args[] = {(void *)&g};
         return hipLaunchKernel(fn, dim3(tiles), dim3(kBlock), args, 0, stream);
     }
     switch (sl.words) {
