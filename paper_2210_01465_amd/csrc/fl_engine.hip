@@ -1748,7 +1748,7 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
     }
     int32_t running = in_batch;
     while (running > 0 && st != FL_EHIP) {
-        st = fl_batch_step(ctx, b, 8, &running);
+        st = fl_batch_step(ctx, b, 16, &running);   // 16 sweeps per host round trip
         if (st != FL_OK) break;
         int64_t tags[64];
         fl_summary sums[64];
