@@ -106,6 +106,42 @@ def workload(name: str):
     return {"large": synth.large, "mid": synth.mid, "tiny": synth.tiny}[name]()
 
 
+def host_cpu() -> str:
+    """CPU model and logical CPU count of the host (for the baseline line)."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs visible"
+
+
+def copy_bandwidth(n_bytes: int = 1 << 30, repeats: int = 10) -> dict:
+    """Device-to-device copy of n_bytes, timed with HIP events: the HBM rate a
+    plain streaming kernel reaches on this GPU (read + write bytes / time)."""
+    import torch
+    n = n_bytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(repeats):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / repeats
+    gbs = 2 * n * 4 / s / 1e9
+    del src, dst
+    return {"bytes_per_copy": 2 * n * 4, "gb_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "how": f"torch device-to-device copy of {n * 4} bytes, {repeats} copies between HIP events"}
+
+
 def cpu_baseline(space, nb, damping, p, tol):
     import oracle
     t0 = time.perf_counter()
@@ -116,7 +152,8 @@ def cpu_baseline(space, nb, damping, p, tol):
     return a, {"value": round(g.E * a.iterations / t / 1e9, 6), "unit": "GTEPS", "cores": 1,
                "kind": "oracle",
                "sample": f"one whole analysis of the same space ({space.name}, N={g.N}, E={g.E}) "
-                         f"at tol {tol:g}: {a.iterations} FP64 iterations in {t:.2f} s"}
+                         f"at tol {tol:g}: {a.iterations} FP64 iterations in {t:.2f} s, single-threaded, "
+                         f"on {host_cpu()}"}
 
 
 def batched_leg(ctx, damping, p, tol, repeats: int = 3):
@@ -339,8 +376,12 @@ def main():
         "phases_ms": {k: round(float(np.mean([t[k] for t in timings])), 4)
                       for k in ("build_ms", "pagerank_ms", "iterate_ms", "sweep_ms", "score_ms")},
         "analysis_pct_hbm_alg": round(alg_bytes / step_s / (HBM_PEAK_GBS * 1e9), 4),
+        # edges x iterations over the PageRank phase alone (build and score excluded)
+        "gteps_spmv": round(E * info["iterations"] / (float(np.mean([t["pagerank_ms"] for t in timings])) / 1e3)
+                            / 1e9, 3),
         "score": info["score"],
     }
+    out["hbm_copy"] = copy_bandwidth()
     if tuning is not None:
         out["autotune"] = tuning
 

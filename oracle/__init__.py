@@ -69,6 +69,9 @@ def load(path: str = LIB) -> ctypes.CDLL:
     lib.flo_score.restype = ctypes.c_double
     lib.flo_dag_rank.argtypes = [P, ctypes.c_double, P, i64p]
     lib.flo_dag_rank.restype = ctypes.c_int
+    lib.flo_analyze.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P, P]
+    lib.flo_analyze.restype = ctypes.c_int
     _lib_cache[path] = lib
     return lib
 
@@ -194,3 +197,39 @@ def analyze(radix, fitness_raw, neighbourhood: int = HAMMING, damping: float = 0
     r, it, res = g.pagerank(damping, tol, max_iter)
     s, num, den = g.score(r, p)
     return Analysis(g, r, it, res, s, num, den)
+
+
+ESIZE = -6
+
+
+def analyze_one_call(radix, fitness_raw, neighbourhood: int = HAMMING, damping: float = 0.85,
+                     p: float = 0.05, tol: float = 1e-13, max_iter: int = 1_000_000,
+                     cap_edges: int | None = None, lib_path: str = LIB) -> dict:
+    """The whole analysis through the library's one-call entry point
+    (flo_analyze); host buffers sized from n_raw, col_idx from cap_edges
+    (default: the candidate-pair bound n_raw * K).  Returns the status and
+    every output; arrays are cut to their sizes when the call succeeded."""
+    lib = load(lib_path)
+    rad = np.ascontiguousarray(radix, dtype=np.int32)
+    fit = np.ascontiguousarray(fitness_raw, dtype=np.float32)
+    n_raw = int(np.prod(rad.astype(np.int64)))
+    K = int(sum((min(int(r) - 1, 2) if neighbourhood == ADJACENT else int(r) - 1) for r in rad))
+    cap = n_raw * max(K, 1) if cap_edges is None else int(cap_edges)
+    pr = np.zeros(max(n_raw, 1), np.float64)
+    minima = np.zeros(max(n_raw, 1), np.int32)
+    valid_raw = np.zeros(max(n_raw, 1), np.int32)
+    row_ptr = np.zeros(n_raw + 1, np.int32)
+    col_idx = np.zeros(max(cap, 1), np.int32)
+    sizes = np.zeros(7, np.int64)
+    stats = np.zeros(5, np.float64)
+    rc = lib.flo_analyze(len(rad), _ptr(rad), _ptr(fit), int(neighbourhood), float(damping), float(p), float(tol),
+                         int(max_iter), _ptr(pr), _ptr(minima), _ptr(valid_raw), _ptr(row_ptr), _ptr(col_idx),
+                         cap, _ptr(sizes), _ptr(stats))
+    n_raw_, N, E, M, plateau, iters, K_ = (int(v) for v in sizes)
+    out = {"status": int(rc), "n_raw": n_raw_, "N": N, "E": E, "M": M, "plateau_minima": plateau,
+           "iterations": iters, "K": K_}
+    if rc in (OK, ENOCONV):
+        out.update(pagerank=pr[:N], minima=minima[:M], valid_raw=valid_raw[:N], row_ptr=row_ptr[:N + 1],
+                   col_idx=col_idx[:E], residual=float(stats[0]), f_opt=float(stats[1]), score=float(stats[2]),
+                   mass_near=float(stats[3]), mass_minima=float(stats[4]))
+    return out

@@ -449,3 +449,68 @@ double flo_score(const flo_graph *g, const double *c, double p, double *num, dou
     if (den) *den = s_all;
     return s_near / s_all;
 }
+
+/*
+ * One whole analysis in one call (the steps above, in order): FFG, local
+ * minima, PageRank and C_p of one space, host buffers, FP64.
+ *   outputs (any may be NULL): pagerank[N], minima[M], valid_raw[N],
+ *   row_ptr[N + 1] and col_idx[E] (the in-edge lists, sources ascending);
+ *   n_raw-sized buffers always suffice for all but col_idx, which holds
+ *   cap_edges entries.
+ *   sizes (7 x int64, may be NULL): n_raw, N, E, M, plateau minima,
+ *   iterations, K (candidate neighbour slots per node).
+ *   stats (5 x double, may be NULL): residual, f_opt, C_p, mass of L_p,
+ *   mass of L.
+ * Returns FLO_OK; FLO_EINVAL / FLO_ENOMEM / FLO_EOVERFLOW as flo_build and
+ * flo_pagerank; FLO_ENOCONV when max_iter was reached (outputs written);
+ * FLO_ESIZE when E > cap_edges (sizes written, nothing else).
+ */
+#define FLO_ESIZE (-6)
+int flo_analyze(int n, const int32_t *radix, const float *fitness_raw, int neighbourhood, double damping,
+                double p, double tol, int64_t max_iter, double *pagerank, int32_t *minima, int32_t *valid_raw,
+                int32_t *row_ptr, int32_t *col_idx, int64_t cap_edges, int64_t *sizes, double *stats)
+{
+    flo_graph *g = NULL;
+    int rc = flo_build(n, radix, fitness_raw, neighbourhood, &g);
+    if (rc != FLO_OK)
+        return rc;
+    int64_t s6[6];
+    flo_sizes(g, s6);
+    if (sizes) {
+        for (int j = 0; j < 5; ++j)
+            sizes[j] = s6[j];
+        sizes[5] = 0;
+        sizes[6] = s6[5];
+    }
+    if (col_idx && g->E > cap_edges) {
+        flo_free(g);
+        return FLO_ESIZE;
+    }
+    double *r = malloc(sizeof(double) * (size_t)(g->N > 0 ? g->N : 1));
+    if (!r) {
+        flo_free(g);
+        return FLO_ENOMEM;
+    }
+    int64_t iterations = 0;
+    double residual = 0.0;
+    rc = flo_pagerank(g, damping, tol, max_iter, r, &iterations, &residual);
+    if (rc == FLO_OK || rc == FLO_ENOCONV) {
+        double num = 0.0, den = 0.0;
+        const double score = flo_score(g, r, p, &num, &den);
+        flo_export(g, valid_raw, row_ptr, col_idx, NULL, minima, NULL);
+        if (pagerank)
+            memcpy(pagerank, r, sizeof(double) * (size_t)g->N);
+        if (sizes)
+            sizes[5] = iterations;
+        if (stats) {
+            stats[0] = residual;
+            stats[1] = g->f_opt;
+            stats[2] = score;
+            stats[3] = num;
+            stats[4] = den;
+        }
+    }
+    free(r);
+    flo_free(g);
+    return rc;
+}
