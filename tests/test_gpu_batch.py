@@ -189,6 +189,63 @@ def test_analyze_batch_against_oracle(ctx):
         assert abs(res[j].score - o.score) <= 1e-5
 
 
+def test_segmented_build_every_record_width(ctx):
+    """fl_analyze_batch builds every space in one launch per stage: record
+    widths 1 to 5 (radices (5,4,4,2), (12,12), (20,20,20), (30,30,30),
+    (60,60) under Hamming), adjacent spaces, a space too wide for slot
+    records (generic kernels inside the same stages), a space rejected at the
+    degree stage (a fitness <= 0) and one with no valid point.  Each result
+    equals the space's own plan_create + slot-sweep run bit for bit; a second
+    call (the context's cached batch) gives the same results again."""
+    import torch
+    from paper_2210_01465_amd import api
+    rng = np.random.default_rng(21)
+
+    def landscape(name, radix, p_nan=0.2):
+        n = int(np.prod(radix))
+        f = rng.lognormal(0.0, 0.6, n).astype(np.float32)
+        f[rng.random(n) < p_nan] = np.nan
+        return synth.Space(name, radix, f)
+
+    spaces = [landscape("w1", (5, 4, 4, 2)), landscape("w2", (12, 12)), landscape("w3", (20, 20, 20)),
+              landscape("w4", (30, 30, 30)), landscape("w5", (60, 60)), landscape("adj", (9, 8, 6, 5)),
+              landscape("adj2", (30, 30, 30))]
+    nbs = ["hamming"] * 5 + ["adjacent", "adjacent"]
+    wide = landscape("wide", (200, 3))                     # 398 candidate slots: generic kernels
+    neg = landscape("neg", (6, 6))
+    neg.fitness_raw[np.flatnonzero(~np.isnan(neg.fitness_raw))[3]] = -1.0   # rejected by the degree stage
+    empty = synth.Space("empty", (4, 4), np.full(16, np.nan, np.float32))
+    spaces += [wide, neg, empty]
+    nbs += ["hamming", "hamming", "hamming"]
+    fits = [torch.from_numpy(np.ascontiguousarray(s.fitness_raw)).cuda() for s in spaces]
+    runs = []
+    for call in range(2):
+        say(f"segmented build, call {call}")
+        runs.append(api.analyze_batch([s.radix for s in spaces], fits, nbs, 0.85, 0.05, ctx=ctx))
+    for res in runs:
+        assert res[-1].info["status"] == -1 and res[-2].info["status"] == -1   # FL_EINVAL
+    words = []
+    for j, s in enumerate(spaces[:-2]):
+        say(f"plain run {s.name} radix={s.radix} nb={nbs[j]}")
+        fit = fits[j]
+        plan = api.plan_create(ctx, s.radix, fit, nbs[j])
+        words.append(plan.sizes["mask_words"])
+        lay = ROWS_SLOTS if plan.sizes["mask_words"] > 0 else 0
+        pr, mins, info = api.execute(plan, 0.85, 0.05, row_mapping=lay)
+        pr, mins = pr.cpu().numpy(), mins.cpu().numpy()
+        plan.close()
+        for res in runs:
+            assert res[j].info["status"] == 0, s.name
+            assert res[j].info["n_edges"] == info["n_edges"] and res[j].info["n_minima"] == info["n_minima"]
+            assert np.array_equal(res[j].minima.cpu().numpy(), mins), s.name
+            if lay == ROWS_SLOTS:
+                assert np.array_equal(res[j].pagerank.cpu().numpy(), pr), s.name
+                assert res[j].info["iterations"] == info["iterations"]
+            else:
+                assert float(np.abs(res[j].pagerank.cpu().numpy() - pr).sum()) <= L1_TOL
+    assert words[:5] == [1, 2, 3, 4, 5] and words[7] == 0, words
+
+
 def test_batch_rejects_bad_members(ctx):
     import torch
     from paper_2210_01465_amd import api, _abi
