@@ -304,13 +304,16 @@ fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *batch, int64_t *sweeps, d
  * or launch its kernels one by one.  Results are identical either way. */
 fl_status fl_batch_set_graphs(fl_ctx *ctx, fl_batch *batch, int32_t enable);
 
-/* One-shot batched analysis of n_spaces spaces: the FFGs are built with one
- * synchronisation per build stage, then PageRank runs as one batch (spaces
- * the slot sweep cannot take run through fl_execute).  All array arguments
- * have n_spaces entries; d_pagerank[j] / d_minima[j] are sized as for
- * fl_execute (n_raw upper bound is always enough).  out[j].status holds each
- * space's status; the call returns the first error, or FL_ENOCONV if some
- * space did not converge. */
+/* One-shot batched analysis of n_spaces spaces (Sec. VII-B for each): the
+ * FFGs are built together, each build stage one launch for all spaces (a
+ * table of per-space descriptors; one host synchronisation per stage), then
+ * PageRank runs as one batch (spaces the slot sweep cannot take run through
+ * fl_execute).  All array arguments have n_spaces entries; d_pagerank[j] /
+ * d_minima[j] are sized as for fl_execute (n_raw upper bound is always
+ * enough).  out[j].status holds each space's status; the call returns the
+ * first error, or FL_ENOCONV if some space did not converge.  The context
+ * keeps the batch between calls (empty between calls; freed by fl_destroy),
+ * so calls on one context must not overlap. */
 fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces,
                            const float *const *d_fitness_raw, const fl_neighbourhood *nb,
                            const fl_params *params, double *const *d_pagerank, int32_t *const *d_minima,
