@@ -162,6 +162,40 @@ def test_mask_widths(ctx):
 
 
 
+def test_slot_sweep_plain_loads(ctx):
+    """A raw-index span of 2^29 or more (here 28 binary parameters, 2^28 raw
+    configurations, neighbours up to 2^27 away) does not fit the buffer-load
+    offsets, so the slot sweep takes its plain-load form.  The valid points
+    form a 2^18-point sub-cube (bits 10..19 zero) with 10 % failures, so every
+    parameter, the most significant included, has in-edges.  Checked against
+    the one-lane CSR sweep on the same plan (same order of addition: equal
+    bit for bit) and against the invariants of a probability vector with
+    teleport (sum 1, r >= (1 - d)/N)."""
+    import torch
+    from paper_2210_01465_amd import api
+    n_raw = 1 << 28
+    rng = np.random.default_rng(29)
+    idx = ((np.arange(256, dtype=np.int64) << 20)[:, None] | np.arange(1024, dtype=np.int64)[None, :]).ravel()
+    idx = idx[rng.random(idx.size) >= 0.1]
+    f = np.full(n_raw, np.nan, np.float32)
+    f[idx] = rng.lognormal(0.0, 0.5, idx.size).astype(np.float32)
+    say(f"plain-load slot sweep: 2^28 raw, {idx.size} valid")
+    plan = api.plan_create(ctx, (2,) * 28, torch.from_numpy(f).cuda(), "hamming")
+    del f
+    try:
+        assert plan.sizes["mask_words"] == 2 and plan.n_valid == idx.size
+        pr_s, mins_s, info_s = api.execute(plan, 0.85, 0.05, row_mapping=ROWS_SLOTS)
+        pr_c, mins_c, info_c = api.execute(plan, 0.85, 0.05, row_mapping=1)
+        pr_s, pr_c = pr_s.cpu().numpy(), pr_c.cpu().numpy()
+        assert info_s["iterations"] == info_c["iterations"] and info_s["status"] == 0
+        assert np.array_equal(pr_s, pr_c)
+        assert np.array_equal(mins_s.cpu().numpy(), mins_c.cpu().numpy())
+        assert info_s["n_edges"] > 0 and abs(pr_s.sum() - 1.0) <= 1e-6
+        assert pr_s.min() >= (1.0 - 0.85) / idx.size * (1.0 - 1e-5)
+    finally:
+        plan.close()
+
+
 def test_edge_cases(ctx):
     rng = np.random.default_rng(0)
     cases = [
