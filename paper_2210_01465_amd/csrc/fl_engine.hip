@@ -653,10 +653,11 @@ struct fl_batch {
     int64_t sweeps = 0;
     double sweep_ms = 0.0;
     hipEvent_t ev[2] = {};
-    // the captured sweep loop of one step and the launch shape it was captured for
+    // the captured sweep loop of one step, per launch shape (kept for the
+    // shapes seen recently, so membership moving back and forth between
+    // shapes replays instead of recapturing; dropped when the tables move)
     bool use_graphs = true;
     hipStream_t capture_stream = nullptr;  // private, only ever captured (the context's stream may be the null stream)
-    hipGraphExec_t graph = nullptr;
     struct Shape {
         int32_t sweeps = 0, finish_grid = 0;
         int32_t grid[fl::kMaxWords + 1] = {};
@@ -669,7 +670,9 @@ struct fl_batch {
                 if (grid[w] != o.grid[w]) return false;
             return true;
         }
-    } shape;
+    };
+    static constexpr size_t kMaxGraphs = 32;
+    std::vector<std::pair<Shape, hipGraphExec_t>> graphs;   // least recently used first
     int64_t graph_launches = 0, graph_captures = 0;
 };
 
@@ -701,7 +704,15 @@ fl_status member_alloc(fl_ctx *ctx, const fl_plan *p, fl_batch::Member &m) {
     return FL_OK;
 }
 
+// Destroy the batch's captured graphs (their kernel arguments point at the
+// batch tables, so they go whenever the tables are reallocated).
+void batch_free_graphs(fl_batch *b) {
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
+    b->graphs.clear();
+}
+
 void batch_free_tables(fl_batch *b) {
+    batch_free_graphs(b);
     fl_ctx *ctx = b->ctx;
     ctx->pool.release(b->d_members);
     ctx->pool.release(b->d_tiles);
@@ -1215,7 +1226,7 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *b) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &m : b->members) member_release(ctx, m);
     batch_free_tables(b);
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    batch_free_graphs(b);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     ctx->pool.release(b->d_counts);
     if (b->h_counts) (void)hipHostFree(b->h_counts);
@@ -1379,10 +1390,19 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         };
         FL_HIP(hipEventRecord(b->ev[0], s));
         if (b->use_graphs) {
-            if (!b->graph || !(shape == b->shape)) {
-                if (b->graph) {
-                    FL_HIP(hipGraphExecDestroy(b->graph));
-                    b->graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            for (size_t q = 0; q < b->graphs.size(); ++q)
+                if (b->graphs[q].first == shape) {
+                    auto hit = b->graphs[q];   // to the most recently used end
+                    b->graphs.erase(b->graphs.begin() + (long)q);
+                    b->graphs.push_back(hit);
+                    exec = hit.second;
+                    break;
+                }
+            if (!exec) {
+                if (b->graphs.size() >= fl_batch::kMaxGraphs) {
+                    (void)hipGraphExecDestroy(b->graphs.front().second);
+                    b->graphs.erase(b->graphs.begin());
                 }
                 // captured on the private stream (capture runs nothing),
                 // launched on the context's stream
@@ -1395,16 +1415,13 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
                     return fail(ctx, FL_EHIP, "graph capture: %s",
                                 hipGetErrorString(le != hipSuccess ? le : ce));
                 }
-                const hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+                const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
-                if (ie != hipSuccess) {
-                    b->graph = nullptr;
-                    return fail(ctx, FL_EHIP, "graph instantiation: %s", hipGetErrorString(ie));
-                }
-                b->shape = shape;
+                if (ie != hipSuccess) return fail(ctx, FL_EHIP, "graph instantiation: %s", hipGetErrorString(ie));
+                b->graphs.emplace_back(shape, exec);
                 ++b->graph_captures;
             }
-            FL_HIP(hipGraphLaunch(b->graph, s));
+            FL_HIP(hipGraphLaunch(exec, s));
             ++b->graph_launches;
         } else {
             FL_HIP(enqueue(s));

@@ -12,7 +12,11 @@ arrive over time.  The server
 * adds admitted requests to one running batch (fl_batch_*): members join and
   leave between steps of a few sweeps, so short analyses are not held behind
   long ones;
-* records, per request, the latency from arrival to a host-visible result.
+* records, per request, the latency from arrival to a host-visible result;
+* keeps Python's cyclic garbage collector from running inside the loop (a
+  full collection over the live request and tensor objects stalls the loop
+  for tens of milliseconds): automatic collection is paused while ``run``
+  serves and the young generations are collected when the loop idles.
 
 The GPU work goes through a backend object (``build``, ``plan_bytes``,
 ``member_bytes``, ``add``, ``step``, ``collect``, ``release``, plus ``plain``
@@ -22,6 +26,7 @@ exercised with any backend.
 from __future__ import annotations
 
 import collections
+import gc
 import heapq
 import time
 from dataclasses import dataclass, field
@@ -70,7 +75,7 @@ def footprint_estimate(radix, words: int = 2) -> int:
 class GpuBackend:
     """The engine through the Python binding (one context, one batch)."""
 
-    def __init__(self, ctx=None, sweeps_per_step: int = 4):
+    def __init__(self, ctx=None, sweeps_per_step: int = 16):
         from . import api
         self.api = api
         self.ctx = ctx or api.Context(0)
@@ -122,8 +127,9 @@ class Server:
 
     def __init__(self, backend, hbm_budget: int, cache_budget: int | None = None,
                  clock: Callable[[], float] | None = None,
-                 sleep: Callable[[float], None] | None = None):
+                 sleep: Callable[[float], None] | None = None, pause_gc: bool = True):
         self.backend = backend
+        self.pause_gc = pause_gc
         self.hbm_budget = int(hbm_budget)
         self.cache_budget = int(cache_budget if cache_budget is not None else hbm_budget // 2)
         self.clock = clock or time.perf_counter
@@ -210,6 +216,16 @@ class Server:
     def run(self, requests, start: float | None = None) -> list:
         """Serve `requests` (sorted by arrival, times relative to `start`)
         until all are done; returns the Done records."""
+        paused = self.pause_gc and gc.isenabled()
+        if paused:
+            gc.disable()
+        try:
+            return self._loop(requests, start)
+        finally:
+            if paused:
+                gc.enable()
+
+    def _loop(self, requests, start) -> list:
         pending = list(requests)
         heapq.heapify(pending)
         t0 = self.clock() if start is None else start
@@ -235,7 +251,12 @@ class Server:
             elif pending and not self.queue:
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
-                    self.sleep(min(wait, 0.001))
+                    if self.pause_gc:
+                        gc.collect(1)         # idle: young generations only
+                        self.stats["gc_idle"] += 1
+                        wait = pending[0].arrival - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(min(wait, 0.001))
         return self.done
 
 

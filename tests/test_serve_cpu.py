@@ -1,6 +1,8 @@
 """Serving scheduler on the CPU: a fake backend (built on the oracle) stands
 in for the GPU engine, with a virtual clock, so admission, the FFG cache and
 continuous batching are tested without a device."""
+import gc
+
 import numpy as np
 import pytest
 
@@ -21,6 +23,7 @@ class FakeBackend:
         self.live_plans = 0
         self.added_while_running = 0
         self.max_on_one_plan = 0                  # members sharing one FFG at once
+        self.gc_during_step = set()
 
     def clock(self):
         return self.now
@@ -51,6 +54,7 @@ class FakeBackend:
                                    sum(1 for m in self.members.values() if m[4] is g))
 
     def step(self):
+        self.gc_during_step.add(gc.isenabled())
         self.now += self.step_cost
         for m in self.members.values():
             m[0] -= self.sweeps
@@ -128,3 +132,17 @@ def test_poisson_arrivals_are_seeded():
     a = serve.poisson_arrivals(1000.0, 0.5, seed=5)
     b = serve.poisson_arrivals(1000.0, 0.5, seed=5)
     assert a == b and 400 < len(a) < 600 and all(x < y for x, y in zip(a, a[1:]))
+
+
+@pytest.mark.parametrize("pause", [True, False])
+def test_collector_paused_while_serving(pause):
+    """Automatic garbage collection is off inside the loop (collected only
+    when idle) and back on afterwards, unless the server is told otherwise."""
+    reqs = make_requests(30, seed=6, rate=500.0)
+    fb = FakeBackend()
+    srv = serve.Server(fb, hbm_budget=1 << 30, clock=fb.clock, sleep=fb.sleep, pause_gc=pause)
+    assert gc.isenabled()
+    done = srv.run(reqs)
+    assert gc.isenabled() and len(done) == len(reqs)
+    assert fb.gc_during_step == {not pause}
+    assert (srv.stats["gc_idle"] > 0) == pause
