@@ -185,7 +185,48 @@ def batched_leg(ctx, damping, p, tol, repeats: int = 3):
             "ms_one_at_a_time": round(t_plain * 1e3, 3), "speedup": round(t_plain / t_batch, 3),
             "gteps_batched": round(edges / t_batch / 1e9, 3),
             "gteps_one_at_a_time": round(edges / t_plain / 1e9, 3),
-            "all_ok": all(r.info["status"] == 0 for r in res)}
+            "all_ok": all(r.info["status"] == 0 for r in res),
+            "sweep_loop": batched_sweep_rate(ctx, spaces, fits, damping, p, tol)}
+
+
+def batched_sweep_rate(ctx, spaces, fits, damping, p, tol, sweeps_per_step: int = 16):
+    """HBM rate of the batched sweep loop alone: every space's plan built
+    first, all added to one batch, stepped to the end.  Algorithmic bytes are
+    the slot sweep's per-sweep bytes ((20 + 8 W) N + 4 E) times each member's
+    iteration count; time is the batch's HIP-event device time around its
+    sweep loops (batched sweeps and the per-member step kernel together).
+    The second of two identical runs is reported (the first captures the
+    loop's graphs)."""
+    import torch
+    from paper_2210_01465_amd import api
+    plans = [api.plan_create(ctx, s.radix, f, "hamming") for s, f in zip(spaces, fits)]
+    try:
+        for _ in range(2):
+            batch = api.Batch(ctx)
+            for j, pl in enumerate(plans):
+                batch.add(pl, damping, p, tol=tol, tag=j)
+            infos = {}
+            while True:
+                running = batch.step(sweeps_per_step)
+                for tag, _, _, info in batch.collect():
+                    infos[tag] = info
+                if running == 0 and len(infos) == len(plans):
+                    break
+            tm = batch.timing()
+            batch.close()
+        torch.cuda.synchronize()
+        alg = 0
+        for j, pl in enumerate(plans):
+            sz = pl.sizes
+            alg += infos[j]["iterations"] * ((20 + 8 * int(sz["mask_words"])) * int(sz["n_valid"])
+                                             + 4 * int(sz["n_edges"]))
+        gbs = alg / (tm["sweep_ms"] * 1e-3) / 1e9
+        return {"members": len(plans), "sweeps": tm["sweeps"], "device_ms": round(tm["sweep_ms"], 3),
+                "alg_bytes": int(alg), "gb_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                "graph_launches": tm["graph_launches"], "graph_captures": tm["graph_captures"]}
+    finally:
+        for pl in plans:
+            pl.close()
 
 
 def serving_leg(ctx, large_space, large_fit, seconds: float, rate: float = 1000.0, warm: float = 2.0):

@@ -1388,7 +1388,8 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
             }
             return hipSuccess;
         };
-        FL_HIP(hipEventRecord(b->ev[0], s));
+        // the start event goes in after any capture, so that host time spent
+        // capturing is not counted as device time of the loop
         if (b->use_graphs) {
             hipGraphExec_t exec = nullptr;
             for (size_t q = 0; q < b->graphs.size(); ++q)
@@ -1421,9 +1422,11 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
                 b->graphs.emplace_back(shape, exec);
                 ++b->graph_captures;
             }
+            FL_HIP(hipEventRecord(b->ev[0], s));
             FL_HIP(hipGraphLaunch(exec, s));
             ++b->graph_launches;
         } else {
+            FL_HIP(hipEventRecord(b->ev[0], s));
             FL_HIP(enqueue(s));
         }
         FL_HIP(hipEventRecord(b->ev[1], s));
