@@ -229,6 +229,67 @@ def batched_sweep_rate(ctx, spaces, fits, damping, p, tol, sweeps_per_step: int 
             pl.close()
 
 
+def _wall_ms(fn, repeats: int = 5):
+    """Median wall time (ms) of fn() over repeats calls after one warm-up call;
+    every call ends with the device idle (the calls synchronise)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2] * 1e3
+
+
+def landscape_leg(ctx, space, fit, nb: str, p: float):
+    """The landscape figures on the large workload, wall time per call:
+    the exact method at d = 1 and 0.85 (Jacobi sweeps to a fixed point), the C_p curve
+    over p = 0..15 %, the naive metric with a 20-bin histogram; and one
+    paper-shaped space analysed with its failures kept as nodes of fitness
+    1e10 (build plus PageRank): the GEMM-shaped space with 78 % failed."""
+    import numpy as np
+    import torch
+    from paper_2210_01465_amd import api, synth
+    plan = api.plan_create(ctx, space.radix, fit, nb)
+    try:
+        res, exact_pr = {}, None
+        for d, key in ((1.0, "exact_d1"), (0.85, "exact_d085")):
+            pr, _, info = api.execute(plan, d, p, exact=True)
+            exact_pr = pr
+            ms = _wall_ms(lambda: api.execute(plan, d, p, exact=True, pagerank=pr))
+            E = int(info["n_edges"])
+            res[key] = {"ms": round(ms, 3), "sweeps": int(info["iterations"]), "score": info["score"],
+                        "gteps": round(E * info["iterations"] / ms / 1e6, 3)}
+        pr, _, info = api.execute(plan, 0.85, p)
+        grid = [j / 100 for j in range(16)]
+        res["score_curve_16"] = {"ms": round(_wall_ms(lambda: api.score_curve(plan, pr, grid)), 4),
+                                 "n_minima": int(info["n_minima"])}
+        res["naive_metric_20"] = {"ms": round(_wall_ms(lambda: api.naive_metric(plan, 20)), 4)}
+    finally:
+        plan.close()
+    s = synth.batched()[18]                      # a GEMM-shaped space, 78 % of it failed
+    f = np.array(s.fitness_raw, dtype=np.float32, copy=True)
+    failed = float(np.isnan(f).mean())
+    f[np.isnan(f)] = np.float32(1e10)
+    f_dev = torch.from_numpy(f).cuda()
+    out = {}
+
+    def paper_mode():
+        pl = api.plan_create(ctx, s.radix, f_dev, nb)
+        _, _, inf = api.execute(pl, 0.85, p)
+        pl.close()
+        out.update(inf)
+    ms = _wall_ms(paper_mode)
+    res["paper_failure_mode"] = {"space": s.name, "radix": list(s.radix), "failed_frac": round(failed, 4),
+                                 "ms": round(ms, 3), "n_valid": int(out["n_valid"]),
+                                 "n_edges": int(out["n_edges"]), "n_minima": int(out["n_minima"]),
+                                 "n_plateau": int(out["n_plateau"]), "iterations": int(out["iterations"])}
+    return res, exact_pr.cpu().numpy()
+
+
 def serving_leg(ctx, large_space, large_fit, seconds: float, rate: float = 1000.0, warm: float = 2.0):
     """Poisson stream (rate per second, seed 5) of analyses: 98 % drawn
     uniformly from the 234 batched spaces, 2 % the large space; damping
@@ -279,6 +340,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched leg (234 spaces in one fl_analyze_batch vs one at a time)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-landscape", action="store_true",
+                    help="skip the landscape figures (exact method, C_p curve, naive metric, failure mode)")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="measured length of the Poisson request stream (after 2 s of warm-up)")
     ap.add_argument("--serving-warmup", type=float, default=2.0)
@@ -430,6 +493,11 @@ def main():
         print("[bench] batched leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(ctx, damping, p, tol)
 
+    exact_pr = None
+    if not args.no_landscape:
+        print("[bench] landscape figures", file=sys.stderr, flush=True)
+        out["landscape"], exact_pr = landscape_leg(ctx, space, fit, args.neighbourhood, p)
+
     if not args.no_serving:
         print("[bench] serving leg", file=sys.stderr, flush=True)
         out["serving"] = serving_leg(ctx, space, fit, args.serving_seconds, warm=args.serving_warmup)
@@ -446,6 +514,9 @@ def main():
                            "score_abs": abs(info["score"] - ref.score),
                            "minima_exact": bool(np.array_equal(min_buf[:M].cpu().numpy(),
                                                                ref.graph.minima))}
+        if exact_pr is not None:      # the exact method at d = 0.85 against the same reference
+            out["accuracy"]["exact_pagerank_l1"] = float(np.abs(exact_pr - ref.pagerank).sum())
+            out["accuracy"]["exact_score_abs"] = abs(out["landscape"]["exact_d085"]["score"] - ref.score)
     ctx.close()
     print(json.dumps(out), flush=True)
 
