@@ -166,6 +166,48 @@ def test_graph_replays_equal_eager_launches(ctx):
         assert np.array_equal(graph[j][0], ref[0])
 
 
+def _alternating(ctx, space, copies, graphs):
+    """One plan added `copies` times (same d: all members stop at the same
+    sweep), stepped with 3 and 5 sweeps in turn: the launch shape alternates
+    between two while the membership stays the same."""
+    import torch
+    from paper_2210_01465_amd import api
+    batch = api.Batch(ctx)
+    batch.set_graphs(graphs)
+    fit = torch.from_numpy(space.fitness_raw).cuda()
+    plan = api.plan_create(ctx, space.radix, fit, "hamming")
+    for j in range(copies):
+        batch.add(plan, 0.85, 0.05, tag=j)
+    done, steps = {}, 0
+    while True:
+        running = batch.step((3, 5)[steps % 2])
+        steps += 1
+        for tag, pr, mins, info in batch.collect():
+            done[tag] = (pr.cpu().numpy(), info["iterations"])
+        if running == 0 and len(done) == copies:
+            break
+    timing = batch.timing()
+    batch.close()
+    plan.close()
+    return done, timing, steps
+
+
+def test_graphs_kept_per_shape(ctx):
+    """Steps whose launch shapes alternate replay the two captured graphs
+    instead of capturing anew each step, with the same ranks as launching
+    kernel by kernel."""
+    say("alternating step shapes, mid x 3")
+    graph, t_graph, steps = _alternating(ctx, synth.mid(), 3, graphs=True)
+    eager, t_eager, _ = _alternating(ctx, synth.mid(), 3, graphs=False)
+    assert steps >= 6 and steps - 1 <= t_graph["graph_launches"] <= steps
+    assert t_graph["graph_captures"] == 2, t_graph
+    assert t_eager["graph_launches"] == 0
+    ref = plain(ctx, synth.mid(), "hamming", 0.85, 0.05)
+    for j in range(3):
+        assert np.array_equal(graph[j][0], eager[j][0]) and graph[j][1] == eager[j][1]
+        assert np.array_equal(graph[j][0], ref[0]) and graph[j][1] == ref[2]["iterations"]
+
+
 def test_analyze_batch_against_oracle(ctx):
     import torch
     from paper_2210_01465_amd import api
