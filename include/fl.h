@@ -283,10 +283,12 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *batch, fl_plan *plan, const fl_par
  * minima and C_p (Sec. VII-B, eq. 3) are written.  *n_running receives the
  * number of members not yet finished.  The sweep loop of a step (per sweep:
  * one launch per node-record width, then the step launch) is captured once
- * in a HIP graph and replayed by later steps of the same launch shape (the
- * number of sweeps and grid sizes rounded to powers of two); member lists
- * and their lengths live in device memory, so members may join and leave
- * between replays.  Synchronises the stream. */
+ * per launch shape (the number of sweeps and grid sizes rounded to powers of
+ * two) in a HIP graph and replayed by later steps of that shape; the batch
+ * keeps the graphs of its 32 most recently used shapes and drops them all
+ * when its tables grow.  Member lists and their lengths live in device
+ * memory, so members may join and leave between replays.  Synchronises the
+ * stream. */
 fl_status fl_batch_step(fl_ctx *ctx, fl_batch *batch, int32_t sweeps, int32_t *n_running);
 
 /* Remove up to `max` finished members: their tags and summaries (status
