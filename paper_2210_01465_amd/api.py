@@ -400,8 +400,10 @@ def batch_create(ctx: Context) -> Batch:
 def analyze_batch(spaces, fitness, neighbourhood="hamming", damping=0.85, p: float = 0.05,
                   tol: float = 0.0, max_iter: int = 0, ctx: Context | None = None) -> list:
     """fl_analyze_batch over many spaces.  ``spaces`` is a list of radix
-    tuples, ``fitness`` a matching list of device float32 tensors; the other
-    arguments may be scalars or per-space lists.  Returns a list of Result."""
+    tuples, ``fitness`` a matching list of device float32 tensors on the
+    context's device; the other arguments may be scalars or per-space lists.
+    Returns a list of Result whose pagerank and minima tensors are views into
+    one float64 and one int32 buffer shared by the call's results."""
     n = len(spaces)
     if len(fitness) != n:
         raise ValueError("spaces and fitness differ in length")
@@ -421,21 +423,27 @@ def analyze_batch(spaces, fitness, neighbourhood="hamming", damping=0.85, p: flo
         pr_ptrs = (ctypes.c_void_p * max(n, 1))()
         min_ptrs = (ctypes.c_void_p * max(n, 1))()
         outs = (_abi.fl_summary * max(n, 1))()
-        bufs = []
+        # one output buffer per type for all spaces: space j owns n_raw
+        # entries from offset[j], rounded up to 64 entries (256-byte aligned
+        # starts); results are views into them
+        offsets, total = [], 0
         for j in range(n):
             _check_fitness(ctx, spaces[j], fitness[j])
+            offsets.append(total)
+            total += (_n_raw(spaces[j]) + 63) // 64 * 64
+        dev = torch.device("cuda", ctx.device)
+        pr_all = torch.empty(max(total, 1), dtype=torch.float64, device=dev)
+        min_all = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+        pr_base, min_base = pr_all.data_ptr(), min_all.data_ptr()
+        for j in range(n):
             sp, arr = _space(spaces[j])
             keep.append(arr)
             sp_arr[j] = sp
             fit_ptrs[j] = fitness[j].data_ptr()
             nb_arr[j] = _nb(nbs[j])
             prm_arr[j] = _params(ds[j], ps[j], tols[j], its[j], 0)
-            n_raw = _n_raw(spaces[j])
-            pr = torch.empty(n_raw, dtype=torch.float64, device=fitness[j].device)
-            mins = torch.empty(n_raw, dtype=torch.int32, device=fitness[j].device)
-            bufs.append((pr, mins))
-            pr_ptrs[j] = pr.data_ptr()
-            min_ptrs[j] = mins.data_ptr()
+            pr_ptrs[j] = pr_base + 8 * offsets[j]
+            min_ptrs[j] = min_base + 4 * offsets[j]
         rc = _abi.load().fl_analyze_batch(ctx.handle, n, sp_arr, fit_ptrs, nb_arr, prm_arr, pr_ptrs,
                                           min_ptrs, outs)
         _check(ctx, rc, "fl_analyze_batch", allow=(_abi.FL_ENOCONV, _abi.FL_EINVAL, _abi.FL_EOVERFLOW))
@@ -443,8 +451,8 @@ def analyze_batch(spaces, fitness, neighbourhood="hamming", damping=0.85, p: flo
         for j in range(n):
             info = outs[j].as_dict()
             N, M = int(info["n_valid"]), int(info["n_minima"])
-            pr, mins = bufs[j]
-            results.append(Result(pr[:N], mins[:M], None, float(info["score"]), info))
+            o = offsets[j]
+            results.append(Result(pr_all[o:o + N], min_all[o:o + M], None, float(info["score"]), info))
         return results
     finally:
         if own:
