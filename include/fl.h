@@ -285,7 +285,7 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *batch, fl_plan *plan, const fl_par
  * one launch per node-record width, then the step launch) is captured once
  * per launch shape (the number of sweeps and grid sizes rounded to powers of
  * two) in a HIP graph and replayed by later steps of that shape; the batch
- * keeps the graphs of its 32 most recently used shapes and drops them all
+ * keeps the graphs of its 256 most recently used shapes and drops them all
  * when its tables grow.  Member lists and their lengths live in device
  * memory, so members may join and leave between replays.  Synchronises the
  * stream. */

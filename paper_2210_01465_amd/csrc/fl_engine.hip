@@ -671,7 +671,7 @@ struct fl_batch {
             return true;
         }
     };
-    static constexpr size_t kMaxGraphs = 32;
+    static constexpr size_t kMaxGraphs = 256;
     std::vector<std::pair<Shape, hipGraphExec_t>> graphs;   // least recently used first
     int64_t graph_launches = 0, graph_captures = 0;
 };
