@@ -8,7 +8,8 @@ This module is a thin ctypes wrapper over ``flo.c`` (plain C, FP64,
 single-threaded), which follows the paper's definitions: search space and
 neighbourhoods (Sec. III-B, eq. 2), failed configurations (Sec. V), fitness
 flow graph, PageRank centrality and the p-proportion of centrality
-(Sec. VII-B, eq. 3).  ``build()`` compiles it with gcc.
+(Sec. VII-B, eq. 3), and the naive metric f_opt / f over the local minima
+(Sec. VII-A).  ``build()`` compiles it with gcc.
 """
 from __future__ import annotations
 
@@ -69,6 +70,8 @@ def load(path: str = LIB) -> ctypes.CDLL:
     lib.flo_score.restype = ctypes.c_double
     lib.flo_dag_rank.argtypes = [P, ctypes.c_double, P, i64p]
     lib.flo_dag_rank.restype = ctypes.c_int
+    lib.flo_naive.argtypes = [P, P, ctypes.c_int64, P]
+    lib.flo_naive.restype = ctypes.c_int
     lib.flo_analyze.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, P, P]
     lib.flo_analyze.restype = ctypes.c_int
@@ -140,6 +143,17 @@ class Graph:
         num, den = ctypes.c_double(), ctypes.c_double()
         s = self._lib.flo_score(self._handle, _ptr(c), p, ctypes.byref(num), ctypes.byref(den))
         return float(s), float(num.value), float(den.value)
+
+    def naive(self, n_bins: int = 20):
+        """Naive metric (flo_naive): f_opt / f(m) for every local minimum in
+        ascending node id (float64[M]) and its histogram over n_bins equal
+        bins of [0, 1] (int64[n_bins])."""
+        ratio = np.empty(max(self.M, 1), dtype=np.float64)
+        hist = np.empty(max(int(n_bins), 1), dtype=np.int64)
+        rc = self._lib.flo_naive(self._handle, _ptr(ratio), int(n_bins), _ptr(hist))
+        if rc != OK:
+            raise OracleError(rc, "flo_naive")
+        return ratio[:self.M], hist[:int(n_bins)]
 
     def close(self):
         if self._handle:

@@ -15,6 +15,7 @@
  *   - local minimum                                        (Sec. III-B)
  *   - fitness flow graph, PageRank centrality              (Sec. VII-B)
  *   - p-proportion of centrality C_p                       (Sec. VII-B, eq. 3)
+ *   - naive metric: f_opt / f over the local minima        (Sec. VII-A)
  *
  * Readings taken where the paper is silent or ambiguous:
  *   - A configuration is a node iff its fitness is finite and > 0; the caller
@@ -122,6 +123,16 @@ static int64_t neighbours_of(const flo_graph *g, int64_t I, int64_t *out)
         }
     }
     return count;
+}
+
+/* 1 iff node v has a valid neighbour whose fitness equals f(v) exactly. */
+static int has_equal_neighbour(const flo_graph *g, int64_t v, int64_t *nb)
+{
+    int64_t k = neighbours_of(g, g->valid_raw[v], nb);
+    for (int64_t j = 0; j < k; ++j)
+        if (g->f[g->node_of[nb[j]]] == g->f[v])
+            return 1;
+    return 0;
 }
 
 static int cmp_i64(const void *a, const void *b)
@@ -247,15 +258,18 @@ int flo_build(int n, const int32_t *radix, const float *fitness_raw,
     g->minima = malloc(sizeof(int64_t) * (size_t)(g->M > 0 ? g->M : 1));
     if (!g->minima) { free(nb); flo_free(g); return FLO_ENOMEM; }
     int64_t m = 0;
-    g->plateau_minima = 0;
     for (int64_t v = 0; v < g->N; ++v) {
         if (g->out_deg[v] != 0)
             continue;
         g->minima[m++] = v;
-        int64_t k = neighbours_of(g, g->valid_raw[v], nb);
-        for (int64_t j = 0; j < k; ++j)
-            if (g->f[g->node_of[nb[j]]] == g->f[v]) { g->plateau_minima += 1; break; }
     }
+
+    /* Plateau minima: sinks with a valid neighbour of exactly equal fitness
+     * (the points the strict reading of Sec. III-B, "all neighbours worse",
+     * would not call minima). */
+    g->plateau_minima = 0;
+    for (int64_t j = 0; j < g->M; ++j)
+        g->plateau_minima += has_equal_neighbour(g, g->minima[j], nb);
     free(nb);
     *out = g;
     return FLO_OK;
@@ -448,6 +462,36 @@ double flo_score(const flo_graph *g, const double *c, double p, double *num, dou
     if (num) *num = s_near;
     if (den) *den = s_all;
     return s_near / s_all;
+}
+
+/*
+ * Naive landscape metric (Sec. VII-A): for every local minimum m the fraction
+ * of optimal fitness it reaches, f_opt / f(m) in (0, 1], FP64 from the
+ * float32 fitness values.  ratio[j] (may be NULL) belongs to the j-th
+ * minimum in ascending node id.  hist (may be NULL, n_bins >= 1 entries)
+ * counts the minima per equal-width bin of [0, 1]: a ratio q falls in bin
+ * floor(q * n_bins), and q = 1 in the last bin.
+ * Returns FLO_OK, or FLO_EINVAL for n_bins < 1 when hist is given.
+ */
+int flo_naive(const flo_graph *g, double *ratio, int64_t n_bins, int64_t *hist)
+{
+    if (hist && n_bins < 1)
+        return FLO_EINVAL;
+    if (hist)
+        for (int64_t b = 0; b < n_bins; ++b)
+            hist[b] = 0;
+    for (int64_t j = 0; j < g->M; ++j) {
+        double q = g->f_opt / (double)g->f[g->minima[j]];
+        if (ratio)
+            ratio[j] = q;
+        if (hist) {
+            int64_t b = (int64_t)floor(q * (double)n_bins);
+            if (b > n_bins - 1)
+                b = n_bins - 1;
+            hist[b] += 1;
+        }
+    }
+    return FLO_OK;
 }
 
 /*

@@ -178,6 +178,78 @@ def check_separable_minima(lib):
         assert s == 1.0
 
 
+def _tie_cases():
+    """Small spaces with many exact ties: the fuzz spaces drawn from a few
+    fitness levels, and config-1 landscapes in the paper's failure mode
+    (failed and constraint-violating configurations kept as points of
+    fitness 1e10, Sec. V), where every failed point ties with the others."""
+    cases = [(r, f) for r, f in small_cases() if np.unique(f[np.isfinite(f)]).size < f.size]
+    for seed in range(3):
+        s = synth.tiny(seed)
+        f = np.array(s.fitness_raw, dtype=np.float32, copy=True)
+        f[~np.isfinite(f)] = np.float32(1e10)
+        cases.append((s.radix, f))
+    return cases
+
+
+def check_plateau_minima(lib):
+    """Plateau minima (sinks with a valid neighbour of exactly equal fitness)
+    counted from the brute-force neighbour lists of digit tuples: every
+    minimum of BruteFFG is looked at, its valid neighbours compared for
+    equality; excluded points (NaN / +inf) are not neighbours."""
+    seen_plateau = 0
+    for radix, fit in _tie_cases():
+        if not np.any(np.isfinite(fit) & (fit > 0)):
+            continue
+        for nb in ("hamming", "adjacent"):
+            b = BruteFFG(radix, fit, nb)
+            want = sum(1 for v in b.minima if any(b.f[w] == b.f[v] for w in b.nbrs[v]))
+            g = oracle.build_graph(radix, fit, NB[nb], lib_path=lib)
+            assert g.plateau_minima == want, (radix, nb, g.plateau_minima, want)
+            seen_plateau += want
+    assert seen_plateau > 0          # the cases do exercise plateaus
+
+
+def check_naive_separable(lib):
+    """Naive metric (Sec. VII-A) on separable power-of-two landscapes:
+    f = 2^(e_0(x_0) + ... + e_{n-1}(x_{n-1})) with distinct exponents per
+    parameter is exact in float32, neighbours never tie, and under the
+    adjacent neighbourhood the minima are exactly the digit tuples whose
+    every digit is a 1-D local minimum of its e_i.  So the ratios
+    f_opt / f(m) form the multiset {2^(sum_i min e_i - e_i(a_i))} over those
+    tuples, each an exact binary fraction, and their histogram is fixed."""
+    rng = np.random.default_rng(23)
+    for _ in range(10):
+        n = int(rng.integers(1, 5))
+        radix = tuple(int(r) for r in rng.integers(2, 7, size=n))
+        es = [rng.permutation(r) for r in radix]          # distinct exponents 0..r-1
+        grid = np.zeros(radix, dtype=np.int64)
+        for i, ei in enumerate(es):
+            shape = [1] * n
+            shape[i] = radix[i]
+            grid = grid + ei.reshape(shape)
+        f = np.ldexp(np.float32(1.0), grid.reshape(-1)).astype(np.float32)
+        local = [[k for k in range(len(ei))
+                  if (k == 0 or ei[k - 1] > ei[k]) and (k == len(ei) - 1 or ei[k + 1] > ei[k])]
+                 for ei in es]
+        want = sorted(2.0 ** -sum(int(es[i][a[i]]) - int(es[i].min()) for i in range(n))
+                      for a in itertools.product(*local))
+        for n_bins in (1, 4, 20):
+            g = oracle.build_graph(radix, f, oracle.ADJACENT, lib_path=lib)
+            ratio, hist = g.naive(n_bins)
+            assert sorted(ratio.tolist()) == want, (radix, ratio, want)
+            want_hist = [0] * n_bins
+            for q in want:                    # exact binary fractions: floor is exact
+                want_hist[min(int(q * n_bins), n_bins - 1)] += 1
+            assert hist.tolist() == want_hist, (radix, n_bins, hist, want_hist)
+            # the ratios follow the minima in ascending node id
+            assert np.array_equal(ratio, g.f_opt / g.fit[g.minima].astype(np.float64))
+        # Hamming: the single minimum is the optimum, ratio exactly 1, last bin
+        h = oracle.build_graph(radix, f, oracle.HAMMING, lib_path=lib)
+        ratio, hist = h.naive(20)
+        assert ratio.tolist() == [1.0] and hist[-1] == 1 and hist.sum() == 1
+
+
 def check_score_brute(lib, cases=None):
     """C_p recomputed from the brute minima with the <= (1+p) f_opt rule;
     non-decreasing in p; 1 once p reaches max_L f / f_opt - 1."""
@@ -369,7 +441,8 @@ def check_errors(lib):
 
 QUICK = [check_paper_sizes, check_adjacent_example, check_neighbours_product_order,
          check_ffg_bruteforce, check_pagerank_dense, check_closed_forms,
-         check_separable_minima, check_score_brute, check_dag_rank, check_metamorphic, check_errors]
+         check_separable_minima, check_plateau_minima, check_naive_separable, check_score_brute,
+         check_dag_rank, check_metamorphic, check_errors]
 
 
 def run_quick(lib):

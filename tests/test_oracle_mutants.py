@@ -48,6 +48,20 @@ MUTANTS = {
     "dag_without_one": [("r[w] = 1.0 + d * sum_get(&acc);", "r[w] = (w == 0) + d * sum_get(&acc);")],
     "dag_divide_by_in_degree": [("sum_add(&acc, r[u] / (double)g->out_deg[u]);",
                                  "sum_add(&acc, r[u] / (double)(g->in_ptr[w + 1] - g->in_ptr[w]));")],
+    "plateau_over_all_nodes": [("for (int64_t j = 0; j < g->M; ++j)\n"
+                                "        g->plateau_minima += has_equal_neighbour(g, g->minima[j], nb);",
+                                "for (int64_t j = 0; j < g->N; ++j)\n"
+                                "        g->plateau_minima += has_equal_neighbour(g, j, nb);")],
+    "plateau_any_neighbour": [("if (g->f[g->node_of[nb[j]]] == g->f[v])\n            return 1;",
+                               "if (g->f[g->node_of[nb[j]]] >= g->f[v])\n            return 1;")],
+    "plateau_first_neighbour_only": [("for (int64_t j = 0; j < k; ++j)\n        if (g->f[g->node_of[nb[j]]] == g->f[v])",
+                                      "for (int64_t j = 0; j < k && j < 1; ++j)\n        if (g->f[g->node_of[nb[j]]] == g->f[v])")],
+    "naive_inverted": [("double q = g->f_opt / (double)g->f[g->minima[j]];",
+                        "double q = (double)g->f[g->minima[j]] / g->f_opt;")],
+    "naive_bins_rounded": [("int64_t b = (int64_t)floor(q * (double)n_bins);",
+                            "int64_t b = (int64_t)floor(q * (double)n_bins + 0.5);")],
+    "naive_over_first_nodes": [("double q = g->f_opt / (double)g->f[g->minima[j]];",
+                                "double q = g->f_opt / (double)g->f[j];")],
 }
 
 
