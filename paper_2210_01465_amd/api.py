@@ -334,13 +334,26 @@ class Batch:
         self.handle = ctypes.c_void_p()
         _check(ctx, _abi.load().fl_batch_create(ctx.handle, ctypes.byref(self.handle)), "fl_batch_create")
         self._outputs = {}
+        self._next_tag = 0
 
     def add(self, plan: Plan, damping: float = 0.85, p: float = 0.05, tol: float = 0.0,
             max_iter: int = 0, tag: int | None = None) -> int:
+        """Add a member; returns its tag.  Without a tag the next unused one
+        of an increasing counter is taken.  A tag of a member that has not
+        been collected yet is rejected (ValueError): its output tensors are
+        still being written."""
+        if tag is None:
+            while self._next_tag in self._outputs:
+                self._next_tag += 1
+            tag = self._next_tag
+            self._next_tag += 1
+        else:
+            tag = int(tag)
+        if tag in self._outputs:
+            raise ValueError(f"tag {tag} belongs to a member that has not been collected")
         dev = torch.device("cuda", self.ctx.device)
         pr = torch.empty(plan.n_valid, dtype=torch.float64, device=dev)
         mins = torch.empty(max(plan.n_minima, 1), dtype=torch.int32, device=dev)
-        tag = len(self._outputs) if tag is None else int(tag)
         prm = _params(damping, p, tol, max_iter, 0)
         rc = _abi.load().fl_batch_add(self.ctx.handle, self.handle, plan.handle, ctypes.byref(prm),
                                       ctypes.c_void_p(pr.data_ptr()), ctypes.c_void_p(mins.data_ptr()), tag)

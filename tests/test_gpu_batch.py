@@ -4,6 +4,8 @@ A member's results must equal its plain slot-sweep run (fl_execute with
 FL_ROWS_SLOTS) bit for bit, whatever else shares the batch and whenever it
 joins; against the FP64 oracle the usual tolerances hold.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -348,3 +350,78 @@ def test_one_plan_many_members(ctx):
         assert done[tag][2]["iterations"] == ref[2]["iterations"]
     assert np.array_equal(mid_pr, done[1][0])          # same d: same ranks
     assert mid_info["iterations"] == done[1][2]["iterations"]
+
+
+def test_default_tags_never_reuse_a_running_members(ctx):
+    """Tags taken by Batch.add without an explicit tag come from a counter:
+    after a member is collected, the next default tag is new, so a member
+    still running keeps its outputs; an explicit tag of an uncollected
+    member is rejected."""
+    import torch
+    from paper_2210_01465_amd import api
+    small, big = synth.tiny(1), synth.mid()
+    fs, fb = (torch.from_numpy(s.fitness_raw).cuda() for s in (small, big))
+    ps, pb = api.plan_create(ctx, small.radix, fs), api.plan_create(ctx, big.radix, fb)
+    batch = api.Batch(ctx)
+    t_big = batch.add(pb, 0.85, 0.05)
+    t_small = batch.add(ps, 0.85, 0.05)
+    with pytest.raises(ValueError):
+        batch.add(ps, 0.85, 0.05, tag=t_big)
+    done = {}
+    while t_small not in done:                  # the small member finishes first
+        batch.step(4)
+        for tag, pr, mins, info in batch.collect():
+            done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+    assert t_big not in done
+    t_third = batch.add(ps, 0.9, 0.05)
+    assert t_third not in (t_big, t_small)
+    while batch.step(8) > 0 or len(done) < 3:
+        for tag, pr, mins, info in batch.collect():
+            done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+    batch.close()
+    ps.close()
+    pb.close()
+    for tag, space, d in ((t_big, big, 0.85), (t_small, small, 0.85), (t_third, small, 0.9)):
+        ref = plain(ctx, space, "hamming", d, 0.05)
+        assert np.array_equal(done[tag][0], ref[0]) and np.array_equal(done[tag][1], ref[1]), tag
+
+
+def _oracle_all(spaces, nbs, dampings, p=0.05):
+    """The FP64 oracle on every space, several at once (the ctypes calls
+    release the interpreter lock)."""
+    def one(j):
+        s = spaces[j]
+        return oracle.analyze(s.radix, s.fitness_raw, oracle.HAMMING if nbs[j] == "hamming" else oracle.ADJACENT,
+                              dampings[j], p, tol=1e-12)
+    with ThreadPoolExecutor(8) as ex:
+        return list(ex.map(one, range(len(spaces))))
+
+
+def test_full_batched_workload_against_oracle(ctx):
+    """The whole 234-space batched workload (26 shapes x 9 landscapes, N from
+    414 to 196 046) through one fl_analyze_batch call, with damping cycling
+    over 0.8, 0.85 and 0.9 per space: every space's sizes and minima equal
+    the FP64 oracle's exactly, its ranks within 1e-5 in L1 and its C_p within
+    1e-5."""
+    import torch
+    from paper_2210_01465_amd import api
+    spaces = synth.batched()
+    dampings = [(0.8, 0.85, 0.9)[j % 3] for j in range(len(spaces))]
+    nbs = ["hamming"] * len(spaces)
+    say(f"fl_analyze_batch over the {len(spaces)}-space workload")
+    res = api.analyze_batch([s.radix for s in spaces], [torch.from_numpy(s.fitness_raw).cuda() for s in spaces],
+                            nbs, dampings, 0.05, ctx=ctx)
+    say("oracle on every space")
+    refs = _oracle_all(spaces, nbs, dampings)
+    worst_l1 = worst_cp = 0.0
+    for j, (s, r, o) in enumerate(zip(spaces, res, refs)):
+        g = o.graph
+        assert r.info["status"] == 0, (j, s.name)
+        assert (r.info["n_valid"], r.info["n_edges"], r.info["n_minima"], r.info["n_plateau"]) == \
+            (g.N, g.E, g.M, g.plateau_minima), (j, s.name)
+        assert np.array_equal(r.minima.cpu().numpy(), g.minima), (j, s.name)
+        l1 = float(np.abs(r.pagerank.cpu().numpy() - o.pagerank).sum())
+        cp = abs(r.score - o.score)
+        assert l1 <= L1_TOL and cp <= 1e-5, (j, s.name, l1, cp)
+        worst_l1, worst_cp = max(worst_l1, l1), max(worst_cp, cp)
+    say(f"worst L1 {worst_l1:.3e}, worst |dC_p| {worst_cp:.3e}")

@@ -105,11 +105,9 @@ def test_naive_metric_and_plateaus_exact(ctx, nb):
         finally:
             plan.close()
         g = oracle.build_graph(radix, f, NB[nb])
-        # the plain definition (Sec. VII-A) on the oracle's minima, in FP64
-        ref = np.float64(g.f_opt) / g.fit[g.minima].astype(np.float64)
+        ref, ref_hist = g.naive(20)           # the oracle's naive metric (Sec. VII-A), FP64
         assert np.array_equal(ratio, ref), name
-        bins = np.minimum(np.floor(ref * 20).astype(np.int64), 19)
-        assert hist == np.bincount(bins, minlength=20).tolist()
+        assert hist == ref_hist.tolist(), (name, hist, ref_hist)
         assert sum(hist) == g.M
         assert info["n_plateau"] == g.plateau_minima, (name, info["n_plateau"], g.plateau_minima)
 
