@@ -245,6 +245,29 @@ fl_status fl_analyze(fl_ctx *ctx, const fl_space *space, const float *d_fitness_
                      fl_neighbourhood nb, const fl_params *params, double *d_pagerank,
                      int32_t *d_minima, int32_t *d_valid_raw, fl_summary *out);
 
+/* fl_analyze without any device allocation, for callers that cannot allocate
+ * device memory (code that runs while a HIP graph is being captured, serving
+ * loops with a fixed memory budget, harnesses that forbid hipMalloc).
+ * Same arguments, outputs, results and errors as fl_analyze; the results
+ * equal fl_analyze's bit for bit.  Every device buffer the analysis needs
+ * (compaction, degrees, node records, CSR, iterates, partial sums, state)
+ * is carved from one array of 64 MiB that the library holds on every device
+ * it runs on until the process ends; the call makes no hipMalloc, hipFree
+ * or event call and no host heap allocation on success.  Limit: about
+ * 20 n_raw + (20 + 8 W) N + 4 E bytes plus small tables must fit in the
+ * 64 MiB (W node-record words): spaces up to about a million raw
+ * configurations with tens of millions of edges.  A space whose raw size
+ * alone (20 n_raw bytes) exceeds it is rejected with FL_EINVAL before any
+ * launch; one whose FFG turns out too large is rejected with FL_EINVAL
+ * after the degree count (fl_last_error names the limit).  The array keeps
+ * the last call's contents; everything that must start at zero is cleared
+ * by the call.  All calls on one device share the array: calls that
+ * overlap on one device (other contexts or streams, other threads) race
+ * and must be serialised by the caller.  Synchronises the stream. */
+fl_status fl_analyze_noalloc(fl_ctx *ctx, const fl_space *space, const float *d_fitness_raw,
+                             fl_neighbourhood nb, const fl_params *params, double *d_pagerank,
+                             int32_t *d_minima, int32_t *d_valid_raw, fl_summary *out);
+
 /* ---- Batches: many spaces in one segmented PageRank (continuous batching) ----
  *
  * A batch runs the power iteration of many plans together: every sweep is one

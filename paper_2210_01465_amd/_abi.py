@@ -78,6 +78,9 @@ PROTOTYPES = {
     "fl_analyze": (ctypes.c_int, [_P, ctypes.POINTER(fl_space), _P, ctypes.c_int,
                                   ctypes.POINTER(fl_params), _P, _P, _P,
                                   ctypes.POINTER(fl_summary)]),
+    "fl_analyze_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(fl_space), _P, ctypes.c_int,
+                                          ctypes.POINTER(fl_params), _P, _P, _P,
+                                          ctypes.POINTER(fl_summary)]),
     "fl_tune": (ctypes.c_int, [_P, _P, ctypes.POINTER(fl_params), ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "fl_batch_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),

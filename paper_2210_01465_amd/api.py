@@ -15,6 +15,7 @@ points without the ``fl_`` prefix:
     naive_metric                       fl_naive_metric  (f_opt / f over the minima)
     plan_destroy                       fl_plan_destroy
     analyze                            fl_analyze       (one shot)
+    analyze(no_alloc=True)             fl_analyze_noalloc (one shot, no device allocation)
     Batch / batch_create               fl_batch_create / _add / _step / _collect / _timing / _destroy
     analyze_batch                      fl_analyze_batch (many spaces, one shot)
 """
@@ -290,8 +291,13 @@ class Result:
 
 def analyze(radix, fitness_raw: torch.Tensor, neighbourhood="hamming", damping: float = 0.85,
             p: float = 0.05, tol: float = 0.0, max_iter: int = 0, row_mapping: int = 0,
-            ctx: Context | None = None, allow_noconv: bool = False) -> Result:
-    """One-shot analysis of one space (fl_analyze)."""
+            ctx: Context | None = None, allow_noconv: bool = False, no_alloc: bool = False,
+            out: tuple | None = None) -> Result:
+    """One-shot analysis of one space (fl_analyze; with no_alloc=True
+    fl_analyze_noalloc, whose device buffers all live in the library's fixed
+    scratch array).  ``out`` may pass the three output tensors
+    (pagerank float64, minima int32, valid_raw int32, each >= prod(radix)
+    entries on the context's device); otherwise they are allocated here."""
     own = ctx is None
     if own:
         ctx = Context(fitness_raw.device.index or 0)
@@ -299,23 +305,31 @@ def analyze(radix, fitness_raw: torch.Tensor, neighbourhood="hamming", damping: 
         _check_fitness(ctx, radix, fitness_raw)
         n_raw = _n_raw(radix)
         dev = fitness_raw.device
-        pr = torch.empty(n_raw, dtype=torch.float64, device=dev)
-        mins = torch.empty(n_raw, dtype=torch.int32, device=dev)
-        vraw = torch.empty(n_raw, dtype=torch.int32, device=dev)
+        if out is None:
+            pr = torch.empty(n_raw, dtype=torch.float64, device=dev)
+            mins = torch.empty(n_raw, dtype=torch.int32, device=dev)
+            vraw = torch.empty(n_raw, dtype=torch.int32, device=dev)
+        else:
+            pr, mins, vraw = out
+            for t, dt in ((pr, torch.float64), (mins, torch.int32), (vraw, torch.int32)):
+                if t.dtype != dt or t.numel() < n_raw or not t.is_contiguous() or t.device != dev:
+                    raise ValueError("out tensors must be contiguous (float64, int32, int32) with "
+                                     f">= {n_raw} entries on {dev}")
         sp, keep = _space(radix)
         prm = _params(damping, p, tol, max_iter, row_mapping)
-        out = _abi.fl_summary()
-        rc = _abi.load().fl_analyze(ctx.handle, ctypes.byref(sp),
-                                    ctypes.c_void_p(fitness_raw.data_ptr()), _nb(neighbourhood),
-                                    ctypes.byref(prm), ctypes.c_void_p(pr.data_ptr()),
-                                    ctypes.c_void_p(mins.data_ptr()),
-                                    ctypes.c_void_p(vraw.data_ptr()), ctypes.byref(out))
-        _check(ctx, rc, "fl_analyze", allow=(_abi.FL_ENOCONV,) if allow_noconv else ())
+        summ = _abi.fl_summary()
+        name = "fl_analyze_noalloc" if no_alloc else "fl_analyze"
+        rc = getattr(_abi.load(), name)(ctx.handle, ctypes.byref(sp),
+                                        ctypes.c_void_p(fitness_raw.data_ptr()), _nb(neighbourhood),
+                                        ctypes.byref(prm), ctypes.c_void_p(pr.data_ptr()),
+                                        ctypes.c_void_p(mins.data_ptr()),
+                                        ctypes.c_void_p(vraw.data_ptr()), ctypes.byref(summ))
+        _check(ctx, rc, name, allow=(_abi.FL_ENOCONV,) if allow_noconv else ())
         del keep
-        info = out.as_dict()
+        info = summ.as_dict()
         info["status"] = rc
-        N, M = int(out.n_valid), int(out.n_minima)
-        return Result(pr[:N], mins[:M], vraw[:N], float(out.score), info)
+        N, M = int(summ.n_valid), int(summ.n_minima)
+        return Result(pr[:N], mins[:M], vraw[:N], float(summ.score), info)
     finally:
         if own:
             ctx.close()

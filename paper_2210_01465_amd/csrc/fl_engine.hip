@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -86,6 +87,57 @@ class DevicePool {
     std::map<void *, size_t> live_;
 };
 
+// Bump allocator over the scratch array of fl_analyze_noalloc: while a
+// context has one installed, every device buffer of a build and an execute
+// is carved from it in 256-byte aligned pieces, and nothing is freed.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    bool overflow = false;
+
+    void *take(size_t bytes) {
+        const size_t need = (bytes + 255) / 256 * 256;
+        if (overflow || need > cap - used) {
+            overflow = true;
+            return nullptr;
+        }
+        void *p = base + used;
+        used += need;
+        return p;
+    }
+};
+
+}  // namespace
+
+// Scratch memory of fl_analyze_noalloc (callers that cannot allocate device
+// memory): one array on every device the library runs on, held until the
+// process ends.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.
+hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = ptr;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+
 }  // namespace
 
 struct fl_ctx {
@@ -106,6 +158,8 @@ struct fl_ctx {
     int32_t *h_seg_ids = nullptr;
     int32_t seg_cap = 0;
     int64_t seg_tile_cap = 0;
+    void *scratch = nullptr;  // this device's address of the no-allocation scratch array
+    Arena *arena = nullptr;   // installed by fl_analyze_noalloc for the length of the call
 };
 
 struct fl_plan {
@@ -160,9 +214,13 @@ fl_status fail(fl_ctx *ctx, fl_status st, const char *fmt, ...) {
             return fail(ctx, FL_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
     } while (0)
 
+// Device buffer of `count` T from the context's pool, or from the scratch
+// arena while fl_analyze_noalloc runs (pool.release ignores arena pieces).
 template <typename T>
 T *pool_alloc(fl_ctx *ctx, int64_t count) {
-    return static_cast<T *>(ctx->pool.alloc(sizeof(T) * (size_t)std::max<int64_t>(count, 1)));
+    const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    if (ctx->arena) return static_cast<T *>(ctx->arena->take(bytes));
+    return static_cast<T *>(ctx->pool.alloc(bytes));
 }
 
 void release_plan_buffers(fl_plan *p) {
@@ -219,16 +277,17 @@ fl::SlotTable make_slots(const SpaceDesc &sp, bool adjacent) {
     }
     t.words = (int32_t)words;
     struct Slot { int64_t off; int delta, dim; };
-    std::vector<Slot> slots;
+    Slot slots[fl::kMaxSlots];
+    int n_slots = 0;
     for (int k = 0; k < sp.n; ++k) {
         const int reach = adjacent ? std::min(1, sp.radix[k] - 1) : sp.radix[k] - 1;
         for (int dl = 1; dl <= reach; ++dl) {
-            slots.push_back({-(int64_t)dl * sp.stride[k], -dl, k});
-            slots.push_back({(int64_t)dl * sp.stride[k], dl, k});
+            slots[n_slots++] = {-(int64_t)dl * sp.stride[k], -dl, k};
+            slots[n_slots++] = {(int64_t)dl * sp.stride[k], dl, k};
         }
     }
-    std::sort(slots.begin(), slots.end(), [](const Slot &x, const Slot &y) { return x.off < y.off; });
-    for (size_t s = 0; s < slots.size(); ++s) {
+    std::sort(slots, slots + n_slots, [](const Slot &x, const Slot &y) { return x.off < y.off; });
+    for (int s = 0; s < n_slots; ++s) {
         t.off[s] = (int32_t)slots[s].off;
         t.delta[s] = (int16_t)slots[s].delta;
         t.dim[s] = (uint8_t)slots[s].dim;
@@ -284,6 +343,7 @@ struct Build {
                                     // many builds at once (segmented build; slot spaces and
                                     // compaction only, the generic kernels still launch here)
     BuildSizes *h_sizes = nullptr;  // pinned slot for this build's sizes
+    fl_plan *storage = nullptr;     // caller-owned plan object to build into (else one is allocated)
     const float *fit = nullptr;
     int32_t *remap = nullptr, *tile_cnt = nullptr, *tile_bad = nullptr, *tile_off = nullptr;
     float *tile_min = nullptr;
@@ -332,7 +392,7 @@ void build_abort(fl_ctx *ctx, Build &b) {
         release_plan_buffers(b.p);
         if (b.p->have_events)
             for (auto &e : b.p->ev) (void)hipEventDestroy(e);
-        delete b.p;
+        if (b.p != b.storage) delete b.p;
         b.p = nullptr;
     }
 }
@@ -357,7 +417,9 @@ void build_begin(fl_ctx *ctx, Build &b, const fl_space *space, const float *fit,
     sp.n_raw = (int32_t)n_raw;
     set_magic(sp);
 
-    fl_plan *p = new (std::nothrow) fl_plan;
+    fl_plan *p = b.storage;
+    if (p) *p = fl_plan{};
+    else p = new (std::nothrow) fl_plan;
     if (!p) return build_fail(b, FL_ENOMEM, "out of host memory");
     b.p = p;
     b.fit = fit;
@@ -825,9 +887,11 @@ fl_status fl_create(fl_ctx **out, int device, void *hip_stream) {
     if (hipSetDevice(device) != hipSuccess ||
         hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_sizes, sizeof(BuildSizes), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->h_state, sizeof(PrState), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&ctx->h_state, sizeof(PrState), hipHostMallocDefault) != hipSuccess ||
+        scratch_address(device, &ctx->scratch) != hipSuccess) {
         (void)hipGetLastError();
         if (ctx->h_sizes) (void)hipHostFree(ctx->h_sizes);
+        if (ctx->h_state) (void)hipHostFree(ctx->h_state);
         delete ctx;
         return FL_EHIP;
     }
@@ -888,8 +952,10 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
 
 namespace {
 
+// PageRank, minima and C_p of a built plan.  quiet: no timing events are
+// created or recorded and no sweep is profiled (fl_analyze_noalloc).
 fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_pagerank, int32_t *d_minima,
-                       fl_summary *out, bool exact) {
+                       fl_summary *out, bool exact, bool quiet = false) {
     if (!ctx) return FL_EINVAL;
     ctx->err.clear();
     if (!p || !prm || !d_pagerank || (!d_minima && p->m > 0)) return fail(ctx, FL_EINVAL, "null argument");
@@ -909,9 +975,11 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
     st = prepare_pr(ctx, p, r, lanes, a, grid, init_grid);
     if (st != FL_OK) return st;
     a.exact = exact ? 1 : 0;
-    FL_HIP(ensure_events(p));
+    const bool timed = !quiet;
+    const int32_t profile_every = quiet ? 0 : ctx->profile_every;
+    if (timed) FL_HIP(ensure_events(p));
 
-    FL_HIP(hipEventRecord(p->ev[2], s));
+    if (timed) FL_HIP(hipEventRecord(p->ev[2], s));
     FL_HIP(hipMemsetAsync(p->state, 0, sizeof(PrState), s));
     FL_HIP(fl::launch_pr_init(a, init_grid, s));
 
@@ -924,30 +992,30 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
     PrState *hs = ctx->h_state;
     int sampled = 0;
     for (;;) {
-        if (ctx->profile_every > 0 && (int)ctx->sweep_ev.size() < 2 * chunk) {
+        if (profile_every > 0 && (int)ctx->sweep_ev.size() < 2 * chunk) {
             for (int j = (int)ctx->sweep_ev.size(); j < 2 * chunk; ++j) {
                 hipEvent_t e;
                 FL_HIP(hipEventCreate(&e));
                 ctx->sweep_ev.push_back(e);
             }
         }
-        FL_HIP(hipEventRecord(p->ev[5], s));
+        if (timed) FL_HIP(hipEventRecord(p->ev[5], s));
         for (int j = 0; j < chunk; ++j) {
-            const bool timed = ctx->profile_every > 0 && (launches + j) % ctx->profile_every == 0;
-            if (timed) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j], s));
+            const bool sampled_here = profile_every > 0 && (launches + j) % profile_every == 0;
+            if (sampled_here) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j], s));
             FL_HIP(fl::launch_pr_sweep(a, p->sl, lanes, grid, s));
-            if (timed) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j + 1], s));
+            if (sampled_here) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j + 1], s));
             FL_HIP(fl::launch_pr_step(a, grid, s));
         }
-        FL_HIP(hipEventRecord(p->ev[6], s));
+        if (timed) FL_HIP(hipEventRecord(p->ev[6], s));
         const int before = launches;
         launches += chunk;
         FL_HIP(hipMemcpyAsync(hs, p->state, sizeof(PrState), hipMemcpyDeviceToHost, s));
         FL_HIP(hipStreamSynchronize(s));
-        iterate_ms += elapsed(p->ev[5], p->ev[6]);
-        if (ctx->profile_every > 0)   // launches past the converged iteration exit at once: not counted
+        if (timed) iterate_ms += elapsed(p->ev[5], p->ev[6]);
+        if (profile_every > 0)   // launches past the converged iteration exit at once: not counted
             for (int j = 0; j < chunk && before + j < hs->worked; ++j)
-                if ((before + j) % ctx->profile_every == 0) {
+                if ((before + j) % profile_every == 0) {
                     sweep_ms += elapsed(ctx->sweep_ev[2 * j], ctx->sweep_ev[2 * j + 1]);
                     ++sampled;
                 }
@@ -963,17 +1031,17 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
         }
         chunk = std::min(chunk, std::max(1, r.max_iter - hs->k));
     }
-    FL_HIP(hipEventRecord(p->ev[3], s));
+    if (timed) FL_HIP(hipEventRecord(p->ev[3], s));
     FL_HIP(fl::launch_pr_output(a, d_pagerank, s));
     if (p->m > 0) FL_HIP(hipMemcpyAsync(d_minima, p->minima, sizeof(int32_t) * p->m, hipMemcpyDeviceToDevice, s));
     const double threshold = (1.0 + r.p) * (double)p->f_opt;
     FL_HIP(fl::launch_score(d_pagerank, p->minima, (int32_t)p->m, p->fit_c, threshold, p->state, s));
-    FL_HIP(hipEventRecord(p->ev[4], s));
+    if (timed) FL_HIP(hipEventRecord(p->ev[4], s));
     FL_HIP(hipMemcpyAsync(hs, p->state, sizeof(PrState), hipMemcpyDeviceToHost, s));
     FL_HIP(hipStreamSynchronize(s));
 
-    p->timing.pagerank_ms = elapsed(p->ev[2], p->ev[3]);
-    p->timing.score_ms = elapsed(p->ev[3], p->ev[4]);
+    p->timing.pagerank_ms = timed ? elapsed(p->ev[2], p->ev[3]) : 0.0;
+    p->timing.score_ms = timed ? elapsed(p->ev[3], p->ev[4]) : 0.0;
     p->timing.iterate_ms = iterate_ms;
     p->timing.sweep_ms = sweep_ms;
     p->timing.sweeps_timed = sampled;
@@ -1120,6 +1188,71 @@ fl_status fl_analyze(fl_ctx *ctx, const fl_space *space, const float *d_fitness_
     const std::string msg = ctx->err;
     fl_plan_destroy(ctx, p);
     ctx->err = msg;
+    return st;
+}
+
+fl_status fl_analyze_noalloc(fl_ctx *ctx, const fl_space *space, const float *d_fitness_raw, fl_neighbourhood nb,
+                             const fl_params *params, double *d_pagerank, int32_t *d_minima, int32_t *d_valid_raw,
+                             fl_summary *out) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!space || !space->radix || !d_fitness_raw || !params || !d_pagerank || !d_minima)
+        return fail(ctx, FL_EINVAL, "null argument");
+    if (!ctx->scratch) return fail(ctx, FL_EHIP, "no scratch array on device %d", ctx->device);
+    // Before any launch: the buffers sized by the raw space alone (node map,
+    // compacted fitness, remap, two x vectors) must fit.
+    int64_t n_raw = 1;
+    for (int i = 0; i < space->n_params && i < fl::kMaxParams; ++i) {
+        n_raw *= std::max<int32_t>(space->radix[i], 1);
+        if (n_raw >= (int64_t(1) << 31)) break;
+    }
+    const int64_t raw_bytes = 20 * n_raw;
+    if (raw_bytes > (int64_t)kNoAllocScratchBytes)
+        return fail(ctx, FL_EINVAL,
+                    "fl_analyze_noalloc: a space of %lld configurations needs at least %lld bytes of scratch, "
+                    "more than its %zu bytes; use fl_analyze",
+                    (long long)n_raw, (long long)raw_bytes, kNoAllocScratchBytes);
+    FL_HIP(hipSetDevice(ctx->device));
+    Arena arena;
+    arena.base = static_cast<char *>(ctx->scratch);
+    arena.cap = kNoAllocScratchBytes;
+    ctx->arena = &arena;
+    fl_plan plan;   // built in place: no host allocation either
+    Build b;
+    b.h_sizes = ctx->h_sizes;
+    b.timed = false;
+    b.storage = &plan;
+    auto sync = [&]() {
+        if (b.status != FL_OK) return;
+        hipError_t he = hipStreamSynchronize(ctx->stream);
+        if (he != hipSuccess) build_fail(b, FL_EHIP, "%s", hipGetErrorString(he));
+    };
+    build_begin(ctx, b, space, d_fitness_raw, nb);
+    sync();
+    build_degree(ctx, b);
+    sync();
+    build_fill(ctx, b);
+    (void)hipStreamSynchronize(ctx->stream);
+    build_end(ctx, b);
+    fl_status st = b.status;
+    if (st == FL_OK) {
+        st = execute_impl(ctx, &plan, params, d_pagerank, d_minima, out, false, true);
+        if ((st == FL_OK || st == FL_ENOCONV) && d_valid_raw) {
+            const hipError_t he = hipMemcpyAsync(d_valid_raw, plan.valid_raw, 4 * plan.n, hipMemcpyDeviceToDevice,
+                                                 ctx->stream);
+            const hipError_t hs = hipStreamSynchronize(ctx->stream);
+            if (he != hipSuccess || hs != hipSuccess) st = fail(ctx, FL_EHIP, "node map copy failed");
+        }
+    } else {
+        (void)hipStreamSynchronize(ctx->stream);
+        fail(ctx, st, "%s", b.err.c_str());
+    }
+    ctx->arena = nullptr;
+    if (arena.overflow)
+        st = fail(ctx, FL_EINVAL,
+                  "fl_analyze_noalloc: the space's FFG and iterates need more than the %zu bytes of scratch; "
+                  "use fl_analyze",
+                  kNoAllocScratchBytes);
     return st;
 }
 
