@@ -162,7 +162,7 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
  *   out         receives the full summary.
  * Errors: FL_EINVAL (damping not in (0,1), p < 0 or not finite, tol_l1 < 0,
  * max_iter < 0, bad row_mapping or FL_ROWS_SLOTS on a space with more than
- * 128 candidate slots), FL_ENOCONV (outputs written, summary holds
+ * 256 candidate slots), FL_ENOCONV (outputs written, summary holds
  * the residual), FL_ENOMEM, FL_EHIP.  Synchronises the stream. */
 fl_status fl_execute(fl_ctx *ctx, fl_plan *plan, const fl_params *params,
                      double *d_pagerank, int32_t *d_minima, fl_summary *out);

@@ -260,7 +260,6 @@ void set_magic(SpaceDesc &sp) {
 // Candidate slots sorted by raw-index offset: Hamming gives parameter k the
 // deltas +-1 .. +-(radix_k - 1), adjacent +-1.  A node record holds the slot
 // bits plus 40 bits of out_deg and raw index, in at most fl::kMaxWords words.
-// Slots rounded up to whole batches of 32 (the lane-mask table's row length).
 // Stride of the two halves of the device offset table: the sweep reads whole
 // batches of offsets (up to 64 past the last slot), so k rounded up to 64, plus 64.
 int32_t k_pad_of(const fl::SlotTable &sl) { return (sl.k + 63) / 64 * 64 + 64; }

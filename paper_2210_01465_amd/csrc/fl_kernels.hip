@@ -905,13 +905,9 @@ __global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
 }
 
 // Tiles of the persistent grid.  XCD j = b % 8 owns the contiguous j-th
-// eighth of the tiles.  In "front" order (FL_TILE_ORDER 0) its workgroups
-// take consecutive tiles in turn, so at any time an XCD sweeps a narrow band
-// of nodes and the x values that band gathers stay in its L2; in "block"
-// order (1) each workgroup sweeps its own contiguous run of tiles.
-#ifndef FL_TILE_ORDER
-#define FL_TILE_ORDER 0
-#endif
+// eighth of the tiles, and its workgroups take consecutive tiles in turn, so
+// at any time an XCD sweeps a narrow band of nodes and the x values that band
+// gathers stay in its L2.
 struct TileWalk {
     int32_t first, end, step;
     __device__ TileWalk(int32_t n_tiles) {
@@ -920,16 +916,9 @@ struct TileWalk {
         const int32_t per = (n_tiles + kXcds - 1) / kXcds;
         const int32_t lo = per * xcd, hi = min(per * (xcd + 1), n_tiles);
         const int nb = g / kXcds, l = blockIdx.x / kXcds;
-#if FL_TILE_ORDER == 0
         first = lo + l;
         end = hi;
         step = nb;
-#else
-        const int32_t run = (per + nb - 1) / nb;
-        first = lo + l * run;
-        end = min(first + run, hi);
-        step = 1;
-#endif
     }
 };
 
