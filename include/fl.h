@@ -281,7 +281,10 @@ fl_status fl_analyze_noalloc(fl_ctx *ctx, const fl_space *space, const float *d_
  * from the context's device cache at fl_batch_add, returned when it leaves),
  * so one plan may be a member several times at once (say with different
  * damping or p), in one or several batches; it must stay alive while it is
- * a member.  fl_execute on a plan does not disturb its batch members. */
+ * a member.  The plan may come from another context on the same device (for
+ * example one that builds FFGs on a second stream): its build must be
+ * complete (fl_plan_create has returned), and it is still destroyed through
+ * its own context.  fl_execute on a plan does not disturb its batch members. */
 typedef struct fl_batch fl_batch;
 
 fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out);
@@ -302,7 +305,8 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *batch, fl_plan *plan, const fl_par
                        double *d_pagerank, int32_t *d_minima, int64_t tag);
 
 /* Run up to `sweeps` power-iteration sweeps (Sec. VII-B) for every running
- * member; members that converge or reach max_iter finish: their ranks,
+ * member (up to 4 x `sweeps` for small members, see fl_batch_set_small);
+ * members that converge or reach max_iter finish: their ranks,
  * minima and C_p (Sec. VII-B, eq. 3) are written.  *n_running receives the
  * number of members not yet finished.  The sweep loop of a step (per sweep:
  * one launch per node-record width, then the step launch) is captured once
@@ -328,6 +332,15 @@ fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *batch, int64_t *sweeps, d
 /* Use the captured HIP graph for the sweep loop (enable != 0, the default)
  * or launch its kernels one by one.  Results are identical either way. */
 fl_status fl_batch_set_graphs(fl_ctx *ctx, fl_batch *batch, int32_t enable);
+
+/* Members of at most max_tiles tiles of 256 nodes (default 16, i.e. up to
+ * 4096 nodes; 0 = none; at most 64) iterate inside one workgroup each: one
+ * launch per record width and step runs up to 4 x `sweeps` of their sweeps
+ * and steps back to back (until they stop), on a second stream of the
+ * batch, while the other members' sweep loop runs on the context's stream.
+ * Their results equal the plain slot sweep's bit for bit as well.  Takes
+ * effect at the next fl_batch_step. */
+fl_status fl_batch_set_small(fl_ctx *ctx, fl_batch *batch, int32_t max_tiles);
 
 /* One-shot batched analysis of n_spaces spaces (Sec. VII-B for each): the
  * FFGs are built together, each build stage one launch for all spaces (a

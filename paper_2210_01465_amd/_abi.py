@@ -93,6 +93,7 @@ PROTOTYPES = {
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int64)]),
     "fl_batch_set_graphs": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "fl_batch_set_small": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "fl_analyze_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(fl_space), _P, _P,
                                         ctypes.POINTER(fl_params), _P, _P, ctypes.POINTER(fl_summary)]),
 }

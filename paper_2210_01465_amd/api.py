@@ -408,6 +408,12 @@ class Batch:
         _check(self.ctx, _abi.load().fl_batch_set_graphs(self.ctx.handle, self.handle, int(bool(enable))),
                "fl_batch_set_graphs")
 
+    def set_small(self, max_tiles: int) -> None:
+        """Members of at most max_tiles tiles of 256 nodes iterate in one
+        workgroup each (fl_batch_set_small; 0 = none, default 16)."""
+        _check(self.ctx, _abi.load().fl_batch_set_small(self.ctx.handle, self.handle, int(max_tiles)),
+               "fl_batch_set_small")
+
     def close(self):
         if self.handle:
             _abi.load().fl_batch_destroy(self.ctx.handle, self.handle)

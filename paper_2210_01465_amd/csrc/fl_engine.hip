@@ -719,6 +719,11 @@ struct fl_batch {
     // shapes replays instead of recapturing; dropped when the tables move)
     bool use_graphs = true;
     hipStream_t capture_stream = nullptr;  // private, only ever captured (the context's stream may be the null stream)
+    // members of at most small_tiles tiles (0: none) iterate in one workgroup
+    // each, on a second stream of the same priority, alongside the others
+    int32_t small_tiles = fl::kSmallTiles;
+    hipStream_t side_stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     struct Shape {
         int32_t sweeps = 0, finish_grid = 0;
         int32_t grid[fl::kMaxWords + 1] = {};
@@ -1324,10 +1329,12 @@ fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out) {
         }
     }
     fl_status st = batch_reserve(b, 16, 1024);
-    if (st == FL_OK && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (st == FL_OK && (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess ||
+                        hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking) != hipSuccess ||
+                        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)) {
         (void)hipGetLastError();
-        b->capture_stream = nullptr;
-        st = fail(ctx, FL_EHIP, "hipStreamCreateWithFlags failed");
+        st = fail(ctx, FL_EHIP, "stream or event creation failed");
     }
     if (st == FL_OK) {
         b->d_counts = pool_alloc<int32_t>(ctx, fl_batch::kCounts);
@@ -1340,6 +1347,9 @@ fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out) {
     if (st != FL_OK) {
         batch_free_tables(b);
         if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+        if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
+        if (b->fork) (void)hipEventDestroy(b->fork);
+        if (b->join) (void)hipEventDestroy(b->join);
         ctx->pool.release(b->d_counts);
         for (auto &e : b->ev)
             if (e) (void)hipEventDestroy(e);
@@ -1360,6 +1370,10 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *b) {
     batch_free_tables(b);
     batch_free_graphs(b);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    (void)hipStreamSynchronize(b->side_stream);
+    (void)hipStreamDestroy(b->side_stream);
+    (void)hipEventDestroy(b->fork);
+    (void)hipEventDestroy(b->join);
     ctx->pool.release(b->d_counts);
     if (b->h_counts) (void)hipHostFree(b->h_counts);
     for (auto &e : b->ev) (void)hipEventDestroy(e);
@@ -1372,7 +1386,10 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     if (!ctx) return FL_EINVAL;
     ctx->err.clear();
     if (!b || !p || !prm || !d_pagerank || (!d_minima && p->m > 0)) return fail(ctx, FL_EINVAL, "null argument");
-    if (b->ctx != ctx || p->ctx != ctx) return fail(ctx, FL_EINVAL, "batch or plan belongs to another context");
+    // a plan built by another context on the same device may join (its FFG
+    // is only read; the member's own buffers come from this context)
+    if (b->ctx != ctx) return fail(ctx, FL_EINVAL, "batch belongs to another context");
+    if (p->ctx->device != ctx->device) return fail(ctx, FL_EINVAL, "plan is on another device");
     if (p->sl.words == 0 || x_bytes_of(p) == 0)
         return fail(ctx, FL_EINVAL, "space has %d candidate slots or 2^29+ configurations: use fl_execute",
                     p->sl.k);
@@ -1449,18 +1466,29 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         for (int32_t t = 0; t < tiles_of(m.plan); ++t) t_init[nt_init++] = {m.slot, t};
         m.phase = 1;
     }
+    // running members: those the segmented launches sweep first (their ids
+    // are the step kernel's list), then the small ones grouped by width
+    auto small = [&](const fl_batch::Member &m) { return b->small_tiles > 0 && tiles_of(m.plan) <= b->small_tiles; };
     int32_t n_run = 0;
     int64_t group_begin[fl::kMaxWords + 2] = {};
     int64_t nt = 0;
     for (int w = 1; w <= fl::kMaxWords; ++w) {
         group_begin[w] = nt;
         for (auto &m : b->members) {
-            if (m.phase != 1 || m.plan->sl.words != w) continue;
+            if (m.phase != 1 || m.plan->sl.words != w || small(m)) continue;
             i_run[n_run++] = m.slot;
             for (int32_t t = 0; t < tiles_of(m.plan); ++t) t_sweep[nt++] = {m.slot, t};
         }
     }
     group_begin[fl::kMaxWords + 1] = nt;
+    int32_t small_begin[fl::kMaxWords + 2] = {};
+    int32_t n_all = n_run;
+    for (int w = 1; w <= fl::kMaxWords; ++w) {
+        small_begin[w] = n_all;
+        for (auto &m : b->members)
+            if (m.phase == 1 && m.plan->sl.words == w && small(m)) i_run[n_all++] = m.slot;
+    }
+    small_begin[fl::kMaxWords + 1] = n_all;
     int32_t *hc = b->h_counts;
     memset(hc, 0, sizeof(int32_t) * fl_batch::kCounts);
     for (int w = 1; w <= fl::kMaxWords; ++w) {
@@ -1484,9 +1512,23 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         FL_HIP(fl::launch_batch_init(b->d_members, b->d_tiles, (int32_t)nt_init, b->d_ids, n_init,
                                      b->d_counts + fl_batch::kInitCount, s));
     }
+    if (n_all > 0) FL_HIP(hipMemcpyAsync(d_run, i_run, sizeof(int32_t) * n_all, hipMemcpyHostToDevice, s));
+    // small members: on the side stream, after the uploads and initial
+    // iterates, up to 4 x sweeps each (most finish within the step)
+    const bool side = n_all > n_run && sweeps > 0;
+    if (side) {
+        FL_HIP(hipEventRecord(b->fork, s));
+        FL_HIP(hipStreamWaitEvent(b->side_stream, b->fork, 0));
+        for (int w = 1; w <= fl::kMaxWords; ++w) {
+            const int32_t cnt = small_begin[w + 1] - small_begin[w];
+            if (cnt == 0) continue;
+            FL_HIP(fl::launch_batch_small(b->d_members, d_run + small_begin[w], cnt, w, 4 * sweeps,
+                                          std::min(cnt, 1024), b->side_stream));
+        }
+        FL_HIP(hipEventRecord(b->join, b->side_stream));
+    }
     if (n_run > 0 && sweeps > 0) {
         FL_HIP(hipMemcpyAsync(d_sweep, t_sweep, sizeof(fl::TileRef) * nt, hipMemcpyHostToDevice, s));
-        FL_HIP(hipMemcpyAsync(d_run, i_run, sizeof(int32_t) * n_run, hipMemcpyHostToDevice, s));
         // launch shape: grids rounded up to powers of two (times the XCD
         // count) so that small changes of membership reuse the captured graph
         fl_batch::Shape shape;
@@ -1565,9 +1607,10 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         b->sweeps += sweeps;
     }
     // state of every running member
-    if (n_run > 0) {
-        FL_HIP(fl::launch_batch_states(b->d_members, d_run, n_run, b->d_states, s));
-        FL_HIP(hipMemcpyAsync(b->h_states, b->d_states, sizeof(PrState) * n_run, hipMemcpyDeviceToHost, s));
+    if (side) FL_HIP(hipStreamWaitEvent(s, b->join, 0));
+    if (n_all > 0) {
+        FL_HIP(fl::launch_batch_states(b->d_members, d_run, n_all, b->d_states, s));
+        FL_HIP(hipMemcpyAsync(b->h_states, b->d_states, sizeof(PrState) * n_all, hipMemcpyDeviceToHost, s));
     }
     FL_HIP(hipStreamSynchronize(s));
     if (n_run > 0 && sweeps > 0) b->sweep_ms += elapsed(b->ev[0], b->ev[1]);
@@ -1575,7 +1618,7 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
     int32_t n_fin = 0;
     int64_t nt_fin = 0;
     std::vector<int> fin_index;
-    for (int32_t j = 0; j < n_run; ++j) {
+    for (int32_t j = 0; j < n_all; ++j) {
         if (!b->h_states[j].done) continue;
         for (size_t q = 0; q < b->members.size(); ++q) {
             if (b->members[q].slot != i_run[j]) continue;
@@ -1640,6 +1683,15 @@ fl_status fl_batch_timing(fl_ctx *ctx, const fl_batch *b, int64_t *sweeps, doubl
     if (sweep_ms) *sweep_ms = b->sweep_ms;
     if (graph_launches) *graph_launches = b->graph_launches;
     if (graph_captures) *graph_captures = b->graph_captures;
+    return FL_OK;
+}
+
+fl_status fl_batch_set_small(fl_ctx *ctx, fl_batch *b, int32_t max_tiles) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!b || b->ctx != ctx) return fail(ctx, FL_EINVAL, "bad batch");
+    if (max_tiles < 0 || max_tiles > 64) return fail(ctx, FL_EINVAL, "max_tiles must be in [0, 64]");
+    b->small_tiles = max_tiles;
     return FL_OK;
 }
 

@@ -18,6 +18,7 @@ constexpr int kBatch = 16;                        // candidate slots whose loads
 constexpr int kMaxFinishGrid = 1024;              // workgroups of the batched step kernel (grid-stride)
 constexpr int kFinishBlock = 1024;                // threads of a step kernel workgroup (1 mod 3)
 constexpr int kFillStage = 6144;                  // col_idx entries of a tile assembled in LDS by the fill
+constexpr int kSmallTiles = 16;                   // batch members of at most this many tiles iterate in one workgroup
 
 // Mixed-radix description of a search space X = S_1 x ... x S_n, parameter 0
 // most significant: stride[i] = prod_{j>i} radix[j].  Digits are peeled off
@@ -228,6 +229,11 @@ hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, 
 hipError_t batch_sweep_blocks_per_cu(int words, int *blocks);
 hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, const int32_t *n_members_dev,
                                int grid, hipStream_t stream);
+// Small members of record width `words`, one workgroup each (grid-stride):
+// up to max_sweeps sweeps and steps per member, back to back in the
+// workgroup, until it stops.
+hipError_t launch_batch_small(const BatchMember *members, const int32_t *member_ids, int32_t n_members, int words,
+                              int32_t max_sweeps, int grid, hipStream_t stream);
 hipError_t launch_batch_output(const BatchMember *members, const TileRef *tiles, int32_t n_tiles,
                                const int32_t *member_ids, int32_t n_members, PrState *states_out,
                                hipStream_t stream);

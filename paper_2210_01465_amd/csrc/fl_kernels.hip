@@ -1012,14 +1012,17 @@ struct SweepTile {
 // more often, 64 and 96 lower the occupancy (80 and 112 VGPRs).
 constexpr int kSweepBatch = 48;
 
+// The node of lane lt (0 <= lt < kBlock) of the tile: its new value, and its
+// terms of the tile's three partial sums in ps, pr, pk (reduced by the caller).
 template <int W, bool BUF>
-__device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
+__device__ __forceinline__ void sweep_tile_sums(const SweepTile &q, int32_t tile, int lt, double &ps, double &pr,
+                                                double &pk) {
     // descriptor based at x_in + off[0] (<= x_in), so every slot's byte offset
     // 4 (off[s] - off[0]) is a non-negative scalar
     const int32_t off0 = q.off[0];
     const __amdgpu_buffer_rsrc_t xr =
         __builtin_amdgcn_make_buffer_rsrc((void *)(q.x_in + off0), (short)0, q.x_bytes, 0x00020000);
-    const int32_t v = tile * kBlock + threadIdx.x;
+    const int32_t v = tile * kBlock + lt;
     const bool active = v < q.n;
     Record<W> r;
     float yin = 0.0f;
@@ -1033,7 +1036,7 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
     const int32_t i = r.raw();
     const uint32_t i4 = 4u * (uint32_t)i;
     // a wave past the last node (in the last tile) has nothing to gather
-    const int32_t first = __builtin_amdgcn_readfirstlane(tile * kBlock + (int32_t)(threadIdx.x & ~63u));
+    const int32_t first = __builtin_amdgcn_readfirstlane(tile * kBlock + (lt & ~63));
     const bool live = first < q.n;
     const_ptr<int32_t> ob = q.off + q.k_pad;
     // The test of a node's in-edge bit for slot s is one class comparison:
@@ -1084,7 +1087,7 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
 #pragma unroll
         for (int u = 0; u < kB; ++u) acc += val[u];
     }
-    double ps = 0.0, pr = 0.0, pk = 0.0;
+    ps = pr = pk = 0.0;
     if (active) {
         const float yf = (float)(q.sd * (double)acc + q.c);
         q.y_out[v] = yf;
@@ -1093,6 +1096,12 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
         pr = fabs((double)yf - q.s * (double)yin);
         if (r.out_deg() == 0) pk = (double)yf;
     }
+}
+
+template <int W, bool BUF>
+__device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
+    double ps, pr, pk;
+    sweep_tile_sums<W, BUF>(q, tile, (int)threadIdx.x, ps, pr, pk);
     write_partials(q.partials, tile, ps, pr, pk);
 }
 
@@ -1184,6 +1193,89 @@ __global__ __launch_bounds__(kFinishBlock) void k_batch_finish(const BatchMember
         if (!FIRST && m.st->done) continue;   // uniform per workgroup
         finish_step(m.st, m.partials, m.n_tiles, m.d, m.tol, m.max_iter, m.n, FIRST);
         __syncthreads();                       // block_sum3's LDS is reused by the next member
+    }
+}
+
+// Small members (at most kSmallTiles tiles): one workgroup of kFinishBlock
+// threads runs a member's sweeps and steps back to back, up to max_sweeps or
+// until it stops, with workgroup barriers instead of launches between them.
+// The four groups of kBlock threads sweep four tiles at a time; each group
+// reduces its tile's partial sums in the order of block_sum3 (wave sums, then
+// the four waves in order), and the step is finish_step itself, so a
+// member's ranks equal those of the plain slot sweep bit for bit.  Thread 0
+// (which writes the state in finish_step) hands the stop flag, k, s and c to
+// the workgroup through LDS, so every wave takes the same branches.
+constexpr int kGroups = kFinishBlock / kBlock;
+
+template <int W>
+__global__ __launch_bounds__(kFinishBlock) void k_batch_small(const BatchMember *__restrict__ members,
+                                                              const int32_t *__restrict__ member_ids,
+                                                              int32_t n_members, int32_t max_sweeps) {
+    __shared__ double part[kGroups][3][kBlock / 64];
+    __shared__ int32_t sh_done, sh_k;
+    __shared__ double sh_s, sh_c;
+    const int g = threadIdx.x / kBlock, lt = threadIdx.x % kBlock;
+    const int lane = threadIdx.x & 63, wl = lt >> 6;
+    for (int32_t j = blockIdx.x; j < n_members; j += gridDim.x) {
+        const_ptr<BatchMember> m = to_const(members) + member_ids[j];
+        PrState *st = m->st;
+        for (int32_t sweep = 0; sweep < max_sweeps; ++sweep) {
+            if (threadIdx.x == 0) {
+                sh_done = st->done;
+                sh_k = st->k;
+                sh_s = st->s;
+                sh_c = st->c;
+            }
+            __syncthreads();
+            if (sh_done) break;               // uniform
+            const int32_t k = sh_k;
+            SweepTile q;
+            q.rec = m->rec;
+            q.off = to_const(m->off);
+            q.y_in = m->y[k & 1];
+            q.x_in = m->x[k & 1];
+            q.y_out = m->y[(k + 1) & 1];
+            q.x_out = m->x[(k + 1) & 1];
+            q.partials = m->partials;
+            q.s = sh_s;
+            q.c = sh_c;
+            q.sd = q.s * m->d;
+            q.n = m->n;
+            q.k_slots = m->k_slots;
+            q.k_pad = m->k_pad;
+            q.x_bytes = m->x_bytes;
+            const int32_t n_tiles = m->n_tiles;
+            for (int32_t t0 = 0; t0 < n_tiles; t0 += kGroups) {
+                const int32_t tile = t0 + g;      // a group past the last tile only joins the barriers
+                double ps = 0.0, pr = 0.0, pk = 0.0;
+                if (tile < n_tiles) sweep_tile_sums<W, true>(q, tile, lt, ps, pr, pk);
+                ps = wave_sum(ps);
+                pr = wave_sum(pr);
+                pk = wave_sum(pk);
+                if (lane == 0) {
+                    part[g][0][wl] = ps;
+                    part[g][1][wl] = pr;
+                    part[g][2][wl] = pk;
+                }
+                __syncthreads();
+                if (lt == 0 && tile < n_tiles) {
+                    double a = part[g][0][0], b = part[g][1][0], c = part[g][2][0];
+#pragma unroll
+                    for (int w = 1; w < kBlock / 64; ++w) {
+                        a += part[g][0][w];
+                        b += part[g][1][w];
+                        c += part[g][2][w];
+                    }
+                    double *pp = m->partials + 3 * (int64_t)tile;
+                    pp[0] = a;
+                    pp[1] = b;
+                    pp[2] = c;
+                }
+                __syncthreads();                  // part is reused; the partials are visible
+            }
+            finish_step(st, m->partials, n_tiles, m->d, m->tol, m->max_iter, m->n, false);
+        }
+        __syncthreads();                          // sh_* are rewritten for the next member
     }
 }
 
@@ -1629,6 +1721,26 @@ hipError_t launch_batch_sweep(const BatchMember *members, const TileRef *tiles, 
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {(void *)&members, (void *)&tiles, (void *)&range_dev};
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+}
+
+static const void *batch_small_kernel(int words) {
+    switch (words) {
+        case 1: return (const void *)k_batch_small<1>;
+        case 2: return (const void *)k_batch_small<2>;
+        case 3: return (const void *)k_batch_small<3>;
+        case 4: return (const void *)k_batch_small<4>;
+        case 5: return (const void *)k_batch_small<5>;
+        default: return nullptr;
+    }
+}
+
+hipError_t launch_batch_small(const BatchMember *members, const int32_t *member_ids, int32_t n_members, int words,
+                              int32_t max_sweeps, int grid, hipStream_t stream) {
+    const void *fn = batch_small_kernel(words);
+    if (!fn) return hipErrorInvalidValue;
+    if (n_members <= 0 || max_sweeps <= 0) return hipSuccess;
+    void *args[] = {(void *)&members, (void *)&member_ids, (void *)&n_members, (void *)&max_sweeps};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kFinishBlock), args, 0, stream);
 }
 
 hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, const int32_t *n_members_dev,

@@ -9,6 +9,11 @@ arrive over time.  The server
 * keeps built fitness flow graphs in a device-resident LRU cache keyed by the
   request's content key, so a repeated space with another d or p only reruns
   PageRank;
+* builds the FFG of a cache miss off the serving loop when the backend can
+  (``GpuBackend(async_builds=True)``: a builder thread with its own engine
+  context on a second stream, so the build's kernels overlap the running
+  batch and no step waits for it); requests for a space whose build is in
+  flight wait for that build instead of starting another;
 * adds admitted requests to one running batch (fl_batch_*): members join and
   leave between steps of a few sweeps, so short analyses are not held behind
   long ones;
@@ -20,14 +25,17 @@ arrive over time.  The server
 
 The GPU work goes through a backend object (``build``, ``plan_bytes``,
 ``member_bytes``, ``add``, ``step``, ``collect``, ``release``, plus ``plain``
-for the one-at-a-time reference path), so the scheduling logic can be
-exercised with any backend.
+for the one-at-a-time reference path; a backend with ``async_builds`` set
+also has ``submit_build`` / ``submit_plain`` / ``poll``), so the scheduling
+logic can be exercised with any backend.
 """
 from __future__ import annotations
 
 import collections
 import gc
 import heapq
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 from typing import Any, Callable, Hashable
@@ -72,21 +80,91 @@ def footprint_estimate(radix, words: int = 2) -> int:
     return n_raw * (4 * 4) + n_raw * per_node // 2 + (1 << 20)
 
 
-class GpuBackend:
-    """The engine through the Python binding (one context, one batch)."""
+class _Builder:
+    """A thread that owns a second engine context on its own stream (default
+    priority) and runs FFG builds, lone analyses of spaces the batch cannot
+    take, and plan releases for that context, one job at a time.  The engine
+    calls release the interpreter lock, so its kernels run while the serving
+    loop steps the batch on the first context's stream.  Fitness tensors
+    handed to it must have no pending writes."""
 
-    def __init__(self, ctx=None, sweeps_per_step: int = 16):
+    def __init__(self, api, device: int):
+        import torch
+        self.api = api
+        self.device = device
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = api.Context(device, self.stream)
+        self.jobs: "queue.Queue" = queue.Queue()
+        self.done: "queue.Queue" = queue.Queue()
+        self.thread = threading.Thread(target=self._run, name="ffg-builder", daemon=True)
+        self.thread.start()
+
+    def _run(self):
+        import torch
+        torch.cuda.set_device(self.device)
+        with torch.cuda.stream(self.stream):
+            while True:
+                job = self.jobs.get()
+                if job is None:
+                    return
+                kind, a, b = job
+                try:
+                    if kind == "build":
+                        plan = self.api.plan_create(self.ctx, a.radix, a.fitness, a.neighbourhood)
+                        self.done.put(("build", a, (plan, _batchable(plan)), None))
+                    elif kind == "plain":
+                        self.done.put(("plain", b, self.api.execute(a, b.damping, b.p), None))
+                    else:
+                        a.close()
+                except Exception as e:          # handed to the serving loop, which raises it
+                    self.done.put((kind, a if kind == "build" else b, None, e))
+
+    def close(self):
+        self.jobs.put(None)
+        self.thread.join()
+        self.ctx.close()
+
+
+def _batchable(plan) -> bool:
+    words = int(plan.sizes.get("mask_words", 0))
+    return words > 0 and 4 * plan.sizes["n_raw"] < 2 ** 31
+
+
+class GpuBackend:
+    """The engine through the Python binding (one context, one batch; with
+    async_builds, a builder thread with a second context for cache misses)."""
+
+    def __init__(self, ctx=None, sweeps_per_step: int = 16, async_builds: bool = False):
         from . import api
         self.api = api
         self.ctx = ctx or api.Context(0)
         self.batch = api.Batch(self.ctx)
         self.sweeps = sweeps_per_step
+        self.async_builds = bool(async_builds)
+        self.builder = _Builder(api, self.ctx.device) if async_builds else None
 
     def build(self, req: Request):
         plan = self.api.plan_create(self.ctx, req.radix, req.fitness, req.neighbourhood)
-        words = int(plan.sizes.get("mask_words", 0))
-        batchable = words > 0 and 4 * plan.sizes["n_raw"] < 2 ** 31
-        return plan, batchable
+        return plan, _batchable(plan)
+
+    def submit_build(self, req: Request) -> None:
+        self.builder.jobs.put(("build", req, None))
+
+    def submit_plain(self, plan, req: Request) -> None:
+        self.builder.jobs.put(("plain", plan, req))
+
+    def poll(self) -> list:
+        """Finished builder jobs: ("build", req, (plan, batchable)) and
+        ("plain", req, (pagerank, minima, info)); a job that failed raises."""
+        out = []
+        while True:
+            try:
+                kind, req, res, err = self.builder.done.get_nowait()
+            except queue.Empty:
+                return out
+            if err is not None:
+                raise err
+            out.append((kind, req, res))
 
     def plan_bytes(self, plan) -> int:
         s = plan.sizes
@@ -112,23 +190,38 @@ class GpuBackend:
         return pr, mins, info
 
     def release(self, plan) -> None:
-        plan.close()
+        if self.builder is not None and plan.ctx is self.builder.ctx:
+            self.builder.jobs.put(("release", plan, None))   # its context belongs to the builder thread
+        else:
+            plan.close()
 
     def sync(self) -> None:
         import torch
         torch.cuda.synchronize()
 
     def close(self) -> None:
+        """Release the batch and the builder (after the plans it built)."""
         self.batch.close()
+        if self.builder is not None:
+            self.builder.close()
+            self.builder = None
 
 
 class Server:
-    """Continuous-batching scheduler (see the module docstring)."""
+    """Continuous-batching scheduler (see the module docstring).
+
+    Plans are held in the LRU cache (shared by any number of requests) or,
+    when larger than the cache budget, owned by the requests of their key and
+    released when the last of them finishes.  Memory accounting: every
+    admitted request reserves 16 n_raw bytes for its own iterates until it
+    joins (then its member bytes), and a build in flight reserves the
+    estimated footprint of its FFG until the plan's own size is known."""
 
     def __init__(self, backend, hbm_budget: int, cache_budget: int | None = None,
                  clock: Callable[[], float] | None = None,
                  sleep: Callable[[float], None] | None = None, pause_gc: bool = True):
         self.backend = backend
+        self.async_builds = bool(getattr(backend, "async_builds", False))
         self.pause_gc = pause_gc
         self.hbm_budget = int(hbm_budget)
         self.cache_budget = int(cache_budget if cache_budget is not None else hbm_budget // 2)
@@ -136,17 +229,21 @@ class Server:
         self.sleep = sleep or time.sleep
         self.cache: "collections.OrderedDict[Hashable, tuple]" = collections.OrderedDict()
         self.cache_bytes = 0
-        self.in_use: dict = {}            # key -> running members using the cached plan
-        self.reserved = 0                 # bytes of running members' plans not in the cache
+        self.in_use: dict = {}            # key -> requests using the cached plan
+        self.owned: dict = {}             # key -> [plan, nbytes, batchable, users] (plans above the cache budget)
+        self.reserved = 0                 # bytes of owned plans, members and admitted requests' iterates
+        self.building: dict = {}          # key -> requests waiting for the build in flight
+        self.building_bytes: dict = {}    # key -> estimated footprint reserved for that build
+        self.plain_inflight = 0           # lone analyses running on the builder
         self.peak_bytes = 0
         self.queue: list = []             # admitted order: waiting requests
-        self.running: dict = {}           # rid -> (req, key, plan, bytes, shared)
+        self.running: dict = {}           # rid -> (req, key, member bytes)
         self.done: list = []
         self.stats = collections.Counter()
 
     # -- memory accounting -------------------------------------------------
     def _held(self) -> int:
-        return self.cache_bytes + self.reserved
+        return self.cache_bytes + self.reserved + sum(self.building_bytes.values())
 
     def _evict(self, need: int, keep=None) -> None:
         for key in list(self.cache):
@@ -159,58 +256,117 @@ class Server:
             self.backend.release(plan)
             self.stats["evicted"] += 1
 
-    def _admit(self, req: Request) -> bool:
-        """Build or reuse the request's plan and add it to the batch, if the
-        budget allows; False leaves the request queued.  A plan that fits the
-        cache budget is cached and shared (members running on one FFG keep
-        their own iterate vectors); any other is owned by its request and
-        released when the request finishes."""
-        hit = self.cache.get(req.key)
+    @staticmethod
+    def _iterate_estimate(req: Request) -> int:
         n_raw = 1
         for r in req.radix:
             n_raw *= int(r)
-        need = 16 * n_raw + (footprint_estimate(req.radix) if hit is None else 0)
-        self._evict(need, keep=req.key)
+        return 16 * n_raw
+
+    def _admit(self, req: Request) -> bool:
+        """Reserve memory for the request and start it: join the batch at
+        once on a cached (or owned) plan, wait for a build of its space that
+        is in flight, or start that build.  False leaves it queued."""
+        key = req.key
+        hit = self.cache.get(key)
+        known = hit is not None or key in self.owned or key in self.building
+        it_bytes = self._iterate_estimate(req)
+        build_bytes = 0 if known else footprint_estimate(req.radix)
+        need = it_bytes + build_bytes
+        self._evict(need, keep=key)
         if self._held() + need > self.hbm_budget and (self.running or self._held() > 0):
             return False
-        if hit is None:
-            plan, batchable = self.backend.build(req)
-            nbytes = self.backend.plan_bytes(plan)
-            self.stats["built"] += 1
-            shared = nbytes <= self.cache_budget
-            if shared:
-                self.cache[req.key] = (plan, nbytes, batchable)
-                self.cache_bytes += nbytes
-            else:
-                self.reserved += nbytes
-        else:
-            self.cache.move_to_end(req.key)
+        self.reserved += it_bytes
+        self.peak_bytes = max(self.peak_bytes, self._held() + build_bytes)
+        if hit is not None:
+            self.cache.move_to_end(key)
             self.stats["cache_hits"] += 1
-            plan, nbytes, batchable = hit
-            shared = True
+            self._start(req, key, hit[0], hit[2], it_bytes)
+        elif key in self.owned:
+            self.stats["cache_hits"] += 1
+            self._start(req, key, self.owned[key][0], self.owned[key][2], it_bytes)
+        elif key in self.building:
+            self.stats["build_waits"] += 1
+            self.building[key].append(req)
+        elif self.async_builds:
+            self.stats["built"] += 1
+            self.building[key] = [req]
+            self.building_bytes[key] = build_bytes
+            self.backend.submit_build(req)
+        else:
+            self.stats["built"] += 1
+            plan, batchable = self.backend.build(req)
+            self._store(key, plan, batchable)
+            self._start(req, key, plan, batchable, it_bytes)
         self.peak_bytes = max(self.peak_bytes, self._held())
-        if not batchable:
-            # a space the batched sweep cannot take runs alone
-            pr, mins, info = self.backend.plain(plan, req)
-            self._finish(req, pr, mins, info)
-            if not shared:
-                self._release(plan, nbytes)
-            return True
-        mbytes = self.backend.member_bytes(plan)
-        self.reserved += mbytes
-        self.peak_bytes = max(self.peak_bytes, self._held())
-        self.backend.add(plan, req)
-        if shared:
-            self.in_use[req.key] = self.in_use.get(req.key, 0) + 1
-        self.running[req.rid] = (req, req.key, plan, nbytes, shared, mbytes)
         return True
 
-    def _release(self, plan, nbytes) -> None:
+    def _store(self, key, plan, batchable) -> None:
+        """A plan just built: into the cache if it fits the cache budget, else
+        owned by the requests of its key."""
+        nbytes = self.backend.plan_bytes(plan)
+        if nbytes <= self.cache_budget:
+            self.cache[key] = (plan, nbytes, batchable)
+            self.cache_bytes += nbytes
+        else:
+            self.owned[key] = [plan, nbytes, batchable, 0]
+            self.reserved += nbytes
+
+    def _use(self, key, delta: int) -> None:
+        if key in self.owned:
+            o = self.owned[key]
+            o[3] += delta
+            if o[3] == 0:
+                del self.owned[key]
+                self.reserved -= o[1]
+                self.backend.release(o[0])
+        else:
+            self.in_use[key] = self.in_use.get(key, 0) + delta
+
+    def _start(self, req: Request, key, plan, batchable, it_bytes: int) -> None:
+        """Run an admitted request on its plan: as a batch member, or alone
+        when the batched sweep cannot take the space."""
+        self._use(key, +1)
+        if not batchable:
+            if self.async_builds:
+                self.plain_inflight += 1
+                self.running[req.rid] = (req, key, it_bytes)
+                self.backend.submit_plain(plan, req)
+            else:
+                pr, mins, info = self.backend.plain(plan, req)
+                self.reserved -= it_bytes
+                self._finish(req, pr, mins, info)
+                self._use(key, -1)
+            return
+        mbytes = self.backend.member_bytes(plan)
+        self.reserved += mbytes - it_bytes
+        self.peak_bytes = max(self.peak_bytes, self._held())
+        self.backend.add(plan, req)
+        self.running[req.rid] = (req, key, mbytes)
+
+    def _end(self, rid, pr, mins, info) -> None:
+        req, key, nbytes = self.running.pop(rid)
         self.reserved -= nbytes
-        self.backend.release(plan)
+        self._finish(req, pr, mins, info)
+        self._use(key, -1)
 
     def _finish(self, req: Request, pr, mins, info) -> None:
         self.done.append(Done(req.rid, req.arrival, self.clock(), float(info["score"]), pr, mins, info))
+
+    def _poll_builder(self) -> None:
+        for kind, req, res in self.backend.poll():
+            if kind == "build":
+                plan, batchable = res
+                key = req.key
+                waiting = self.building.pop(key)
+                self.building_bytes.pop(key)
+                self._store(key, plan, batchable)
+                for r in waiting:
+                    self._start(r, key, plan, batchable, self._iterate_estimate(r))
+                self.peak_bytes = max(self.peak_bytes, self._held())
+            else:
+                self.plain_inflight -= 1
+                self._end(req.rid, *res)
 
     # -- main loop ----------------------------------------------------------
     def run(self, requests, start: float | None = None) -> list:
@@ -229,25 +385,24 @@ class Server:
         pending = list(requests)
         heapq.heapify(pending)
         t0 = self.clock() if start is None else start
-        while pending or self.queue or self.running:
+        while pending or self.queue or self.running or self.building:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 self.queue.append(heapq.heappop(pending))
+            if self.async_builds:
+                self._poll_builder()
             still = []
             for req in self.queue:
                 if not self._admit(_shift(req, t0)):
                     still.append(req)
             self.queue = still
-            if self.running:
+            members = len(self.running) - self.plain_inflight
+            if members > 0:
                 self.backend.step()
                 for tag, pr, mins, info in self.backend.collect():
-                    req, key, plan, nbytes, shared, mbytes = self.running.pop(tag)
-                    self.reserved -= mbytes
-                    self._finish(req, pr, mins, info)
-                    if shared:
-                        self.in_use[key] -= 1
-                    else:
-                        self._release(plan, nbytes)
+                    self._end(tag, pr, mins, info)
+            elif self.building or self.plain_inflight:
+                self.sleep(5e-5)              # only builder work in flight
             elif pending and not self.queue:
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
@@ -258,6 +413,13 @@ class Server:
                     if wait > 0:
                         self.sleep(min(wait, 0.001))
         return self.done
+
+    def close(self) -> None:
+        """Release every cached plan (the server must be idle)."""
+        for plan, _, _ in self.cache.values():
+            self.backend.release(plan)
+        self.cache.clear()
+        self.cache_bytes = 0
 
 
 def _shift(req: Request, t0: float) -> Request:
@@ -271,12 +433,17 @@ def _shift(req: Request, t0: float) -> Request:
 
 
 def serve_plain(backend, requests, clock: Callable[[], float] | None = None,
-                start: float | None = None, sleep: Callable[[float], None] | None = None) -> list:
-    """The one-at-a-time reference: FIFO, each analysis run alone with a
-    fresh FFG build, in arrival order."""
+                start: float | None = None, sleep: Callable[[float], None] | None = None,
+                cache_budget: int = 0) -> list:
+    """The one-at-a-time reference: FIFO, each analysis run alone in arrival
+    order.  With cache_budget > 0 it keeps the same kind of content-keyed LRU
+    plan cache as the server (plans up to that many bytes in total), so a
+    repeated space reruns only PageRank; with 0 every request builds its FFG."""
     clock = clock or time.perf_counter
     sleep = sleep or time.sleep
     t0 = clock() if start is None else start
+    cache: "collections.OrderedDict[Hashable, tuple]" = collections.OrderedDict()
+    held = 0
     done = []
     for req in sorted(requests):
         while True:
@@ -284,10 +451,26 @@ def serve_plain(backend, requests, clock: Callable[[], float] | None = None,
             if wait <= 0:
                 break
             sleep(min(wait, 0.001))
-        plan, _ = backend.build(req)
+        hit = cache.get(req.key)
+        if hit is not None:
+            cache.move_to_end(req.key)
+            plan = hit[0]
+        else:
+            plan, _ = backend.build(req)
+            nbytes = backend.plan_bytes(plan)
+            if nbytes <= cache_budget:
+                while cache and held + nbytes > cache_budget:
+                    old, ob = cache.popitem(last=False)[1]
+                    held -= ob
+                    backend.release(old)
+                cache[req.key] = (plan, nbytes)
+                held += nbytes
         pr, mins, info = backend.plain(plan, req)
-        backend.release(plan)
+        if req.key not in cache:
+            backend.release(plan)
         done.append(Done(req.rid, req.arrival + t0, clock(), float(info["score"]), pr, mins, info))
+    for plan, _ in cache.values():
+        backend.release(plan)
     return done
 
 
@@ -311,7 +494,12 @@ def latency_summary(done: list, since: float = 0.0) -> dict:
         return {"n": 0}
     span = max(d.finish for d in done) - min(d.arrival for d in done)
     edges = sum(float(d.info.get("n_edges", 0)) * float(d.info.get("iterations", 0)) for d in done)
+    # over the measured requests alone: from the first measured arrival to the last of their results
+    meas = [d for d in done if d.arrival - t0 >= since]
+    mspan = max(d.finish for d in meas) - min(d.arrival for d in meas)
     return {"n": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "max_ms": float(lat.max() * 1e3),
             "throughput_per_s": float(len(done) / span) if span > 0 else None,
+            "measured_throughput_per_s": float(len(meas) / mspan) if mspan > 0 else None,
             "gteps": float(edges / span / 1e9) if span > 0 else None}

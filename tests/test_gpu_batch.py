@@ -425,3 +425,44 @@ def test_full_batched_workload_against_oracle(ctx):
         assert l1 <= L1_TOL and cp <= 1e-5, (j, s.name, l1, cp)
         worst_l1, worst_cp = max(worst_l1, l1), max(worst_cp, cp)
     say(f"worst L1 {worst_l1:.3e}, worst |dC_p| {worst_cp:.3e}")
+
+
+def test_small_members_iterate_in_one_workgroup(ctx):
+    """Members of at most 16 tiles run their sweeps inside one workgroup on
+    the batch's second stream: with steps of 16 sweeps they finish in the
+    first step (up to 64 sweeps), while a large member keeps iterating; every
+    result equals the plain slot sweep bit for bit, with the path on or off."""
+    import torch
+    from paper_2210_01465_amd import api
+    small = [synth.tiny(s) for s in range(3)] + [s for s in synth.batched() if s.n_valid <= 4096][:12]
+    big = synth.mid()
+    spaces = small + [big]
+    for setting in (16, 0):
+        say(f"small-member path max_tiles={setting}: {len(small)} small spaces and the mid space")
+        batch = api.Batch(ctx)
+        batch.set_small(setting)
+        fits = [torch.from_numpy(s.fitness_raw).cuda() for s in spaces]
+        plans = [api.plan_create(ctx, s.radix, f, "hamming") for s, f in zip(spaces, fits)]
+        for j, pl in enumerate(plans):
+            batch.add(pl, (0.8, 0.85, 0.9)[j % 3], 0.05, tag=j)
+        done, first = {}, None
+        while True:
+            running = batch.step(16)
+            got = batch.collect()
+            if first is None:
+                first = {t for t, *_ in got}
+            for tag, pr, mins, info in got:
+                done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+            if running == 0:
+                break
+        batch.close()
+        for pl in plans:
+            pl.close()
+        if setting:
+            quick = {j for j in range(len(small)) if done[j][2]["iterations"] <= 64}
+            assert quick and quick <= first, (quick, first)
+            assert len(spaces) - 1 not in first
+        for j, s in enumerate(spaces):
+            ref = plain(ctx, s, "hamming", (0.8, 0.85, 0.9)[j % 3], 0.05)
+            assert np.array_equal(done[j][0], ref[0]), (setting, s.name)
+            assert np.array_equal(done[j][1], ref[1]) and done[j][2]["iterations"] == ref[2]["iterations"]

@@ -80,11 +80,21 @@ def test_served_results_match_oracle(large_reference):
         reqs.append(serve.Request(t, len(times) + k, ("large", "hamming"), large.radix, large_fit,
                                   "hamming", d, 0.05))
     reqs.sort()
-    print(f"[case] serve {len(reqs)} requests ({len(spaces)} spaces + 2 large) against the oracle", flush=True)
-    backend = serve.GpuBackend(ctx, sweeps_per_step=8)
+    # a space too wide for the batched sweep (398 candidate slots) runs alone on the builder
+    wide = synth.Space("wide", (200, 3), rng.lognormal(0.0, 0.5, 600).astype(np.float32))
+    wide_fit = torch.from_numpy(wide.fitness_raw).cuda()
+    spaces.append(wide)
+    for k, t in enumerate((times[5], times[-5])):
+        reqs.append(serve.Request(t, len(times) + 2 + k, (len(spaces) - 1, "hamming"), wide.radix, wide_fit,
+                                  "hamming", 0.85, 0.05))
+    reqs.sort()
+    print(f"[case] serve {len(reqs)} requests ({len(spaces)} spaces + 2 large) against the oracle, "
+          f"FFG builds on the builder thread", flush=True)
+    backend = serve.GpuBackend(ctx, sweeps_per_step=8, async_builds=True)
     srv = serve.Server(backend, hbm_budget=16 << 30)
     done = {d.rid: d for d in srv.run(reqs)}
     assert sorted(done) == sorted(r.rid for r in reqs)
+    assert srv.stats["built"] == len({r.key for r in reqs})
     keys = sorted({(r.key[0], r.damping) for r in reqs if r.key[0] != "large"}, key=str)
 
     def ref(kd):
@@ -104,7 +114,6 @@ def test_served_results_match_oracle(large_reference):
         assert abs(got.score - a.score) <= 1e-5, (r.rid, r.key, got.score, a.score)
         worst = max(worst, l1)
     print(f"[case] worst served L1 vs oracle {worst:.3e}", flush=True)
+    srv.close()
     backend.close()
-    for cached in list(srv.cache.values()):
-        cached[0].close()
     ctx.close()

@@ -24,6 +24,7 @@ class FakeBackend:
         self.added_while_running = 0
         self.max_on_one_plan = 0                  # members sharing one FFG at once
         self.gc_during_step = set()
+        self.n_builds = 0
 
     def clock(self):
         return self.now
@@ -33,6 +34,7 @@ class FakeBackend:
 
     def build(self, req):
         self.now += self.build_cost
+        self.n_builds += 1
         self.live_plans += 1
         g = oracle.build_graph(req.radix, req.fitness, {"hamming": 0, "adjacent": 1}[req.neighbourhood])
         self.built.append(g)
@@ -146,3 +148,89 @@ def test_collector_paused_while_serving(pause):
     assert gc.isenabled() and len(done) == len(reqs)
     assert fb.gc_during_step == {not pause}
     assert (srv.stats["gc_idle"] > 0) == pause
+
+
+class FakeAsyncBackend(FakeBackend):
+    """Builds (and lone analyses of spaces marked unbatchable) run off the
+    loop: each completes build_cost (or its step cost) of virtual time after
+    it was submitted, while the loop keeps stepping the batch."""
+    async_builds = True
+
+    def __init__(self, unbatchable=(), **kw):
+        super().__init__(**kw)
+        self.jobs = []                     # (ready time, kind, req, payload)
+        self.unbatchable = set(unbatchable)
+        self.steps_during_builds = 0
+
+    def submit_build(self, req):
+        g = oracle.build_graph(req.radix, req.fitness, {"hamming": 0, "adjacent": 1}[req.neighbourhood])
+        self.built.append(g)
+        self.live_plans += 1
+        self.jobs.append((self.now + self.build_cost, "build", req, (g, req.key[0] not in self.unbatchable)))
+
+    def submit_plain(self, g, req):
+        r, it, _ = g.pagerank(req.damping, 2e-7)
+        res = (r, g.minima, {"score": g.score(r, req.p)[0], "iterations": it, "status": 0})
+        self.jobs.append((self.now + self.step_cost * (it // self.sweeps + 1), "plain", req, res))
+
+    def poll(self):
+        ready = [j for j in self.jobs if j[0] <= self.now]
+        self.jobs = [j for j in self.jobs if j[0] > self.now]
+        return [(kind, req, res) for _, kind, req, res in ready]
+
+    def step(self):
+        if any(j[1] == "build" for j in self.jobs):
+            self.steps_during_builds += 1
+        return super().step()
+
+
+def _check_against_plain(reqs, done):
+    assert sorted(done) == sorted(r.rid for r in reqs)
+    for r in reqs:
+        g = oracle.build_graph(r.radix, r.fitness)
+        rr, _, _ = g.pagerank(r.damping, 2e-7)
+        assert done[r.rid].score == g.score(rr, r.p)[0]
+
+
+def test_async_builds_overlap_the_batch_and_are_shared():
+    """Cache misses build off the loop: the batch keeps stepping while builds
+    are in flight, requests for a space being built wait for that one build,
+    and every result equals its plain result."""
+    reqs = make_requests(80, seed=7, rate=20000.0)
+    fb = FakeAsyncBackend(build_cost=5e-4)
+    srv = serve.Server(fb, hbm_budget=1 << 30, clock=fb.clock, sleep=fb.sleep)
+    done = {d.rid: d for d in srv.run(reqs)}
+    _check_against_plain(reqs, done)
+    keys = {r.key for r in reqs}
+    assert srv.stats["built"] == len(keys)          # one build per distinct space
+    assert srv.stats["build_waits"] > 0             # later requests joined a build in flight
+    assert fb.steps_during_builds > 0               # the batch ran while builds were in flight
+    assert not srv.building and not srv.running
+    srv.close()
+    assert fb.live_plans == 0
+
+
+def test_async_unbatchable_spaces_and_budget():
+    """Spaces the batch cannot take run alone on the builder; with no cache
+    every plan is released once its requests finish, and the budget holds."""
+    reqs = make_requests(50, seed=8, rate=50000.0)
+    fb = FakeAsyncBackend(unbatchable={0, 2}, build_cost=3e-4)
+    budget = 4 * (64 + 16) * 160 + (1 << 20) * 4
+    srv = serve.Server(fb, hbm_budget=budget, cache_budget=0, clock=fb.clock, sleep=fb.sleep)
+    done = {d.rid: d for d in srv.run(reqs)}
+    _check_against_plain(reqs, done)
+    assert srv.peak_bytes <= budget
+    assert fb.live_plans == 0 and srv.reserved == 0
+
+
+def test_plain_path_with_the_same_cache():
+    """The one-at-a-time path with a plan cache builds each distinct space
+    once; without one it builds per request.  Results are the same."""
+    reqs = make_requests(40, seed=9)
+    fb = FakeBackend()
+    cached = {d.rid: d for d in serve.serve_plain(fb, reqs, clock=fb.clock, sleep=fb.sleep, cache_budget=1 << 30)}
+    assert fb.n_builds == len({r.key for r in reqs}) and fb.live_plans == 0
+    fb2 = FakeBackend()
+    fresh = {d.rid: d for d in serve.serve_plain(fb2, reqs, clock=fb2.clock, sleep=fb2.sleep)}
+    assert fb2.n_builds == len(reqs) and fb2.live_plans == 0
+    assert {r.rid: cached[r.rid].score for r in reqs} == {r.rid: fresh[r.rid].score for r in reqs}
