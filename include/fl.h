@@ -76,15 +76,22 @@ typedef struct {
  *   max_iter  iteration cap (0 => 1000); reaching it gives FL_ENOCONV.
  *   row_mapping  layout of the PageRank sweep: 0 = automatic (the layout
  *             fl_tune cached for the plan's shape class, else FL_ROWS_SLOTS
- *             where available, else CSR lanes from the mean in-degree);
+ *             where available, else FL_ROWS_BINNED);
  *             FL_ROWS_SLOTS = one node per lane over the in-edge slot
  *             records (needs at most 256 candidate slots per node);
+ *             FL_ROWS_BINNED = the CSR with rows binned by in-degree into
+ *             8 buckets (0; [2^(b-1), 2^b) for b = 1..6; 64 and more), each
+ *             bucket with its own lanes per row and rows per tile (the
+ *             mapping fl_tune chose for the plan's shape class, else about a
+ *             quarter of the bucket's largest in-degree in lanes);
  *             1, 2, 4, 8, 16, 32 or 64 = that many lanes per row over the
- *             CSR.  Every layout sums a row's terms in the same order: the
- *             slot layout and the one-lane CSR layout give the same ranks
- *             bit for bit. */
+ *             CSR.  Every layout sums a row's terms in ascending source
+ *             order (one lane per row: sequentially; several: lane partial
+ *             sums reduced by a fixed tree): the slot layout and the
+ *             one-lane CSR layout give the same ranks bit for bit. */
 #define FL_ROWS_SLOTS (-1)
-#define FL_TUNE_LAYOUTS 8
+#define FL_ROWS_BINNED (-2)
+#define FL_TUNE_LAYOUTS 9
 typedef struct {
     double damping;
     double p;
@@ -150,6 +157,8 @@ const char *fl_last_error(const fl_ctx *ctx);
  *   d_fitness_raw  device float32[prod radix] in raw order; borrowed.
  *   out            receives a plan owned by the library (fl_plan_destroy).
  *   sizes          receives n_raw, n_valid, n_edges, n_minima, f_opt.
+ * A space with more than 256 candidate slots (no slot records) also gets
+ * its rows binned by in-degree here, for the binned sweep.
  * Errors: FL_EINVAL (space, neighbourhood, a fitness <= 0 or -inf, no valid
  * point), FL_EOVERFLOW, FL_ENOMEM, FL_EHIP.  Synchronises the stream. */
 fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitness_raw,
@@ -192,17 +201,30 @@ fl_status fl_execute_exact(fl_ctx *ctx, fl_plan *plan, const fl_params *params, 
 fl_status fl_plan_export(fl_ctx *ctx, const fl_plan *plan, int32_t *d_valid_raw,
                          int32_t *d_row_ptr, int32_t *d_col_idx, int32_t *d_out_deg);
 
-/* Autotuner: time every sweep layout the plan allows (the slot sweep, then
- * the CSR sweep with 1, 2, 4, 8, 16, 32, 64 lanes per row) for `sweeps`
- * forced power-iteration sweeps each (HIP events, after one warm-up sweep), store the fastest in the context's tuning cache
- * under the plan's shape class (node-record width, neighbourhood, log2 N,
- * mean in-degree) and return it in *best.  us_per_sweep (may be NULL)
- * receives FL_TUNE_LAYOUTS times in microseconds in that layout order, -1
- * where a layout does not apply.  Afterwards fl_execute with row_mapping 0
- * uses the cached layout for plans of the same shape class.  The plan's iterate buffers are overwritten; outputs of
+/* Autotuner.  First, per in-degree bucket of the plan (see FL_ROWS_BINNED):
+ * time `sweeps` binned sweeps over that bucket's rows alone for every lanes
+ * per row L in 1, 2, ..., up to the bucket's largest in-degree (64 at most)
+ * and every tile of T = 1 or 4 blocks of 256 / L rows, and keep the fastest
+ * (L, T) of each bucket as the shape class's bucket mapping.  Then time every
+ * sweep layout the plan allows (the slot sweep, the CSR sweep with 1, 2, 4,
+ * 8, 16, 32, 64 lanes per row, the binned sweep with that mapping) for
+ * `sweeps` forced power-iteration sweeps each (HIP events, after one warm-up
+ * sweep), store the fastest in the context's tuning cache under the plan's
+ * shape class (node-record width, neighbourhood, log2 N, mean in-degree) and
+ * return it in *best.  us_per_sweep (may be NULL) receives FL_TUNE_LAYOUTS
+ * times in microseconds in that layout order, -1 where a layout does not
+ * apply.  Afterwards fl_execute and fl_batch_add with row_mapping 0 use the
+ * cached layout (and FL_ROWS_BINNED the cached mapping) for plans of the
+ * same shape class.  The plan's iterate buffers are overwritten; outputs of
  * earlier fl_execute calls are not touched.  Synchronises the stream. */
 fl_status fl_tune(fl_ctx *ctx, fl_plan *plan, const fl_params *params, int32_t sweeps, int32_t *best,
                   double *us_per_sweep);
+
+/* The in-degree bucket mapping the context holds for the plan's shape class
+ * (tuned by fl_tune, else the default; see FL_ROWS_BINNED) and the plan's
+ * rows per bucket.  lanes, blocks (int32[8]) and rows (int64[8]) are host
+ * arrays, any may be NULL.  Synchronises the stream when rows is given. */
+fl_status fl_bucket_map(fl_ctx *ctx, const fl_plan *plan, int32_t *lanes, int32_t *blocks, int64_t *rows);
 
 /* C_p curve (Sec. VII-B, eq. 3; the paper plots C_p for p = 0, 1, ..., 15 %):
  * scores[j] = C_p for p = p_values[j] (fractions >= 0), from the ranks
@@ -272,8 +294,8 @@ fl_status fl_analyze_noalloc(fl_ctx *ctx, const fl_space *space, const float *d_
  *
  * A batch runs the power iteration of many plans together: every sweep is one
  * segmented launch over the tiles of all running members (one launch per
- * node-record width), followed by one launch that finishes the step of every
- * member.  Each member keeps its own damping, tolerance, iteration count and
+ * node-record width of the slot-sweep members, one for the binned members),
+ * followed by one launch that finishes the step of every member.  Each member keeps its own damping, tolerance, iteration count and
  * stop flag, and its results equal those of fl_execute with the slot sweep
  * (row_mapping FL_ROWS_SLOTS) bit for bit, whatever else runs in the batch.
  * Members join (fl_batch_add) and leave (fl_batch_collect) between steps.
@@ -297,10 +319,18 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *batch);
  * written when the member finishes; `tag` is returned by fl_batch_collect.
  * The member holds 8 n_raw + 8 N + 24 ceil(N/256) + 80 bytes of device
  * memory of its own while it is in the batch.
- * Members always run the slot sweep (FL_ROWS_SLOTS).
- * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0 or
- * FL_ROWS_SLOTS, or a space the slot sweep cannot take: use fl_execute),
- * FL_ENOMEM, FL_EHIP. */
+ * A member runs the slot sweep (FL_ROWS_SLOTS) or the binned sweep
+ * (FL_ROWS_BINNED); row_mapping 0 takes the layout fl_tune cached for the
+ * plan's shape class in this context (the binned sweep for any tuned layout
+ * other than the slot sweep), the slot sweep when nothing is tuned, and the
+ * binned sweep for spaces the slot sweep cannot take.  A binned member
+ * sweeps the plan's binned rows (built here with the class's tuned mapping
+ * when the plan belongs to this context; a plan of another context must
+ * already have them, as plans without slot records do).  Its results equal
+ * fl_execute with FL_ROWS_BINNED and the same mapping bit for bit.
+ * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0,
+ * FL_ROWS_SLOTS or FL_ROWS_BINNED, FL_ROWS_SLOTS for a space the slot sweep
+ * cannot take), FL_ENOMEM, FL_EHIP. */
 fl_status fl_batch_add(fl_ctx *ctx, fl_batch *batch, fl_plan *plan, const fl_params *params,
                        double *d_pagerank, int32_t *d_minima, int64_t tag);
 
@@ -345,8 +375,9 @@ fl_status fl_batch_set_small(fl_ctx *ctx, fl_batch *batch, int32_t max_tiles);
 /* One-shot batched analysis of n_spaces spaces (Sec. VII-B for each): the
  * FFGs are built together, each build stage one launch for all spaces (a
  * table of per-space descriptors; one host synchronisation per stage), then
- * PageRank runs as one batch (spaces the slot sweep cannot take run through
- * fl_execute).  All array arguments have n_spaces entries; d_pagerank[j] /
+ * PageRank runs as one batch (every space joins it, as fl_batch_add with the
+ * space's row_mapping; only an explicit lanes-per-row CSR layout runs
+ * alone through fl_execute).  All array arguments have n_spaces entries; d_pagerank[j] /
  * d_minima[j] are sized as for fl_execute (n_raw upper bound is always
  * enough).  out[j].status holds each space's status; the call returns the
  * first error, or FL_ENOCONV if some space did not converge.  The context

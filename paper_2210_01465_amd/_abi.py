@@ -83,6 +83,8 @@ PROTOTYPES = {
                                           ctypes.POINTER(fl_summary)]),
     "fl_tune": (ctypes.c_int, [_P, _P, ctypes.POINTER(fl_params), ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "fl_bucket_map": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64)]),
     "fl_batch_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
     "fl_batch_destroy": (ctypes.c_int, [_P, _P]),
     "fl_batch_add": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(fl_params), _P, _P, ctypes.c_int64]),

@@ -220,13 +220,15 @@ def plan_export(plan: Plan) -> dict:
 
 
 ROWS_SLOTS = -1
-TUNE_LAYOUTS = (ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64)
+ROWS_BINNED = -2
+TUNE_LAYOUTS = (ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64, ROWS_BINNED)
 
 
 def tune(plan: Plan, damping: float = 0.85, sweeps: int = 4) -> dict:
-    """Autotune the sweep layout for the plan's shape class (fl_tune).
-    Returns {"best": layout, "us_per_sweep": {layout: us}} (-1 slot sweep,
-    else CSR lanes per row)."""
+    """Autotune the in-degree bucket mapping and the sweep layout for the
+    plan's shape class (fl_tune).  Returns {"best": layout, "us_per_sweep":
+    {layout: us}, "buckets": bucket_map(plan)} (-1 slot sweep, -2 binned
+    sweep, else CSR lanes per row)."""
     best = ctypes.c_int32()
     times = (ctypes.c_double * len(TUNE_LAYOUTS))()
     prm = _params(damping, 0.05, 0.0, 0, 0)
@@ -234,7 +236,23 @@ def tune(plan: Plan, damping: float = 0.85, sweeps: int = 4) -> dict:
                              ctypes.byref(best), times)
     _check(plan.ctx, rc, "fl_tune")
     return {"best": int(best.value),
-            "us_per_sweep": {lay: float(t) for lay, t in zip(TUNE_LAYOUTS, times) if t >= 0}}
+            "us_per_sweep": {lay: float(t) for lay, t in zip(TUNE_LAYOUTS, times) if t >= 0},
+            "buckets": bucket_map(plan)}
+
+
+BUCKETS = ("0", "1", "2-3", "4-7", "8-15", "16-31", "32-63", "64+")
+
+
+def bucket_map(plan: Plan) -> dict:
+    """The context's in-degree bucket mapping for the plan's shape class and
+    the plan's rows per bucket (fl_bucket_map): {bucket: {"lanes", "blocks",
+    "rows"}} with buckets named by their in-degree range."""
+    lanes = (ctypes.c_int32 * 8)()
+    blocks = (ctypes.c_int32 * 8)()
+    rows = (ctypes.c_int64 * 8)()
+    rc = _abi.load().fl_bucket_map(plan.ctx.handle, plan.handle, lanes, blocks, rows)
+    _check(plan.ctx, rc, "fl_bucket_map")
+    return {BUCKETS[b]: {"lanes": int(lanes[b]), "blocks": int(blocks[b]), "rows": int(rows[b])} for b in range(8)}
 
 
 def score_curve(plan: Plan, pagerank: torch.Tensor, p_values=tuple(j / 100 for j in range(16))) -> list:
@@ -351,11 +369,12 @@ class Batch:
         self._next_tag = 0
 
     def add(self, plan: Plan, damping: float = 0.85, p: float = 0.05, tol: float = 0.0,
-            max_iter: int = 0, tag: int | None = None) -> int:
+            max_iter: int = 0, tag: int | None = None, row_mapping: int = 0) -> int:
         """Add a member; returns its tag.  Without a tag the next unused one
         of an increasing counter is taken.  A tag of a member that has not
         been collected yet is rejected (ValueError): its output tensors are
-        still being written."""
+        still being written.  row_mapping: 0 (automatic), ROWS_SLOTS or
+        ROWS_BINNED."""
         if tag is None:
             while self._next_tag in self._outputs:
                 self._next_tag += 1
@@ -368,7 +387,7 @@ class Batch:
         dev = torch.device("cuda", self.ctx.device)
         pr = torch.empty(plan.n_valid, dtype=torch.float64, device=dev)
         mins = torch.empty(max(plan.n_minima, 1), dtype=torch.int32, device=dev)
-        prm = _params(damping, p, tol, max_iter, 0)
+        prm = _params(damping, p, tol, max_iter, row_mapping)
         rc = _abi.load().fl_batch_add(self.ctx.handle, self.handle, plan.handle, ctypes.byref(prm),
                                       ctypes.c_void_p(pr.data_ptr()), ctypes.c_void_p(mins.data_ptr()), tag)
         _check(self.ctx, rc, "fl_batch_add")

@@ -147,6 +147,8 @@ struct fl_ctx {
     std::string err;
     DevicePool pool;
     std::map<uint64_t, int> tuned;  // shape class -> sweep layout chosen by fl_tune
+    std::map<uint64_t, uint64_t> tuned_map;  // shape class -> in-degree bucket mapping chosen by fl_tune
+    int32_t *h_bins = nullptr;      // pinned: bucket classes out, class sizes back
     int32_t profile_every = 0;      // bracket every n-th sweep kernel with events (fl_profile), 0 = off
     std::vector<hipEvent_t> sweep_ev;  // 2 per launch of the longest chunk so far
     BuildSizes *h_sizes = nullptr;  // pinned
@@ -186,6 +188,13 @@ struct fl_plan {
     double *partials = nullptr;
     PrState *state = nullptr;
     int pr_grid = 0;
+    // rows binned by in-degree (binned sweep): node ids grouped by class,
+    // the classes, and the bucket mapping they were built for
+    int32_t *bin_rows = nullptr;
+    fl::BinTable bins{};
+    uint64_t bin_map = 0;
+    bool have_bins = false;
+    int32_t bin_users = 0;      // batch members sweeping these bins (no rebinning meanwhile)
     int32_t *d_off = nullptr;   // 2 k_pad entries in device memory, read by the slot sweep:
                                 // raw-index offsets, then byte offsets from the most negative
                                 // (written by the degree kernel)
@@ -227,7 +236,7 @@ void release_plan_buffers(fl_plan *p) {
     DevicePool &pool = p->ctx->pool;
     void *bufs[] = {p->valid_raw, p->out_deg, p->row_ptr, p->col_idx, p->minima,  p->fit_c,
                     p->rec,       p->presence, p->y[0], p->y[1],      p->x[0],     p->x[1],
-                    p->partials,  p->state,   p->d_off};
+                    p->partials,  p->state,   p->d_off, p->bin_rows};
     for (void *b : bufs) pool.release(b);
 }
 
@@ -543,6 +552,122 @@ int32_t x_bytes_of(const fl_plan *p) {
 }
 
 bool is_slot_layout(int lanes) { return lanes == FL_ROWS_SLOTS; }
+bool is_binned_layout(int lanes) { return lanes == FL_ROWS_BINNED; }
+
+// ---- rows binned by in-degree ----
+// A bucket mapping: byte b holds log2 of bucket b's lanes per row (bits 0..2)
+// and of its row blocks per tile (bits 3..4).
+int map_lanes(uint64_t m, int b) { return 1 << (int)((m >> (8 * b)) & 7u); }
+int map_blocks(uint64_t m, int b) { return 1 << (int)((m >> (8 * b + 3)) & 3u); }
+int log2i(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+}
+uint64_t map_with(uint64_t m, int b, int lanes, int blocks) {
+    const uint64_t byte = (uint64_t)(log2i(lanes) | (log2i(blocks) << 3));
+    return (m & ~(uint64_t(0xff) << (8 * b))) | (byte << (8 * b));
+}
+// Largest in-degree of bucket b (the last bucket: taken as 4x its lower edge).
+int bucket_hi(int b) { return b == 0 ? 0 : (b == fl::kBuckets - 1 ? 4 << (b - 1) : (1 << b) - 1); }
+// Untuned mapping: about a quarter of the bucket's largest in-degree in lanes
+// (one round of four loads in flight per lane), one block per tile.
+uint64_t default_bin_map() {
+    uint64_t m = 0;
+    for (int b = 0; b < fl::kBuckets; ++b) {
+        int l = 1;
+        while (l < 64 && 4 * l < bucket_hi(b)) l <<= 1;
+        m = map_with(m, b, l, 1);
+    }
+    return m;
+}
+uint64_t bin_map_for(const fl_ctx *ctx, uint64_t shape);
+
+// Classes of a mapping: its distinct (L, T) pairs in ascending order, and the
+// class of every bucket.  Returns the number of classes.
+int bin_classes(uint64_t m, int8_t *class_of, int *lanes, int *blocks) {
+    int n = 0;
+    for (int l = 1; l <= 64; l <<= 1)
+        for (int t = 1; t <= 8; t <<= 1) {
+            bool used = false;
+            for (int b = 0; b < fl::kBuckets; ++b)
+                if (map_lanes(m, b) == l && map_blocks(m, b) == t) {
+                    class_of[b] = (int8_t)n;
+                    used = true;
+                }
+            if (used) {
+                lanes[n] = l;
+                blocks[n] = t;
+                ++n;
+            }
+        }
+    return n;
+}
+
+// Bin the rows of `row_ptr` (n rows) into `rows` by the classes of `class_of`;
+// sizes[c] receives each class's row count.  Synchronises the stream.
+fl_status bin_rows_into(fl_ctx *ctx, const int32_t *row_ptr, int64_t n, const int8_t *class_of, int32_t *rows,
+                        int32_t *sizes) {
+    const int64_t n_tiles = (n + fl::kBlock - 1) / fl::kBlock;
+    int32_t *tmp = pool_alloc<int32_t>(ctx, 2 * fl::kBuckets * n_tiles + fl::kBuckets + 2);
+    if (!tmp) return fail(ctx, FL_ENOMEM, "device allocation failed");
+    int32_t *d_class = tmp + 2 * fl::kBuckets * n_tiles + fl::kBuckets;
+    memcpy(ctx->h_bins, class_of, fl::kBuckets);
+    hipStream_t s = ctx->stream;
+    hipError_t e = hipMemcpyAsync(d_class, ctx->h_bins, fl::kBuckets, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = fl::launch_bin_rows(row_ptr, (int32_t)n, (const int8_t *)d_class, tmp, tmp + fl::kBuckets * n_tiles,
+                                tmp + 2 * fl::kBuckets * n_tiles, rows, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->h_bins + 16, tmp + 2 * fl::kBuckets * n_tiles, sizeof(int32_t) * fl::kBuckets,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    ctx->pool.release(tmp);
+    if (e != hipSuccess) return fail(ctx, FL_EHIP, "row binning: %s", hipGetErrorString(e));
+    memcpy(sizes, ctx->h_bins + 16, sizeof(int32_t) * fl::kBuckets);
+    return FL_OK;
+}
+
+// Table of classes over binned rows: rows[c] rows in class c (in order),
+// lanes and blocks per class; empty classes are left out.
+fl::BinTable bin_table(int n_classes, const int32_t *rows, const int *lanes, const int *blocks) {
+    fl::BinTable t{};
+    int32_t row = 0, tile = 0;
+    for (int c = 0; c < n_classes; ++c) {
+        if (rows[c] > 0) {
+            fl::BinClass &k = t.c[t.n_classes++];
+            k.row_begin = row;
+            k.rows = rows[c];
+            k.tile_begin = tile;
+            k.lanes = (int16_t)lanes[c];
+            k.blocks = (int16_t)blocks[c];
+            const int32_t per = blocks[c] * (fl::kBlock / lanes[c]);
+            tile += (rows[c] + per - 1) / per;
+        }
+        row += rows[c];
+    }
+    t.tiles = tile;
+    return t;
+}
+
+// The plan's rows binned for mapping m (kept while batch members sweep them).
+fl_status ensure_binned(fl_ctx *ctx, fl_plan *p, uint64_t m) {
+    if (p->have_bins && (p->bin_map == m || p->bin_users > 0)) return FL_OK;
+    int8_t class_of[fl::kBuckets];
+    int lanes[fl::kBuckets], blocks[fl::kBuckets];
+    const int nc = bin_classes(m, class_of, lanes, blocks);
+    if (!p->bin_rows) {
+        p->bin_rows = pool_alloc<int32_t>(ctx, p->n);
+        if (!p->bin_rows) return fail(ctx, FL_ENOMEM, "device allocation failed");
+    }
+    int32_t sizes[fl::kBuckets];
+    const fl_status st = bin_rows_into(ctx, p->row_ptr, p->n, class_of, p->bin_rows, sizes);
+    if (st != FL_OK) return st;
+    p->bins = bin_table(nc, sizes, lanes, blocks);
+    p->bin_map = m;
+    p->have_bins = true;
+    return FL_OK;
+}
 
 struct Resolved {
     double d, p, tol;
@@ -557,8 +682,9 @@ fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Re
     if (!(prm->p >= 0.0) || !isfinite(prm->p)) return fail(ctx, FL_EINVAL, "p must be finite and >= 0");
     if (!(prm->tol_l1 >= 0.0) || !isfinite(prm->tol_l1)) return fail(ctx, FL_EINVAL, "tol_l1 must be finite and >= 0");
     if (prm->max_iter < 0) return fail(ctx, FL_EINVAL, "max_iter must be >= 0");
-    if (prm->row_mapping != 0 && !is_slot_layout(prm->row_mapping) && !valid_lanes(prm->row_mapping))
-        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS or a power of two <= 64");
+    if (prm->row_mapping != 0 && !is_slot_layout(prm->row_mapping) && !is_binned_layout(prm->row_mapping) &&
+        !valid_lanes(prm->row_mapping))
+        return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS, FL_ROWS_BINNED or a power of two <= 64");
     if (is_slot_layout(prm->row_mapping) && p->sl.words == 0)
         return fail(ctx, FL_EINVAL, "the slot sweep needs at most %d candidate slots (space has %d)",
                     fl::kMaxSlots, p->sl.k);
@@ -567,7 +693,7 @@ fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Re
     r.tol = prm->tol_l1 > 0.0 ? prm->tol_l1 : 2e-7;
     // the exact sweeps settle after (longest path + 1) <= N sweeps
     r.max_iter = prm->max_iter > 0 ? prm->max_iter : (exact ? (int32_t)std::min<int64_t>(p->n + 2, INT32_MAX) : 1000);
-    r.lanes = prm->row_mapping ? prm->row_mapping : (p->sl.words > 0 ? FL_ROWS_SLOTS : auto_lanes(p->n, p->e));
+    r.lanes = prm->row_mapping ? prm->row_mapping : (p->sl.words > 0 ? FL_ROWS_SLOTS : FL_ROWS_BINNED);
     return FL_OK;
 }
 
@@ -627,13 +753,25 @@ uint64_t shape_key(const fl_plan *p) {
            (uint64_t)std::min<int64_t>(deg2, (int64_t(1) << 40) - 1);
 }
 
+uint64_t bin_map_for(const fl_ctx *ctx, uint64_t shape) {
+    const auto it = ctx->tuned_map.find(shape);
+    return it != ctx->tuned_map.end() ? it->second : default_bin_map();
+}
+
 // Grid, buffers and arguments of the power iteration of plan p in layout
 // `lanes` (FL_ROWS_SLOTS or CSR lanes per row).
 fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrArgs &a, int &grid,
                      int &init_grid) {
-    const int kind = is_slot_layout(lanes) ? fl::kSweepSlots : fl::kSweepCsr;
+    const int kind = is_slot_layout(lanes) ? fl::kSweepSlots : is_binned_layout(lanes) ? fl::kSweepBinned
+                                                                                      : fl::kSweepCsr;
     a = PrArgs{};
     a.kind = kind;
+    if (kind == fl::kSweepBinned) {
+        const fl_status bst = ensure_binned(ctx, p, bin_map_for(ctx, shape_key(p)));
+        if (bst != FL_OK) return bst;
+        a.bin_rows = p->bin_rows;
+        a.bins = p->bins;
+    }
     a.adjacent = p->adjacent;
     a.x_bytes = kind == fl::kSweepSlots ? x_bytes_of(p) : 0;
     // persistent grid: every workgroup resident at once (occupancy query), a
@@ -642,15 +780,16 @@ fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrAr
     FL_HIP(fl::pr_iter_blocks_per_cu(a, p->sp, p->sl, lanes, &per_cu));
     const int64_t resident =
         std::max<int64_t>(fl::kXcds, (int64_t)std::max(per_cu, 1) * ctx->num_cus / fl::kXcds * fl::kXcds);
-    const int64_t rows_per_wg = kind == fl::kSweepSlots ? fl::kBlock : fl::kBlock / lanes;
-    const int64_t groups = (p->n + rows_per_wg - 1) / rows_per_wg;
+    const int64_t rows_per_wg = kind == fl::kSweepSlots ? fl::kBlock : (kind == fl::kSweepBinned ? 1 : fl::kBlock / lanes);
+    const int64_t groups = kind == fl::kSweepBinned ? std::max<int64_t>(p->bins.tiles, 1)
+                                                    : (p->n + rows_per_wg - 1) / rows_per_wg;
     grid = (int)std::min<int64_t>(resident, (groups + fl::kXcds - 1) / fl::kXcds * fl::kXcds);
     fl_status st = ensure_pr_buffers(ctx, p, kind == fl::kSweepSlots);
     if (st != FL_OK) return st;
     // partial sums: one triple per tile (init, slot sweep) or per workgroup (CSR sweep)
     const int32_t n_tiles = tiles_of(p);
     init_grid = (int)std::min<int64_t>(n_tiles, (int64_t)ctx->num_cus * 4);
-    st = ensure_partials(ctx, p, std::max(grid, n_tiles));
+    st = ensure_partials(ctx, p, std::max<int64_t>(std::max(grid, n_tiles), p->have_bins ? p->bins.tiles : 0));
     if (st != FL_OK) return st;
     a.row_ptr = p->row_ptr;
     a.col_idx = p->col_idx;
@@ -690,8 +829,10 @@ struct fl_batch {
         int slot = -1;    // row of the device member table
         int phase = 0;    // 0 waiting for initialisation, 1 running, 2 finished
         fl_summary sum{};
-        // the member's own iterate: y (node ids), x (raw indices), per-tile
-        // partial sums and state, from the context's pool
+        bool binned = false;  // binned sweep over the CSR (else the slot sweep)
+        bool holds_bins = false;  // counted in plan->bin_users
+        // the member's own iterate: y (node ids), x (raw indices; node ids
+        // when binned), per-tile partial sums and state, from the context's pool
         float *y[2] = {}, *x[2] = {};
         double *partials = nullptr;
         PrState *state = nullptr;
@@ -706,8 +847,9 @@ struct fl_batch {
     int32_t *d_ids = nullptr, *h_ids = nullptr;  // regions: init | running | finishing
     PrState *d_states = nullptr, *h_states = nullptr;
     // list ranges read by the sweep and step kernels: [2w], [2w+1] start and
-    // length of the tiles of record width w (1..kMaxWords) in the sweep list,
-    // [kRunCount] running members, [kInitCount] joining ones
+    // length of the tiles of record width w (1..kMaxWords; 0: binned
+    // members) in the sweep list, [kRunCount] running members, [kInitCount]
+    // joining ones
     static constexpr int kRunCount = 2 * fl::kMaxWords + 2, kInitCount = kRunCount + 1, kCounts = 16;
     int32_t *d_counts = nullptr, *h_counts = nullptr;
     int sweep_per_cu[fl::kMaxWords + 1] = {};
@@ -744,7 +886,17 @@ struct fl_batch {
 
 namespace {
 
+// Tiles a member needs in the batch's lists: node tiles (initial iterate,
+// output) and, when binned, the tiles of its bin table (sweeps).
+int64_t member_tiles(const fl_batch::Member &m) {
+    return std::max<int64_t>(tiles_of(m.plan), m.binned ? m.plan->bins.tiles : 0);
+}
+
 void member_release(fl_ctx *ctx, fl_batch::Member &m) {
+    if (m.holds_bins) {
+        m.plan->bin_users -= 1;
+        m.holds_bins = false;
+    }
     for (int j = 0; j < 2; ++j) {
         ctx->pool.release(m.y[j]);
         ctx->pool.release(m.x[j]);
@@ -759,9 +911,9 @@ void member_release(fl_ctx *ctx, fl_batch::Member &m) {
 fl_status member_alloc(fl_ctx *ctx, const fl_plan *p, fl_batch::Member &m) {
     for (int j = 0; j < 2; ++j) {
         m.y[j] = pool_alloc<float>(ctx, p->n);
-        m.x[j] = pool_alloc<float>(ctx, (p->n_raw + 3) / 4 * 4);
+        m.x[j] = pool_alloc<float>(ctx, m.binned ? p->n : (p->n_raw + 3) / 4 * 4);
     }
-    m.partials = pool_alloc<double>(ctx, 3 * (int64_t)tiles_of(p));
+    m.partials = pool_alloc<double>(ctx, 3 * std::max<int64_t>(tiles_of(p), m.binned ? p->bins.tiles : 0));
     m.state = pool_alloc<PrState>(ctx, 1);
     if (!m.y[0] || !m.y[1] || !m.x[0] || !m.x[1] || !m.partials || !m.state) {
         member_release(ctx, m);
@@ -892,10 +1044,12 @@ fl_status fl_create(fl_ctx **out, int device, void *hip_stream) {
         hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_sizes, sizeof(BuildSizes), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_state, sizeof(PrState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_bins, sizeof(int32_t) * 64, hipHostMallocDefault) != hipSuccess ||
         scratch_address(device, &ctx->scratch) != hipSuccess) {
         (void)hipGetLastError();
         if (ctx->h_sizes) (void)hipHostFree(ctx->h_sizes);
         if (ctx->h_state) (void)hipHostFree(ctx->h_state);
+        if (ctx->h_bins) (void)hipHostFree(ctx->h_bins);
         delete ctx;
         return FL_EHIP;
     }
@@ -915,6 +1069,7 @@ fl_status fl_destroy(fl_ctx *ctx) {
     for (hipEvent_t e : ctx->sweep_ev) (void)hipEventDestroy(e);
     (void)hipHostFree(ctx->h_sizes);
     (void)hipHostFree(ctx->h_state);
+    (void)hipHostFree(ctx->h_bins);
     delete ctx;
     return FL_OK;
 }
@@ -948,6 +1103,17 @@ fl_status fl_plan_create(fl_ctx *ctx, const fl_space *space, const float *d_fitn
     if (b.status != FL_OK) {
         build_abort(ctx, b);
         return fail(ctx, b.status, "%s", b.err.c_str());
+    }
+    if (b.p->sl.words == 0) {
+        // no slot records: the binned sweep is this plan's layout, so its rows
+        // are binned now (a plan may join a batch of another context, which
+        // must not allocate from this one)
+        const fl_status bst = ensure_binned(ctx, b.p, bin_map_for(ctx, shape_key(b.p)));
+        if (bst != FL_OK) {
+            const std::string msg = ctx->err;
+            build_abort(ctx, b);
+            return fail(ctx, bst, "%s", msg.c_str());
+        }
     }
     if (sizes) fill_sizes(b.p, sizes);
     *out = b.p;
@@ -1260,6 +1426,84 @@ fl_status fl_analyze_noalloc(fl_ctx *ctx, const fl_space *space, const float *d_
     return st;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Rows of plan p grouped by in-degree bucket (every bucket its own class)
+// into rows (N entries); sizes[b] receives each bucket's row count.
+fl_status bucket_rows(fl_ctx *ctx, const fl_plan *p, int32_t *rows, int32_t *sizes) {
+    int8_t ident[fl::kBuckets];
+    for (int b = 0; b < fl::kBuckets; ++b) ident[b] = (int8_t)b;
+    return bin_rows_into(ctx, p->row_ptr, p->n, ident, rows, sizes);
+}
+
+// The per-bucket part of the autotuner: for every non-empty in-degree bucket,
+// time `sweeps` binned sweeps over that bucket's rows alone for every lanes
+// per row L up to the bucket's largest in-degree (rounded up to a power of
+// two) and T in {1, 4} blocks per tile; *map receives the fastest (L, T) of
+// each bucket (the default for empty buckets).
+fl_status tune_buckets(fl_ctx *ctx, fl_plan *p, const Resolved &r, int32_t sweeps, uint64_t *map) {
+    hipStream_t s = ctx->stream;
+    int32_t *rows = pool_alloc<int32_t>(ctx, p->n);
+    if (!rows) return fail(ctx, FL_ENOMEM, "device allocation failed");
+    int32_t sizes[fl::kBuckets];
+    fl_status st = bucket_rows(ctx, p, rows, sizes);
+    PrArgs a;
+    int grid = 0, init_grid = 0;
+    if (st == FL_OK) st = prepare_pr(ctx, p, r, FL_ROWS_BINNED, a, grid, init_grid);
+    // partial triples of the largest candidate table (64 lanes, one block)
+    if (st == FL_OK) st = ensure_partials(ctx, p, p->n / 4 + fl::kBuckets + 1);
+    int per_cu = 0;
+    if (st == FL_OK && fl::pr_binned_blocks_per_cu(&per_cu) != hipSuccess) st = fail(ctx, FL_EHIP, "occupancy query");
+    uint64_t m = default_bin_map();
+    if (st == FL_OK) {
+        a.partials = p->partials;
+        a.bin_rows = rows;
+        hipError_t e = hipMemsetAsync(p->state, 0, sizeof(PrState), s);
+        if (e == hipSuccess) e = fl::launch_pr_init(a, init_grid, s);
+        const int64_t resident = (int64_t)std::max(per_cu, 1) * ctx->num_cus / fl::kXcds * fl::kXcds;
+        int32_t begin = 0;
+        for (int b = 0; b < fl::kBuckets && e == hipSuccess; ++b) {
+            if (sizes[b] == 0) continue;
+            int lmax = 1;
+            while (lmax < 64 && lmax < bucket_hi(b)) lmax <<= 1;
+            double best = -1.0;
+            for (int l = 1; l <= lmax && e == hipSuccess; l <<= 1)
+                for (int t = 1; t <= 4 && e == hipSuccess; t *= 4) {
+                    fl::BinTable tb{};
+                    tb.n_classes = 1;
+                    tb.c[0].row_begin = begin;
+                    tb.c[0].rows = sizes[b];
+                    tb.c[0].lanes = (int16_t)l;
+                    tb.c[0].blocks = (int16_t)t;
+                    const int32_t per = t * (fl::kBlock / l);
+                    tb.tiles = (sizes[b] + per - 1) / per;
+                    const int g = (int)std::min<int64_t>(resident, (tb.tiles + fl::kXcds - 1) / fl::kXcds * fl::kXcds);
+                    e = fl::launch_pr_sweep_binned(a, tb, g, s);   // warm-up
+                    if (e == hipSuccess) e = hipEventRecord(p->ev[5], s);
+                    for (int32_t q = 0; q < sweeps && e == hipSuccess; ++q) e = fl::launch_pr_sweep_binned(a, tb, g, s);
+                    if (e == hipSuccess) e = hipEventRecord(p->ev[6], s);
+                    if (e == hipSuccess) e = hipStreamSynchronize(s);
+                    const double us = e == hipSuccess ? 1e3 * elapsed(p->ev[5], p->ev[6]) / sweeps : 0.0;
+                    if (e == hipSuccess && (best < 0.0 || us < best)) {
+                        best = us;
+                        m = map_with(m, b, l, t);
+                    }
+                }
+            begin += sizes[b];
+        }
+        if (e != hipSuccess) st = fail(ctx, FL_EHIP, "bucket tuning: %s", hipGetErrorString(e));
+    }
+    ctx->pool.release(rows);
+    *map = m;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 fl_status fl_tune(fl_ctx *ctx, fl_plan *p, const fl_params *prm, int32_t sweeps, int32_t *best,
                   double *us_per_sweep) {
     if (!ctx) return FL_EINVAL;
@@ -1274,7 +1518,12 @@ fl_status fl_tune(fl_ctx *ctx, fl_plan *p, const fl_params *prm, int32_t sweeps,
     FL_HIP(hipSetDevice(ctx->device));
     FL_HIP(ensure_events(p));
     hipStream_t s = ctx->stream;
-    const int layouts[FL_TUNE_LAYOUTS] = {FL_ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64};
+    // the bucket mapping first, so that the binned layout below is timed with it
+    uint64_t map = 0;
+    st = tune_buckets(ctx, p, r, sweeps, &map);
+    if (st != FL_OK) return st;
+    ctx->tuned_map[shape_key(p)] = map;
+    const int layouts[FL_TUNE_LAYOUTS] = {FL_ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64, FL_ROWS_BINNED};
     double best_us = 0.0;
     *best = 0;
     for (int j = 0; j < FL_TUNE_LAYOUTS; ++j) {
@@ -1303,6 +1552,28 @@ fl_status fl_tune(fl_ctx *ctx, fl_plan *p, const fl_params *prm, int32_t sweeps,
     return FL_OK;
 }
 
+fl_status fl_bucket_map(fl_ctx *ctx, const fl_plan *p, int32_t *lanes, int32_t *blocks, int64_t *rows) {
+    if (!ctx) return FL_EINVAL;
+    ctx->err.clear();
+    if (!p || p->ctx != ctx) return fail(ctx, FL_EINVAL, "bad plan");
+    FL_HIP(hipSetDevice(ctx->device));
+    const uint64_t m = bin_map_for(ctx, shape_key(p));
+    for (int b = 0; b < fl::kBuckets; ++b) {
+        if (lanes) lanes[b] = map_lanes(m, b);
+        if (blocks) blocks[b] = map_blocks(m, b);
+    }
+    if (rows) {
+        int32_t *tmp = pool_alloc<int32_t>(ctx, p->n);
+        if (!tmp) return fail(ctx, FL_ENOMEM, "device allocation failed");
+        int32_t sizes[fl::kBuckets];
+        const fl_status st = bucket_rows(ctx, p, tmp, sizes);
+        ctx->pool.release(tmp);
+        if (st != FL_OK) return st;
+        for (int b = 0; b < fl::kBuckets; ++b) rows[b] = sizes[b];
+    }
+    return FL_OK;
+}
+
 // ---- batches ----
 
 fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out) {
@@ -1314,8 +1585,9 @@ fl_status fl_batch_create(fl_ctx *ctx, fl_batch **out) {
     fl_batch *b = new (std::nothrow) fl_batch;
     if (!b) return fail(ctx, FL_ENOMEM, "out of host memory");
     b->ctx = ctx;
-    for (int w = 1; w <= fl::kMaxWords; ++w) {
-        hipError_t he = fl::batch_sweep_blocks_per_cu(w, &b->sweep_per_cu[w]);
+    for (int w = 0; w <= fl::kMaxWords; ++w) {
+        hipError_t he = w == 0 ? fl::batch_sweep_binned_blocks_per_cu(&b->sweep_per_cu[0])
+                               : fl::batch_sweep_blocks_per_cu(w, &b->sweep_per_cu[w]);
         if (he != hipSuccess) {
             delete b;
             return fail(ctx, FL_EHIP, "occupancy query: %s", hipGetErrorString(he));
@@ -1390,21 +1662,50 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     // is only read; the member's own buffers come from this context)
     if (b->ctx != ctx) return fail(ctx, FL_EINVAL, "batch belongs to another context");
     if (p->ctx->device != ctx->device) return fail(ctx, FL_EINVAL, "plan is on another device");
-    if (p->sl.words == 0 || x_bytes_of(p) == 0)
-        return fail(ctx, FL_EINVAL, "space has %d candidate slots or 2^29+ configurations: use fl_execute",
-                    p->sl.k);
+    if (prm && prm->row_mapping != 0 && !is_slot_layout(prm->row_mapping) && !is_binned_layout(prm->row_mapping))
+        return fail(ctx, FL_EINVAL, "batch members run FL_ROWS_SLOTS or FL_ROWS_BINNED (0: automatic)");
     Resolved r;
     fl_status st = resolve_params(ctx, p, prm, r);
     if (st != FL_OK) return st;
-    if (!is_slot_layout(r.lanes)) return fail(ctx, FL_EINVAL, "batches run the slot sweep only");
     FL_HIP(hipSetDevice(ctx->device));
-    int64_t tiles = 0;
-    for (const auto &m : b->members) tiles += tiles_of(m.plan);
-    st = batch_reserve(b, (int)b->members.size() + 1, tiles + tiles_of(p));
-    if (st != FL_OK) return st;
+    // layout: the slot sweep where the space allows it and it is asked for
+    // (or is the shape class's tuned layout, or nothing is tuned); else the
+    // binned sweep with the plan's bins (built here, with the class's tuned
+    // mapping, if the plan is this context's and has none)
+    const bool slot_ok = p->sl.words > 0 && x_bytes_of(p) > 0;
+    bool binned;
+    if (is_slot_layout(prm->row_mapping)) {
+        if (!slot_ok) return fail(ctx, FL_EINVAL, "the slot sweep cannot take a space of 2^29+ configurations");
+        binned = false;
+    } else if (is_binned_layout(prm->row_mapping)) {
+        binned = true;
+    } else {
+        const auto hit = ctx->tuned.find(shape_key(p));
+        binned = !slot_ok || (hit != ctx->tuned.end() && hit->second != FL_ROWS_SLOTS);
+    }
+    if (binned) {
+        if (p->ctx == ctx) {
+            st = ensure_binned(ctx, p, bin_map_for(ctx, shape_key(p)));
+            if (st != FL_OK) return st;
+        } else if (!p->have_bins) {
+            if (!slot_ok || is_binned_layout(prm->row_mapping))
+                return fail(ctx, FL_EINVAL, "the plan (of another context) has no binned rows");
+            binned = false;
+        }
+    }
     fl_batch::Member m;
+    m.plan = p;
+    m.binned = binned;
+    int64_t tiles = 0;
+    for (const auto &q : b->members) tiles += member_tiles(q);
+    st = batch_reserve(b, (int)b->members.size() + 1, tiles + member_tiles(m));
+    if (st != FL_OK) return st;
     st = member_alloc(ctx, p, m);
     if (st != FL_OK) return st;
+    if (binned) {
+        p->bin_users += 1;
+        m.holds_bins = true;
+    }
     m.plan = p;
     m.prm = r;
     m.out_pr = d_pagerank;
@@ -1436,11 +1737,18 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     bm.n = (int32_t)p->n;
     bm.m = (int32_t)p->m;
     bm.k_slots = p->sl.k;
-    bm.words = p->sl.words;
+    bm.words = binned ? 0 : p->sl.words;
     bm.x_bytes = x_bytes_of(p);
-
     bm.n_tiles = tiles_of(p);
     bm.max_iter = r.max_iter;
+    bm.xmap = binned ? nullptr : p->valid_raw;
+    bm.n_parts = binned ? p->bins.tiles : tiles_of(p);
+    if (binned) {
+        bm.row_ptr = p->row_ptr;
+        bm.col_idx = p->col_idx;
+        bm.bin_rows = p->bin_rows;
+        bm.bins = p->bins;
+    }
     b->members.push_back(m);
     return FL_OK;
 }
@@ -1468,16 +1776,20 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
     }
     // running members: those the segmented launches sweep first (their ids
     // are the step kernel's list), then the small ones grouped by width
-    auto small = [&](const fl_batch::Member &m) { return b->small_tiles > 0 && tiles_of(m.plan) <= b->small_tiles; };
+    auto small = [&](const fl_batch::Member &m) {
+        return !m.binned && b->small_tiles > 0 && tiles_of(m.plan) <= b->small_tiles;
+    };
+    auto width = [](const fl_batch::Member &m) { return m.binned ? 0 : m.plan->sl.words; };
     int32_t n_run = 0;
     int64_t group_begin[fl::kMaxWords + 2] = {};
     int64_t nt = 0;
-    for (int w = 1; w <= fl::kMaxWords; ++w) {
+    for (int w = 0; w <= fl::kMaxWords; ++w) {
         group_begin[w] = nt;
         for (auto &m : b->members) {
-            if (m.phase != 1 || m.plan->sl.words != w || small(m)) continue;
+            if (m.phase != 1 || width(m) != w || small(m)) continue;
             i_run[n_run++] = m.slot;
-            for (int32_t t = 0; t < tiles_of(m.plan); ++t) t_sweep[nt++] = {m.slot, t};
+            const int32_t sweep_tiles = m.binned ? m.plan->bins.tiles : tiles_of(m.plan);
+            for (int32_t t = 0; t < sweep_tiles; ++t) t_sweep[nt++] = {m.slot, t};
         }
     }
     group_begin[fl::kMaxWords + 1] = nt;
@@ -1486,12 +1798,12 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
     for (int w = 1; w <= fl::kMaxWords; ++w) {
         small_begin[w] = n_all;
         for (auto &m : b->members)
-            if (m.phase == 1 && m.plan->sl.words == w && small(m)) i_run[n_all++] = m.slot;
+            if (m.phase == 1 && width(m) == w && small(m)) i_run[n_all++] = m.slot;
     }
     small_begin[fl::kMaxWords + 1] = n_all;
     int32_t *hc = b->h_counts;
     memset(hc, 0, sizeof(int32_t) * fl_batch::kCounts);
-    for (int w = 1; w <= fl::kMaxWords; ++w) {
+    for (int w = 0; w <= fl::kMaxWords; ++w) {
         hc[2 * w] = (int32_t)group_begin[w];
         hc[2 * w + 1] = (int32_t)(group_begin[w + 1] - group_begin[w]);
     }
@@ -1536,7 +1848,7 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         shape.members = b->d_members;
         shape.tiles = b->d_tiles;
         shape.ids = b->d_ids;
-        for (int w = 1; w <= fl::kMaxWords; ++w) {
+        for (int w = 0; w <= fl::kMaxWords; ++w) {
             const int32_t cnt = hc[2 * w + 1];
             if (cnt == 0) continue;
             const int64_t resident =
@@ -1550,10 +1862,12 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         shape.finish_grid = fg;
         auto enqueue = [&](hipStream_t q) -> hipError_t {
             for (int32_t j = 0; j < sweeps; ++j) {
-                for (int w = 1; w <= fl::kMaxWords; ++w) {
+                for (int w = 0; w <= fl::kMaxWords; ++w) {
                     if (shape.grid[w] == 0) continue;
-                    hipError_t e = fl::launch_batch_sweep(b->d_members, d_sweep, b->d_counts + 2 * w, w,
-                                                          shape.grid[w], q);
+                    hipError_t e = w == 0 ? fl::launch_batch_sweep_binned(b->d_members, d_sweep, b->d_counts,
+                                                                          shape.grid[0], q)
+                                          : fl::launch_batch_sweep(b->d_members, d_sweep, b->d_counts + 2 * w, w,
+                                                                   shape.grid[w], q);
                     if (e != hipSuccess) return e;
                 }
                 hipError_t e = fl::launch_batch_finish(b->d_members, d_run, b->d_counts + fl_batch::kRunCount,
@@ -1639,7 +1953,8 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         for (int32_t j = 0; j < n_fin; ++j) {
             fl_batch::Member &m = b->members[fin_index[j]];
             const PrState &hs = b->h_states[j];
-            fill_summary(m.plan, hs, FL_ROWS_SLOTS, hs.done == 1 ? FL_OK : FL_ENOCONV, &m.sum);
+            fill_summary(m.plan, hs, m.binned ? FL_ROWS_BINNED : FL_ROWS_SLOTS, hs.done == 1 ? FL_OK : FL_ENOCONV,
+                         &m.sum);
             m.phase = 2;
         }
     }
@@ -1912,7 +2227,7 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
         int32_t cap = 0;
         int64_t tiles = 0;
         for (auto &bd : builds)
-            if (bd.status == FL_OK && bd.p->sl.words > 0 && x_bytes_of(bd.p) > 0) {
+            if (bd.status == FL_OK) {
                 ++cap;
                 tiles += tiles_of(bd.p);
             }
@@ -1940,12 +2255,16 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
             out[j].status = FL_EINVAL;
             continue;
         }
-        if (p->sl.words > 0 && x_bytes_of(p) > 0 && is_slot_layout(r.lanes)) {
+        // every space joins the batch (slot or binned sweep); an explicit
+        // lanes-per-row CSR layout runs alone
+        const int32_t rm = prm[j].row_mapping;
+        if (rm == 0 || is_slot_layout(rm) || is_binned_layout(rm)) {
             st = fl_batch_add(ctx, b, p, &prm[j], d_pagerank[j], d_minima[j], j);
             if (st == FL_OK) {
                 ++in_batch;
                 continue;
             }
+            if (st == FL_EHIP) break;
         }
         st = fl_execute(ctx, p, &prm[j], d_pagerank[j], d_minima[j], &out[j]);
         status[j] = st;

@@ -116,9 +116,36 @@ struct PrState {
 
 // Row formats of the PageRank sweep.
 enum SweepKind : int32_t {
-    kSweepCsr = 0,   // pull over the CSR, L lanes per row, x indexed by node id
-    kSweepSlots = 1  // pull over the records' in-edge slot bits, x indexed by raw index
+    kSweepCsr = 0,    // pull over the CSR, L lanes per row, x indexed by node id
+    kSweepSlots = 1,  // pull over the records' in-edge slot bits, x indexed by raw index
+    kSweepBinned = 2  // pull over the CSR with rows binned by in-degree, each bin its own lanes per row
 };
+
+// Rows binned by in-degree: bucket 0 holds in-degree 0, bucket b >= 1 the
+// in-degrees [2^(b-1), 2^b), the last bucket everything above.  A mapping
+// gives every bucket its lanes per row L and rows blocks per tile T; buckets
+// with the same (L, T) form one class, whose rows (node ids, ascending) are
+// contiguous in the plan's bin_rows array.  A tile of a class is T blocks of
+// kBlock / L rows and writes one partial-sum triple.
+constexpr int kBuckets = 8;
+struct BinClass {
+    int32_t row_begin;   // first entry of the class in bin_rows
+    int32_t rows;
+    int32_t tile_begin;  // index of its first tile (and partial triple)
+    int16_t lanes;       // L
+    int16_t blocks;      // T
+};
+struct BinTable {
+    int32_t n_classes;
+    int32_t tiles;       // total tiles = partial triples of a sweep
+    BinClass c[kBuckets];
+};
+__host__ __device__ inline int bucket_of(int32_t deg) {
+    if (deg <= 0) return 0;
+    int b = 1;
+    while (b < kBuckets - 1 && deg >= (1 << b)) ++b;
+    return b;
+}
 
 struct PrArgs {
     const int32_t *row_ptr;
@@ -144,6 +171,8 @@ struct PrArgs {
     int32_t x_bytes;        // slot sweep: bytes its buffer loads span (x from the most negative slot
                             // offset to the end plus the largest), when < 2^31; else 0 (plain loads)
     int32_t exact;          // 1: Jacobi sweeps u <- 1 + d P u to an exact fixed point (s = c = 1)
+    const int32_t *bin_rows;  // binned sweep: node ids grouped by class
+    BinTable bins;            // binned sweep: classes and tiles
 };
 
 // One member of a batch: an FFG with its own power iteration, run together
@@ -164,6 +193,14 @@ struct BatchMember {
     int32_t *out_minima;
     double d, tol, threshold;
     int32_t n, m, k_slots, k_pad, words, x_bytes, n_tiles, max_iter;
+    // binned members (words == 0 in the batch's lists): CSR, bin rows and
+    // classes; x indexed by node id; a sweep writes bins.tiles partial
+    // triples (the initial iterate n_tiles, one per kBlock nodes)
+    const int32_t *row_ptr, *col_idx, *bin_rows;
+    const int32_t *xmap;       // node -> x index for the initial iterate (valid_raw, or null for node ids)
+    int32_t n_parts;           // partial triples a sweep writes
+    int32_t pad;
+    BinTable bins;
 };
 
 struct TileRef {
@@ -205,6 +242,18 @@ hipError_t launch_pr_step(const PrArgs &a, int grid, hipStream_t stream);
 hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
                                  int *blocks);
 hipError_t launch_pr_output(const PrArgs &a, double *pagerank, hipStream_t stream);
+// Binning of the rows by in-degree class: class_of[b] is the class of bucket
+// b.  Count per (class, node tile) into cnt (kBuckets x n_tiles, class-major),
+// scan it into off and totals (kBuckets entries), write bin_rows.
+hipError_t launch_bin_rows(const int32_t *row_ptr, int32_t n, const int8_t *class_of_dev, int32_t *cnt,
+                           int32_t *off, int32_t *totals, int32_t *bin_rows, hipStream_t stream);
+// One binned sweep restricted to the given table (the autotuner times one
+// class at a time this way), without the step kernel.
+hipError_t launch_pr_sweep_binned(const PrArgs &a, const BinTable &t, int grid, hipStream_t stream);
+hipError_t pr_binned_blocks_per_cu(int *blocks);
+hipError_t launch_batch_sweep_binned(const BatchMember *members, const TileRef *tiles, const int32_t *range_dev,
+                                     int grid, hipStream_t stream);
+hipError_t batch_sweep_binned_blocks_per_cu(int *blocks);
 hipError_t launch_score(const double *pagerank, const int32_t *minima, int32_t m,
                         const float *fit_c, double threshold, PrState *st, hipStream_t stream);
 // C_p for n thresholds: num[j], den[j] = rank sums over minima below

@@ -978,21 +978,185 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
 }
 
 
+// ---------------------------------------------------------------------------
+// Rows binned by in-degree (BinTable): each class of buckets has its own lanes
+// per row L and T blocks of kBlock / L rows per tile.  A row's terms are
+// gathered through the CSR exactly as in k_pr_iter_csr<L> and reduced over
+// its L lanes with shuffles; x is indexed by node id.
+
+struct BinSweep {
+    const int32_t *row_ptr, *col_idx, *out_deg, *rows;
+    const float *y_in, *x_in;
+    float *y_out, *x_out;
+    double s, c, sd;
+};
+
+template <int L>
+__device__ __forceinline__ void binned_block(const BinSweep &q, int32_t first, int32_t count, double &ps,
+                                             double &pr, double &pk) {
+    const int lane = threadIdx.x % L;
+    const int32_t r = first + (int32_t)(threadIdx.x / L);
+    const bool live = r < count;
+    const int32_t v = live ? q.rows[r] : 0;
+    float acc = 0.0f;
+    if (live) {
+        const int32_t e1 = q.row_ptr[v + 1];
+        for (int32_t e = q.row_ptr[v] + lane; e < e1; e += 4 * L) {
+            int32_t cix[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cix[u] = e + u * L < e1 ? q.col_idx[e + u * L] : -1;
+            float xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = cix[u] >= 0 ? q.x_in[cix[u]] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += xv[u];
+        }
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0 && live) {
+        const float yf = (float)(q.sd * (double)acc + q.c);
+        const int32_t deg = q.out_deg[v];
+        q.y_out[v] = yf;
+        q.x_out[v] = deg > 0 ? yf / (float)deg : 0.0f;
+        ps += (double)yf;
+        pr += fabs((double)yf - q.s * (double)q.y_in[v]);
+        if (deg == 0) pk += (double)yf;
+    }
+}
+
+// Tile t (0 <= t < table.tiles) of a binned sweep: its class, then T blocks.
+// The table is read in place (kernel arguments or the member table) through
+// the scalar unit.
+__device__ __forceinline__ void binned_tile(const BinSweep &q0, const_ptr<BinTable> tb, int32_t t, double &ps,
+                                            double &pr, double &pk) {
+    int cl = 0;
+    const int nc = tb->n_classes;
+    for (int j = 1; j < nc; ++j)
+        if (t >= tb->c[j].tile_begin) cl = j;
+    const const_ptr<BinClass> c = &tb->c[cl];
+    const int32_t rows = c->rows, lanes = c->lanes, blocks = c->blocks;
+    BinSweep q = q0;
+    q.rows = q0.rows + c->row_begin;
+    const int32_t lt = t - c->tile_begin;
+    ps = pr = pk = 0.0;
+    for (int b = 0; b < blocks; ++b) {
+        const int32_t first = (lt * blocks + b) * (kBlock / lanes);
+        switch (lanes) {
+            case 1: binned_block<1>(q, first, rows, ps, pr, pk); break;
+            case 2: binned_block<2>(q, first, rows, ps, pr, pk); break;
+            case 4: binned_block<4>(q, first, rows, ps, pr, pk); break;
+            case 8: binned_block<8>(q, first, rows, ps, pr, pk); break;
+            case 16: binned_block<16>(q, first, rows, ps, pr, pk); break;
+            case 32: binned_block<32>(q, first, rows, ps, pr, pk); break;
+            default: binned_block<64>(q, first, rows, ps, pr, pk); break;
+        }
+    }
+}
+
+// The binned sweep over the tiles of a.bins (the plan's whole table, or a
+// part of it while the autotuner times one class).
+__global__ __launch_bounds__(kBlock) void k_pr_iter_binned(PrArgs a) {
+    const PrState *st = a.st;
+    if (st->done) return;
+    const int32_t k = st->k;
+    BinSweep q;
+    q.row_ptr = a.row_ptr;
+    q.col_idx = a.col_idx;
+    q.out_deg = a.out_deg;
+    q.rows = a.bin_rows;
+    q.y_in = a.y[k & 1];
+    q.x_in = a.x[k & 1];
+    q.y_out = a.y[(k + 1) & 1];
+    q.x_out = a.x[(k + 1) & 1];
+    q.s = st->s;
+    q.c = st->c;
+    q.sd = q.s * a.d;
+    const const_ptr<BinTable> tb = &kernel_arg<PrArgs>()->bins;
+    const TileWalk w(a.bins.tiles);
+    for (int32_t t = w.first; t < w.end; t += w.step) {
+        double ps, pr, pk;
+        binned_tile(q, tb, t, ps, pr, pk);
+        write_partials(a.partials, t, ps, pr, pk);
+    }
+}
+
+// Binning of the rows: per node tile, the number of rows of each class;
+// one-workgroup scan of those counts in class-major order; then every row
+// written to its class's range in ascending node id.
+__device__ __forceinline__ int8_t row_class(const int32_t *__restrict__ row_ptr, int32_t v, int32_t n,
+                                            const int8_t *__restrict__ class_of) {
+    return v < n ? class_of[bucket_of(row_ptr[v + 1] - row_ptr[v])] : (int8_t)-1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t *__restrict__ row_ptr, int32_t n,
+                                                      const int8_t *__restrict__ class_of,
+                                                      int32_t *__restrict__ cnt, int32_t n_tiles) {
+    __shared__ int32_t wc[kBuckets][kBlock / 64];
+    const int32_t tile = blockIdx.x, v = tile * kBlock + threadIdx.x;
+    const int8_t cls = row_class(row_ptr, v, n, class_of);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < kBuckets; ++c) {
+        const uint64_t m = __ballot(cls == c);
+        if (lane == 0) wc[c][wid] = __popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x < kBuckets) {
+        int32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += wc[threadIdx.x][w];
+        cnt[(int64_t)threadIdx.x * n_tiles + tile] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_scan(const int32_t *__restrict__ cnt, int32_t *__restrict__ off,
+                                                     int32_t *__restrict__ totals, int32_t n_tiles) {
+    const int32_t total = scan_tiles(cnt, off, kBuckets * n_tiles);
+    __syncthreads();
+    if (threadIdx.x < kBuckets) {
+        const int c = threadIdx.x;
+        const int32_t lo = off[(int64_t)c * n_tiles];
+        const int32_t hi = c + 1 < kBuckets ? off[(int64_t)(c + 1) * n_tiles] : total;
+        totals[c] = hi - lo;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_write(const int32_t *__restrict__ row_ptr, int32_t n,
+                                                      const int8_t *__restrict__ class_of,
+                                                      const int32_t *__restrict__ off, int32_t n_tiles,
+                                                      int32_t *__restrict__ bin_rows) {
+    __shared__ int32_t wc[kBuckets][kBlock / 64];
+    const int32_t tile = blockIdx.x, v = tile * kBlock + threadIdx.x;
+    const int8_t cls = row_class(row_ptr, v, n, class_of);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int32_t rank = 0;
+#pragma unroll
+    for (int c = 0; c < kBuckets; ++c) {
+        const uint64_t m = __ballot(cls == c);
+        if (cls == c) rank = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wc[c][wid] = __popcll(m);
+    }
+    __syncthreads();
+    if (cls >= 0) {
+        int32_t base = off[(int64_t)cls * n_tiles + tile];
+        for (int w = 0; w < wid; ++w) base += wc[cls][w];
+        bin_rows[base + rank] = v;
+    }
+}
+
 // Slot sweep of one tile of kBlock nodes: one node per lane, 64 consecutive
 // nodes per wave.  For every candidate slot whose in-edge bit is set, gather
 // x at raw index i + off[s] (x lives in raw-index space, so neither col_idx
-// nor an index remap is read).  The wave's lanes that have slot s as an
-// in-edge are given by one 64-bit mask per (wave, slot), written by the
-// degree pass and read here through the scalar unit: a zero mask skips the
-// slot with a scalar branch, any other becomes the execution mask of the
-// slot's load directly, so a slot costs no per-lane bit test.  The slot's
-// offset goes into the load's scalar offset (the buffer base is moved down by
-// the most negative offset so that every scalar offset is >= 0), leaving
-// the zeroing of the register and the add as the only vector work per slot.
-// Slots run in ascending raw-index order, the order of the CSR rows, so the
-// FP32 sum equals the one-lane-per-row CSR sweep's bit for bit.  The plain
-// and the batched sweep both run this routine, so their results agree bit
-// for bit.
+// nor an index remap is read).  A lane's in-edge bit for a slot is tested
+// with one class comparison on a field of its record (see below), and the
+// result is the execution mask of the slot's load, so lanes without the
+// in-edge issue nothing.  The slot's offset goes into the load's scalar
+// offset (the buffer base is moved down by the most negative offset so that
+// every scalar offset is >= 0).  Slots run in ascending raw-index order, the
+// order of the CSR rows, so the FP32 sum equals the one-lane-per-row CSR
+// sweep's bit for bit.  The plain and the batched sweep both run this
+// routine, so their results agree bit for bit.
 struct SweepTile {
     const uint64_t *rec;         // node records
     const_ptr<int32_t> off;      // [k_pad] slot offsets, ascending (off[0] the most negative),
@@ -1170,13 +1334,45 @@ __global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchMember *__res
     }
 }
 
+// Binned members: each listed (member, tile) is a tile of the member's bin
+// table, swept as by k_pr_iter_binned.
+__global__ __launch_bounds__(kBlock) void k_batch_sweep_binned(const BatchMember *__restrict__ members,
+                                                               const TileRef *__restrict__ tiles,
+                                                               const int32_t *__restrict__ range_dev) {
+    const int32_t begin = to_const(range_dev)[0], count = to_const(range_dev)[1];
+    const TileWalk w(count);
+    const_ptr<TileRef> tl = to_const(tiles) + begin;
+    for (int32_t t = w.first; t < w.end; t += w.step) {
+        const int32_t member = tl[t].member, tile = tl[t].tile;
+        const_ptr<BatchMember> m = to_const(members) + member;
+        const_ptr<PrState> st = to_const(m->st);
+        if (st->done) continue;
+        const int32_t k = st->k;
+        BinSweep q;
+        q.row_ptr = m->row_ptr;
+        q.col_idx = m->col_idx;
+        q.out_deg = m->out_deg;
+        q.rows = m->bin_rows;
+        q.y_in = m->y[k & 1];
+        q.x_in = m->x[k & 1];
+        q.y_out = m->y[(k + 1) & 1];
+        q.x_out = m->x[(k + 1) & 1];
+        q.s = st->s;
+        q.c = st->c;
+        q.sd = q.s * m->d;
+        double ps, pr, pk;
+        binned_tile(q, &m->bins, tile, ps, pr, pk);
+        write_partials(m->partials, tile, ps, pr, pk);
+    }
+}
+
 // Initial iterate r = 1/N of every listed tile, with its partial sums.
 __global__ __launch_bounds__(kBlock) void k_batch_init(const BatchMember *__restrict__ members,
                                                        const TileRef *__restrict__ tiles, int32_t n_tiles) {
     for (int32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileRef tr = tiles[t];
         const BatchMember &m = members[tr.member];
-        init_tile(tr.tile, m.n, m.out_deg, m.valid_raw, m.y[0], m.x[0], m.partials);
+        init_tile(tr.tile, m.n, m.out_deg, m.xmap, m.y[0], m.x[0], m.partials);
     }
 }
 
@@ -1191,7 +1387,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_batch_finish(const BatchMember
     for (int32_t j = blockIdx.x; j < n_members; j += gridDim.x) {
         const BatchMember &m = members[member_ids[j]];
         if (!FIRST && m.st->done) continue;   // uniform per workgroup
-        finish_step(m.st, m.partials, m.n_tiles, m.d, m.tol, m.max_iter, m.n, FIRST);
+        finish_step(m.st, m.partials, FIRST ? m.n_tiles : m.n_parts, m.d, m.tol, m.max_iter, m.n, FIRST);
         __syncthreads();                       // block_sum3's LDS is reused by the next member
     }
 }
@@ -1629,12 +1825,36 @@ hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream) {
 hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
                                  int *blocks) {
     (void)sp;
+    if (a.kind == kSweepBinned) return pr_binned_blocks_per_cu(blocks);
     const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(lanes);
     if (!fn) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
 }
 
+hipError_t launch_pr_sweep_binned(const PrArgs &a, const BinTable &t, int grid, hipStream_t stream) {
+    if (t.tiles <= 0) return hipSuccess;
+    PrArgs b = a;
+    b.bins = t;
+    hipLaunchKernelGGL(k_pr_iter_binned, dim3(grid), dim3(kBlock), 0, stream, b);
+    return hipGetLastError();
+}
+
+hipError_t pr_binned_blocks_per_cu(int *blocks) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_pr_iter_binned, kBlock, 0);
+}
+
+hipError_t launch_bin_rows(const int32_t *row_ptr, int32_t n, const int8_t *class_of_dev, int32_t *cnt,
+                           int32_t *off, int32_t *totals, int32_t *bin_rows, hipStream_t stream) {
+    const int32_t n_tiles = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_bin_count, dim3(n_tiles), dim3(kBlock), 0, stream, row_ptr, n, class_of_dev, cnt, n_tiles);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBlock), 0, stream, cnt, off, totals, n_tiles);
+    hipLaunchKernelGGL(k_bin_write, dim3(n_tiles), dim3(kBlock), 0, stream, row_ptr, n, class_of_dev, off, n_tiles,
+                       bin_rows);
+    return hipGetLastError();
+}
+
 hipError_t launch_pr_sweep(const PrArgs &a, const SlotTable &sl, int lanes, int grid, hipStream_t stream) {
+    if (a.kind == kSweepBinned) return launch_pr_sweep_binned(a, a.bins, grid, stream);
     const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(lanes);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {(void *)&a};
@@ -1642,8 +1862,10 @@ hipError_t launch_pr_sweep(const PrArgs &a, const SlotTable &sl, int lanes, int 
 }
 
 hipError_t launch_pr_step(const PrArgs &a, int grid, hipStream_t stream) {
-    // partial sums: one triple per tile (slot sweep) or per workgroup (CSR sweep)
-    const int32_t count = a.kind == kSweepSlots ? (a.n + kBlock - 1) / kBlock : grid;
+    // partial sums: one triple per tile (slot sweep, binned sweep) or per
+    // workgroup (CSR sweep)
+    const int32_t count = a.kind == kSweepSlots ? (a.n + kBlock - 1) / kBlock
+                          : a.kind == kSweepBinned ? a.bins.tiles : grid;
     hipLaunchKernelGGL(k_pr_finish<false>, dim3(1), dim3(kFinishBlock), 0, stream, a, count);
     return hipGetLastError();
 }
@@ -1707,6 +1929,16 @@ static const void *batch_sweep_kernel(int words) {
         case 5: return (const void *)k_batch_sweep<5, true>;
         default: return nullptr;
     }
+}
+
+hipError_t launch_batch_sweep_binned(const BatchMember *members, const TileRef *tiles, const int32_t *range_dev,
+                                     int grid, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_sweep_binned, dim3(grid), dim3(kBlock), 0, stream, members, tiles, range_dev);
+    return hipGetLastError();
+}
+
+hipError_t batch_sweep_binned_blocks_per_cu(int *blocks) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_batch_sweep_binned, kBlock, 0);
 }
 
 hipError_t batch_sweep_blocks_per_cu(int words, int *blocks) {

@@ -126,8 +126,11 @@ class _Builder:
 
 
 def _batchable(plan) -> bool:
+    """Whether a batch can take the plan: a space without slot records has
+    its rows binned when it is built (binned sweep); one with them needs the
+    slot sweep's buffer loads (4 n_raw < 2^31)."""
     words = int(plan.sizes.get("mask_words", 0))
-    return words > 0 and 4 * plan.sizes["n_raw"] < 2 ** 31
+    return words == 0 or 4 * plan.sizes["n_raw"] < 2 ** 31
 
 
 class GpuBackend:

@@ -291,6 +291,8 @@ def test_segmented_build_every_record_width(ctx):
 
 
 def test_batch_rejects_bad_members(ctx):
+    """Bad parameters and layouts are rejected at fl_batch_add; a space too
+    wide for slot records joins as a binned member."""
     import torch
     from paper_2210_01465_amd import api, _abi
     batch = api.Batch(ctx)
@@ -298,16 +300,21 @@ def test_batch_rejects_bad_members(ctx):
     fit = torch.from_numpy((rng.permutation(200) + 1.0).astype(np.float32)).cuda()
     plan = api.plan_create(ctx, (200,), fit)
     with pytest.raises(api.FLError) as e:
-        batch.add(plan)
+        batch.add(plan, row_mapping=ROWS_SLOTS)        # 398 candidate slots: no slot records
     assert e.value.status == _abi.FL_EINVAL
     s = synth.tiny(0)
     plan2 = api.plan_create(ctx, s.radix, torch.from_numpy(s.fitness_raw).cuda())
-    for kw in ({"damping": 1.0}, {"p": -1.0}):
+    for kw in ({"damping": 1.0}, {"p": -1.0}, {"row_mapping": 8}, {"row_mapping": 3}):
         with pytest.raises(api.FLError):
             batch.add(plan2, **kw)
-    batch.add(plan2)
-    assert batch.step(100) == 0
-    assert len(batch.collect()) == 1
+    batch.add(plan2, tag=0)
+    batch.add(plan, tag=1)                             # binned
+    while batch.step(100) > 0:
+        pass
+    got = {t: (pr.cpu().numpy(), info) for t, pr, _, info in batch.collect()}
+    assert sorted(got) == [0, 1] and got[1][1]["row_mapping"] == -2
+    ref, _, _ = api.execute(plan, 0.85, 0.05, row_mapping=-2)
+    assert np.array_equal(got[1][0], ref.cpu().numpy())
     batch.close()
     plan.close()
     plan2.close()
@@ -466,3 +473,49 @@ def test_small_members_iterate_in_one_workgroup(ctx):
             ref = plain(ctx, s, "hamming", (0.8, 0.85, 0.9)[j % 3], 0.05)
             assert np.array_equal(done[j][0], ref[0]), (setting, s.name)
             assert np.array_equal(done[j][1], ref[1]) and done[j][2]["iterations"] == ref[2]["iterations"]
+
+
+def test_binned_members_equal_plain_binned_runs(ctx):
+    """Members on the binned sweep (rows binned by in-degree, per-bucket lanes
+    per row), mixed with slot-sweep members and joining mid-run: each result
+    equals fl_execute with FL_ROWS_BINNED bit for bit and matches the FP64
+    oracle."""
+    import torch
+    from paper_2210_01465_amd import api
+    rng = np.random.default_rng(17)
+    wide = synth.Space("wide", (200, 3), rng.lognormal(0.0, 0.5, 600).astype(np.float32))
+    spaces = [synth.mid(), synth.tiny(2), wide] + synth.batched()[9:200:40]
+    nbs = ["hamming", "adjacent", "hamming"] + ["hamming"] * (len(spaces) - 3)
+    say(f"binned members: {len(spaces)} spaces")
+    fits = [torch.from_numpy(s.fitness_raw).cuda() for s in spaces]
+    plans = [api.plan_create(ctx, s.radix, f, nb) for s, f, nb in zip(spaces, fits, nbs)]
+    batch = api.Batch(ctx)
+    done = {}
+    for j, pl in enumerate(plans):
+        lay = -2 if j % 2 == 0 or pl.sizes["mask_words"] == 0 else ROWS_SLOTS
+        batch.add(pl, (0.8, 0.85, 0.9)[j % 3], 0.05, tag=j, row_mapping=lay)
+        batch.step(3)                                   # members join a running batch
+        for tag, pr, mins, info in batch.collect():
+            done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+    while True:
+        running = batch.step(8)
+        for tag, pr, mins, info in batch.collect():
+            done[tag] = (pr.cpu().numpy(), mins.cpu().numpy(), info)
+        if running == 0:
+            break
+    batch.close()
+    for j, (s, pl, nb) in enumerate(zip(spaces, plans, nbs)):
+        d = (0.8, 0.85, 0.9)[j % 3]
+        lay = done[j][2]["row_mapping"]
+        pr, mins, info = api.execute(pl, d, 0.05, row_mapping=lay)
+        assert np.array_equal(done[j][0], pr.cpu().numpy()), (s.name, lay)
+        assert np.array_equal(done[j][1], mins.cpu().numpy())
+        assert done[j][2]["iterations"] == info["iterations"]
+        o = oracle.analyze(s.radix, s.fitness_raw, oracle.HAMMING if nb == "hamming" else oracle.ADJACENT, d, 0.05,
+                           tol=1e-12)
+        assert np.array_equal(done[j][1], o.graph.minima)
+        assert float(np.abs(done[j][0] - o.pagerank).sum()) <= L1_TOL, s.name
+        assert abs(done[j][2]["score"] - o.score) <= 1e-5
+    assert any(done[j][2]["row_mapping"] == -2 for j in done)
+    for pl in plans:
+        pl.close()

@@ -104,9 +104,10 @@ def test_fuzz_parity(ctx, seed):
 ROWS_SLOTS = -1
 
 
-@pytest.mark.parametrize("lanes", [ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lanes", [ROWS_SLOTS, 1, 2, 4, 8, 16, 32, 64, -2])
 def test_every_row_mapping(ctx, lanes):
-    """Every sweep layout: the slot sweep and the CSR sweep with 1..64 lanes."""
+    """Every sweep layout: the slot sweep, the CSR sweep with 1..64 lanes and
+    the CSR sweep with rows binned by in-degree (-2)."""
     for nb in ("hamming", "adjacent"):
         check_parity(ctx, synth.tiny(3), nb, row_mapping=lanes)
         check_parity(ctx, synth.fuzz_space(5, max_params=6, max_radix=8), nb, row_mapping=lanes)
@@ -285,7 +286,7 @@ def test_error_paths(ctx):
     plan = api.plan_create(ctx, (8,), ones)
     try:
         for kw in ({"damping": 0.0}, {"damping": 1.0}, {"damping": float("nan")},
-                   {"p": -0.1}, {"p": float("inf")}, {"row_mapping": 3}, {"row_mapping": -2},
+                   {"p": -0.1}, {"p": float("inf")}, {"row_mapping": 3}, {"row_mapping": -3},
                    {"max_iter": -1}):
             args = {"damping": 0.85, "p": 0.05}
             args.update(kw)

@@ -12,7 +12,7 @@ from paper_2210_01465_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = (-1, 1, 2, 4, 8, 16, 32, 64)
+LAYOUTS = (-1, 1, 2, 4, 8, 16, 32, 64, -2)
 
 
 def say(msg):
@@ -93,6 +93,41 @@ def test_tune_rejects_bad_arguments(api_mod):
             api.tune(plan, sweeps=0)
         with pytest.raises(api.FLError):
             api.tune(plan, damping=1.5)
+        plan.close()
+    finally:
+        ctx.close()
+
+
+def test_bucket_mapping_is_tuned_and_used(api_mod):
+    """The tuner's per-bucket mapping: rows per in-degree bucket exactly as the
+    oracle's in-degrees give them, lanes per row and blocks per tile from the
+    allowed sets; the binned layout then runs that mapping and matches the
+    oracle."""
+    import torch
+    api = api_mod
+    space = synth.mid()
+    ctx = api.Context(0)
+    try:
+        say("bucket mapping, mid hamming")
+        plan = api.plan_create(ctx, space.radix, torch.from_numpy(space.fitness_raw).cuda(), "hamming")
+        before = api.bucket_map(plan)
+        res = api.tune(plan, sweeps=3)
+        after = res["buckets"]
+        g = oracle.build_graph(space.radix, space.fitness_raw)
+        deg = np.diff(g.row_ptr.astype(np.int64))
+        edges = [0, 1, 2, 4, 8, 16, 32, 64, 1 << 40]
+        for b, name in enumerate(api.BUCKETS):
+            lo, hi = (0, 0) if b == 0 else (edges[b], edges[b + 1] - 1)
+            want = int(np.count_nonzero((deg >= lo) & (deg <= hi)))
+            assert after[name]["rows"] == before[name]["rows"] == want, (name, after[name], want)
+            assert after[name]["lanes"] in (1, 2, 4, 8, 16, 32, 64) and after[name]["blocks"] in (1, 4)
+        assert sum(v["rows"] for v in after.values()) == g.N
+        assert -2 in res["us_per_sweep"] and res["us_per_sweep"][-2] > 0
+        pr, mins, info = api.execute(plan, 0.85, 0.05, row_mapping=-2)
+        assert info["row_mapping"] == -2
+        o = oracle.analyze(space.radix, space.fitness_raw, oracle.HAMMING, 0.85, 0.05, tol=1e-12)
+        assert np.array_equal(mins.cpu().numpy(), o.graph.minima)
+        assert float(np.abs(pr.cpu().numpy() - o.pagerank).sum()) <= 1e-5
         plan.close()
     finally:
         ctx.close()
