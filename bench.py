@@ -101,10 +101,11 @@ def _pmc_total(csv_dir: str, counter: str, kernel_parts):
     return total, n
 
 
-def trace_mean_us(trace_dir: str, kernel_part: str, floor_frac: float = 0.1):
+def trace_mean_us(trace_dir: str, kernel_part: str, floor_frac: float = 0.5):
     """Mean duration (us) of the working launches of a kernel in a rocprofv3
     --kernel-trace CSV: launches at least floor_frac of the longest (sweep
-    launches after convergence exit at once)."""
+    launches after convergence exit at once, in about a fifth of a working
+    launch's time)."""
     import csv
     import glob
     ds = []
@@ -348,6 +349,42 @@ def batched_oracle(spaces, results, damping, p, tol):
             {"pagerank_l1_max": l1, "score_abs_max": cp, "minima_exact": exact})
 
 
+def batched_autotune(spaces, fits, damping, p, tol, repeats: int = 3):
+    """The autotuner on the batched workload, in a context of its own: fl_tune
+    on every space (its shape class's per-bucket mapping and layout), then
+    the 234 spaces through fl_analyze_batch with automatic layouts, against
+    the same call in a fresh untuned context.  Reports the tuning time, the
+    layouts chosen and both call times."""
+    import collections
+    import torch
+    from paper_2210_01465_amd import api
+    radices = [s.radix for s in spaces]
+
+    def timed(ctx):
+        api.analyze_batch(radices, fits, "hamming", damping, p, tol, ctx=ctx)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            res = api.analyze_batch(radices, fits, "hamming", damping, p, tol, ctx=ctx)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / repeats, res
+    with api.Context(0) as fresh:
+        t_plain, _ = timed(fresh)
+    with api.Context(0) as ctx:
+        chosen = collections.Counter()
+        t0 = time.perf_counter()
+        for s, f in zip(spaces, fits):
+            plan = api.plan_create(ctx, s.radix, f, "hamming")
+            chosen[{-1: "slots", -2: "binned"}.get(api.tune(plan, damping, sweeps=3)["best"], "csr")] += 1
+            plan.close()
+        tune_s = time.perf_counter() - t0
+        t_tuned, res = timed(ctx)
+        used = collections.Counter({-1: "slots", -2: "binned"}.get(r.info["row_mapping"], "csr") for r in res)
+    return {"tune_ms": round(tune_s * 1e3, 1), "layout_chosen": dict(chosen), "layout_run": dict(used),
+            "ms_untuned": round(t_plain * 1e3, 3), "ms_tuned": round(t_tuned * 1e3, 3),
+            "all_ok": all(r.info["status"] == 0 for r in res)}
+
+
 def batched_leg(ctx, damping, p, tol, repeats: int = 3):
     """234 spaces (26 shapes x 9 landscapes, N from 414 to 196k): one
     fl_analyze_batch over all of them against the same analyses run one at a
@@ -374,29 +411,32 @@ def batched_leg(ctx, damping, p, tol, repeats: int = 3):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     oracle_cpu, accuracy = batched_oracle(spaces, res, damping, p, tol)
+    tuned = batched_autotune(spaces, fits, damping, p, tol, repeats)
     return {"spaces": len(spaces), "n_valid_total": nodes, "ms_batched": round(t_batch * 1e3, 3),
             "ms_one_at_a_time": round(t_plain * 1e3, 3), "speedup": round(t_plain / t_batch, 3),
             "gteps_batched": round(edges / t_batch / 1e9, 3),
             "gteps_one_at_a_time": round(edges / t_plain / 1e9, 3),
             "all_ok": all(r.info["status"] == 0 for r in res),
-            "accuracy": accuracy, "oracle_all_threads": oracle_cpu,
+            "accuracy": accuracy, "oracle_all_threads": oracle_cpu, "autotune": tuned,
             "sweep_loop": batched_sweep_rate(ctx, spaces, fits, damping, p, tol)}
 
 
 def batched_sweep_rate(ctx, spaces, fits, damping, p, tol, sweeps_per_step: int = 16):
     """HBM rate of the batched sweep loop alone: every space's plan built
-    first, all added to one batch, stepped to the end.  Algorithmic bytes are
-    the slot sweep's per-sweep bytes ((20 + 8 W) N + 4 E) times each member's
-    iteration count; time is the batch's HIP-event device time around its
-    sweep loops (batched sweeps and the per-member step kernel together).
-    The second of two identical runs is reported (the first captures the
-    loop's graphs)."""
+    first, all added to one batch (the small-member path off, so that every
+    member's sweeps run inside the timed loop), stepped to the end.
+    Algorithmic bytes are the slot sweep's per-sweep bytes ((20 + 8 W) N +
+    4 E) times each member's iteration count; time is the batch's HIP-event
+    device time around its sweep loops (batched sweeps and the per-member
+    step kernel together).  The second of two identical runs is reported
+    (the first captures the loop's graphs)."""
     import torch
     from paper_2210_01465_amd import api
     plans = [api.plan_create(ctx, s.radix, f, "hamming") for s, f in zip(spaces, fits)]
     try:
         for _ in range(2):
             batch = api.Batch(ctx)
+            batch.set_small(0)
             for j, pl in enumerate(plans):
                 batch.add(pl, damping, p, tol=tol, tag=j)
             infos = {}

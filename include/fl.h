@@ -320,10 +320,11 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *batch);
  * The member holds 8 n_raw + 8 N + 24 ceil(N/256) + 80 bytes of device
  * memory of its own while it is in the batch.
  * A member runs the slot sweep (FL_ROWS_SLOTS) or the binned sweep
- * (FL_ROWS_BINNED); row_mapping 0 takes the layout fl_tune cached for the
- * plan's shape class in this context (the binned sweep for any tuned layout
- * other than the slot sweep), the slot sweep when nothing is tuned, and the
- * binned sweep for spaces the slot sweep cannot take.  A binned member
+ * (FL_ROWS_BINNED); row_mapping 0 takes the binned sweep where fl_tune
+ * chose it for the plan's shape class in this context or where the slot
+ * sweep cannot take the space, else the slot sweep (a tuned lanes-per-row
+ * CSR layout wins on a lone space by spreading it over more workgroups; in
+ * a batch the other members supply that parallelism).  A binned member
  * sweeps the plan's binned rows (built here with the class's tuned mapping
  * when the plan belongs to this context; a plan of another context must
  * already have them, as plans without slot records do).  Its results equal

@@ -1680,8 +1680,11 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     } else if (is_binned_layout(prm->row_mapping)) {
         binned = true;
     } else {
+        // a tuned lanes-per-row CSR layout wins on a lone space by spreading
+        // it over more workgroups; in a batch the members supply that
+        // parallelism, so such members keep the slot sweep
         const auto hit = ctx->tuned.find(shape_key(p));
-        binned = !slot_ok || (hit != ctx->tuned.end() && hit->second != FL_ROWS_SLOTS);
+        binned = !slot_ok || (hit != ctx->tuned.end() && hit->second == FL_ROWS_BINNED);
     }
     if (binned) {
         if (p->ctx == ctx) {

@@ -1072,12 +1072,23 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_binned(PrArgs a) {
     q.s = st->s;
     q.c = st->c;
     q.sd = q.s * a.d;
+    // Every class's tiles are dealt to the XCDs in eighths, XCD j taking the
+    // j-th eighth of each class in turn: a class's rows ascend in node id,
+    // so an XCD works in about the j-th eighth of the nodes whatever the
+    // class, and the x values its rows gather stay local to its L2.
     const const_ptr<BinTable> tb = &kernel_arg<PrArgs>()->bins;
-    const TileWalk w(a.bins.tiles);
-    for (int32_t t = w.first; t < w.end; t += w.step) {
-        double ps, pr, pk;
-        binned_tile(q, tb, t, ps, pr, pk);
-        write_partials(a.partials, t, ps, pr, pk);
+    const int xcd = blockIdx.x % kXcds, nb = gridDim.x / kXcds, l = blockIdx.x / kXcds;
+    const int nc = tb->n_classes;
+    for (int cl = 0; cl < nc; ++cl) {
+        const int32_t t0 = tb->c[cl].tile_begin;
+        const int32_t ct = (cl + 1 < nc ? tb->c[cl + 1].tile_begin : a.bins.tiles) - t0;
+        const int32_t per = (ct + kXcds - 1) / kXcds;
+        const int32_t lo = t0 + per * xcd, hi = t0 + min(per * (xcd + 1), ct);
+        for (int32_t t = lo + l; t < hi; t += nb) {
+            double ps, pr, pk;
+            binned_tile(q, tb, t, ps, pr, pk);
+            write_partials(a.partials, t, ps, pr, pk);
+        }
     }
 }
 
