@@ -9,9 +9,11 @@ vector is resident in HBM before the timed region.
 
 value = FFG+PageRank edges traversed per second over the timed steps,
         sum(E * iterations) / wall time, in GTEPS.
-roofline = the PageRank sweep kernel: its algorithmic bytes per launch
-        ((20 + 8 W) N + 4 E for the slot sweep with W record words per node,
-        20 N + 8 E for the CSR sweep) over its mean duration, from pairs of
+roofline = the PageRank sweep kernel (which, in the engine's default lagged
+        form, also does the step of the sweep before): the algorithmic bytes
+        of one SpMV iteration, 20 N + 8 E, over its mean duration (and, as
+        layout_model, the bytes its own layout moves: (28 + 8 W) N + 4 E for
+        the slot sweep with W record words per node), from pairs of
         HIP events on the engine's stream around sweep launches of the timed
         steps (every 8th launch by default, so that the events barely slow
         the steps; launches after convergence, which exit at once, are not
@@ -690,7 +692,7 @@ def main():
     ap.add_argument("--traffic-from", metavar="DIR",
                     help="write the sweep kernel's HBM traffic record from the rocprofv3 --pmc "
                          "runs under DIR (no GPU needed) and exit")
-    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true>")
+    ap.add_argument("--traffic-kernel", default="k_pr_iter_slots<2, true, true>")
     ap.add_argument("--trace-from", metavar="DIR", default="",
                     help="with --traffic-from: a rocprofv3 --kernel-trace run whose mean working-launch "
                          "duration of the kernel goes into the traffic record")
@@ -802,14 +804,16 @@ def main():
     # out_deg, row_ptr (4 N each) and col_idx plus the x gathers (4 E each)
     bytes_per_launch = 20 * N + 8 * E
     if info["row_mapping"] == -1:   # slot sweep: records, y in/out, x out; x gathers (no col_idx)
-        layout_bytes = (20 + 8 * info["mask_words"]) * N + 4 * E
-        layout_formula = f"(20 + 8 W) N + 4 E, W = {info['mask_words']} record words"
+        # lagged step: the previous iterate and g are read as well (8 N)
+        layout_bytes = (28 + 8 * info["mask_words"]) * N + 4 * E
+        layout_formula = f"(28 + 8 W) N + 4 E, W = {info['mask_words']} record words"
         buf = 16 * ((n_raw + 3) // 4) < 2 ** 31
-        kernel = f"k_pr_iter_slots<{info['mask_words']}, {'true' if buf else 'false'}>"
-    else:                           # CSR sweep reads exactly the SpMV bytes
-        layout_bytes = bytes_per_launch
-        layout_formula = "20 N + 8 E"
-        kernel = f"k_pr_iter_csr<{info['row_mapping']}>"
+        kernel = f"k_pr_iter_slots<{info['mask_words']}, {'true' if buf else 'false'}, true>"
+    else:                           # CSR sweep reads the SpMV bytes, and 8 N more for the lagged step
+        layout_bytes = bytes_per_launch + 8 * N
+        layout_formula = "28 N + 8 E"
+        kernel = ("k_pr_iter_binned<true>" if info["row_mapping"] == -2
+                  else f"k_pr_iter_csr<{info['row_mapping']}, true>")
     achieved = bytes_per_launch / avg_launch_s / 1e9
     traffic_rec = traffic_record(TRAFFIC_FILE, kernel)
     traffic = traffic_rec.get("bytes_per_launch") if traffic_rec else None

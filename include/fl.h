@@ -87,17 +87,34 @@ typedef struct {
  *             1, 2, 4, 8, 16, 32 or 64 = that many lanes per row over the
  *             CSR.  Every layout sums a row's terms in ascending source
  *             order (one lane per row: sequentially; several: lane partial
- *             sums reduced by a fixed tree): the slot layout and the
- *             one-lane CSR layout give the same ranks bit for bit. */
+ *             sums reduced by a fixed tree): with FL_STEP_SEPARATE the
+ *             slot layout and the one-lane CSR layout give the same ranks
+ *             bit for bit (the lagged step sums per workgroup, and their
+ *             number depends on the layout's kernel). */
 #define FL_ROWS_SLOTS (-1)
 #define FL_ROWS_BINNED (-2)
 #define FL_TUNE_LAYOUTS 9
+/* flags: 0, or FL_STEP_SEPARATE.  By default fl_execute and
+ *             fl_execute_exact run the sweeps back to back and each sweep
+ *             also does the step (sums, residual, stop test) of the one
+ *             before; the power iteration then stores each iterate without
+ *             its constant teleport-and-sink term and adds it one step
+ *             later.  Same iterates in exact arithmetic, same iteration
+ *             count up to rounding at the tolerance; one or two more sweeps
+ *             run past the stop.  FL_STEP_SEPARATE runs a step kernel after
+ *             every sweep instead, the order of sums that batch members
+ *             (fl_batch_step, fl_analyze_batch) use: a plan run that way
+ *             gives its batch results bit for bit.
+ *   reserved  must be 0. */
+#define FL_STEP_SEPARATE 1
 typedef struct {
     double damping;
     double p;
     double tol_l1;
     int32_t max_iter;
     int32_t row_mapping;
+    int32_t flags;
+    int32_t reserved;
 } fl_params;
 
 /* Sizes and results of one analysis. */
@@ -276,7 +293,7 @@ fl_status fl_analyze(fl_ctx *ctx, const fl_space *space, const float *d_fitness_
  * is carved from one array of 64 MiB that the library holds on every device
  * it runs on until the process ends; the call makes no hipMalloc, hipFree
  * or event call and no host heap allocation on success.  Limit: about
- * 20 n_raw + (20 + 8 W) N + 4 E bytes plus small tables must fit in the
+ * 20 n_raw + (28 + 8 W) N + 4 E bytes plus small tables must fit in the
  * 64 MiB (W node-record words): spaces up to about a million raw
  * configurations with tens of millions of edges.  A space whose raw size
  * alone (20 n_raw bytes) exceeds it is rejected with FL_EINVAL before any
@@ -297,7 +314,9 @@ fl_status fl_analyze_noalloc(fl_ctx *ctx, const fl_space *space, const float *d_
  * node-record width of the slot-sweep members, one for the binned members),
  * followed by one launch that finishes the step of every member.  Each member keeps its own damping, tolerance, iteration count and
  * stop flag, and its results equal those of fl_execute with the slot sweep
- * (row_mapping FL_ROWS_SLOTS) bit for bit, whatever else runs in the batch.
+ * (row_mapping FL_ROWS_SLOTS, flags FL_STEP_SEPARATE) bit for bit, whatever
+ * else runs in the batch.  A batch ignores FL_STEP_SEPARATE in the
+ * parameters: its members always take a step kernel per sweep.
  * Members join (fl_batch_add) and leave (fl_batch_collect) between steps.
  * A member reads its plan's FFG and keeps its own iterate vectors (taken
  * from the context's device cache at fl_batch_add, returned when it leaves),
@@ -328,7 +347,8 @@ fl_status fl_batch_destroy(fl_ctx *ctx, fl_batch *batch);
  * sweeps the plan's binned rows (built here with the class's tuned mapping
  * when the plan belongs to this context; a plan of another context must
  * already have them, as plans without slot records do).  Its results equal
- * fl_execute with FL_ROWS_BINNED and the same mapping bit for bit.
+ * fl_execute with FL_ROWS_BINNED, FL_STEP_SEPARATE and the same mapping bit
+ * for bit.
  * Errors: FL_EINVAL (bad parameters, a row_mapping other than 0,
  * FL_ROWS_SLOTS or FL_ROWS_BINNED, FL_ROWS_SLOTS for a space the slot sweep
  * cannot take), FL_ENOMEM, FL_EHIP. */

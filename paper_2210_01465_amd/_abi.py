@@ -21,6 +21,7 @@ FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ENOCONV, FL_EOVERFLOW, FL_EBUSY, FL_ENO
 STATUS_NAMES = {0: "FL_OK", -1: "FL_EINVAL", -2: "FL_ENOMEM", -3: "FL_EHIP", -4: "FL_ENOCONV",
                 -5: "FL_EOVERFLOW", -6: "FL_EBUSY", -7: "FL_ENOTIMPL"}
 FL_NB_HAMMING, FL_NB_ADJACENT = 0, 1
+FL_STEP_SEPARATE = 1
 
 
 class fl_space(ctypes.Structure):
@@ -29,7 +30,8 @@ class fl_space(ctypes.Structure):
 
 class fl_params(ctypes.Structure):
     _fields_ = [("damping", ctypes.c_double), ("p", ctypes.c_double), ("tol_l1", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("row_mapping", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("row_mapping", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class fl_summary(ctypes.Structure):

@@ -166,15 +166,19 @@ def plan_create(ctx: Context, radix, fitness_raw: torch.Tensor, neighbourhood="h
     return Plan(ctx, h, tuple(int(r) for r in radix), sizes.as_dict())
 
 
-def _params(damping, p, tol, max_iter, row_mapping):
-    return _abi.fl_params(float(damping), float(p), float(tol), int(max_iter), int(row_mapping))
+def _params(damping, p, tol, max_iter, row_mapping, separate_step=False):
+    return _abi.fl_params(float(damping), float(p), float(tol), int(max_iter), int(row_mapping),
+                          _abi.FL_STEP_SEPARATE if separate_step else 0, 0)
 
 
 def execute(plan: Plan, damping: float = 0.85, p: float = 0.05, tol: float = 0.0,
             max_iter: int = 0, row_mapping: int = 0, pagerank: torch.Tensor | None = None,
-            minima: torch.Tensor | None = None, allow_noconv: bool = False, exact: bool = False):
+            minima: torch.Tensor | None = None, allow_noconv: bool = False, exact: bool = False,
+            separate_step: bool = False):
     """PageRank, local minima and C_p on a plan (fl_execute; with exact=True
-    fl_execute_exact, which also accepts damping 1).
+    fl_execute_exact, which also accepts damping 1).  separate_step=True
+    (FL_STEP_SEPARATE) runs a step kernel after every sweep, the order of
+    sums a batch uses, instead of the lagged step.
 
     Returns (pagerank float64[N], minima int32[M], summary dict).  Output
     tensors may be passed in (sizes N and M, on the context's device)."""
@@ -190,7 +194,7 @@ def execute(plan: Plan, damping: float = 0.85, p: float = 0.05, tol: float = 0.0
     if (minima.dtype != torch.int32 or minima.numel() < plan.n_minima
             or not minima.is_contiguous() or minima.device != dev):
         raise ValueError("minima must be a contiguous int32 tensor of >= M entries")
-    prm = _params(damping, p, tol, max_iter, row_mapping)
+    prm = _params(damping, p, tol, max_iter, row_mapping, separate_step)
     out = _abi.fl_summary()
     fn = _abi.load().fl_execute_exact if exact else _abi.load().fl_execute
     rc = fn(ctx.handle, plan.handle, ctypes.byref(prm), ctypes.c_void_p(pagerank.data_ptr()),

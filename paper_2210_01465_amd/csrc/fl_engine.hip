@@ -182,8 +182,9 @@ struct fl_plan {
     uint64_t *presence = nullptr;  // per wave of 64 nodes: OR of their slot bits
     fl::SlotTable sl{};
     // power-iteration working set, allocated by the first fl_execute
-    float *y[2] = {nullptr, nullptr};
+    float *y[3] = {nullptr, nullptr, nullptr};   // the third for the lagged step
     float *x[2] = {nullptr, nullptr};
+    float *g = nullptr;         // lagged step: the first sweep's edge sums (node ids)
     int64_t x_cap = 0;          // entries of each x buffer
     double *partials = nullptr;
     PrState *state = nullptr;
@@ -235,8 +236,8 @@ T *pool_alloc(fl_ctx *ctx, int64_t count) {
 void release_plan_buffers(fl_plan *p) {
     DevicePool &pool = p->ctx->pool;
     void *bufs[] = {p->valid_raw, p->out_deg, p->row_ptr, p->col_idx, p->minima,  p->fit_c,
-                    p->rec,       p->presence, p->y[0], p->y[1],      p->x[0],     p->x[1],
-                    p->partials,  p->state,   p->d_off, p->bin_rows};
+                    p->rec,       p->presence, p->y[0], p->y[1],      p->y[2],     p->x[0],
+                    p->x[1],      p->g,       p->partials, p->state,  p->d_off,    p->bin_rows};
     for (void *b : bufs) pool.release(b);
 }
 
@@ -673,6 +674,7 @@ struct Resolved {
     double d, p, tol;
     int32_t max_iter;
     int lanes;  // FL_ROWS_SLOTS or CSR lanes
+    bool lag;   // lagged step (no FL_STEP_SEPARATE)
 };
 
 fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Resolved &r, bool exact = false) {
@@ -682,6 +684,8 @@ fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Re
     if (!(prm->p >= 0.0) || !isfinite(prm->p)) return fail(ctx, FL_EINVAL, "p must be finite and >= 0");
     if (!(prm->tol_l1 >= 0.0) || !isfinite(prm->tol_l1)) return fail(ctx, FL_EINVAL, "tol_l1 must be finite and >= 0");
     if (prm->max_iter < 0) return fail(ctx, FL_EINVAL, "max_iter must be >= 0");
+    if (prm->flags & ~FL_STEP_SEPARATE) return fail(ctx, FL_EINVAL, "unknown flags 0x%x", prm->flags);
+    if (prm->reserved != 0) return fail(ctx, FL_EINVAL, "reserved must be 0");
     if (prm->row_mapping != 0 && !is_slot_layout(prm->row_mapping) && !is_binned_layout(prm->row_mapping) &&
         !valid_lanes(prm->row_mapping))
         return fail(ctx, FL_EINVAL, "row_mapping must be 0, FL_ROWS_SLOTS, FL_ROWS_BINNED or a power of two <= 64");
@@ -694,15 +698,22 @@ fl_status resolve_params(fl_ctx *ctx, const fl_plan *p, const fl_params *prm, Re
     // the exact sweeps settle after (longest path + 1) <= N sweeps
     r.max_iter = prm->max_iter > 0 ? prm->max_iter : (exact ? (int32_t)std::min<int64_t>(p->n + 2, INT32_MAX) : 1000);
     r.lanes = prm->row_mapping ? prm->row_mapping : (p->sl.words > 0 ? FL_ROWS_SLOTS : FL_ROWS_BINNED);
+    r.lag = !(prm->flags & FL_STEP_SEPARATE);
     return FL_OK;
 }
 
-// y, x (x in raw-index space for the slot sweep) and the state of a plan.
-fl_status ensure_pr_buffers(fl_ctx *ctx, fl_plan *p, bool slots) {
+// y, x (x in raw-index space for the slot sweep) and the state of a plan;
+// lag: the third y buffer and g of the lagged step as well.
+fl_status ensure_pr_buffers(fl_ctx *ctx, fl_plan *p, bool slots, bool lag) {
     if (!p->state) {
         for (int j = 0; j < 2; ++j) p->y[j] = pool_alloc<float>(ctx, p->n);
         p->state = pool_alloc<PrState>(ctx, 1);
         if (!p->y[0] || !p->y[1] || !p->state) return fail(ctx, FL_ENOMEM, "device allocation failed");
+    }
+    if (lag && !p->g) {
+        p->y[2] = pool_alloc<float>(ctx, p->n);
+        p->g = pool_alloc<float>(ctx, p->n);
+        if (!p->y[2] || !p->g) return fail(ctx, FL_ENOMEM, "device allocation failed");
     }
     const int64_t x_need = slots ? (p->n_raw + 3) / 4 * 4 : p->n;   // raw-index space, whole 16-byte groups
     if (x_need > p->x_cap) {
@@ -784,12 +795,13 @@ fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrAr
     const int64_t groups = kind == fl::kSweepBinned ? std::max<int64_t>(p->bins.tiles, 1)
                                                     : (p->n + rows_per_wg - 1) / rows_per_wg;
     grid = (int)std::min<int64_t>(resident, (groups + fl::kXcds - 1) / fl::kXcds * fl::kXcds);
-    fl_status st = ensure_pr_buffers(ctx, p, kind == fl::kSweepSlots);
+    fl_status st = ensure_pr_buffers(ctx, p, kind == fl::kSweepSlots, r.lag);
     if (st != FL_OK) return st;
-    // partial sums: one triple per tile (init, slot sweep) or per workgroup (CSR sweep)
+    // partial sums: one triple per tile (init, slot sweep) or per workgroup
+    // (CSR sweep, lagged step: two buffers of them)
     const int32_t n_tiles = tiles_of(p);
     init_grid = (int)std::min<int64_t>(n_tiles, (int64_t)ctx->num_cus * 4);
-    st = ensure_partials(ctx, p, std::max<int64_t>(std::max(grid, n_tiles), p->have_bins ? p->bins.tiles : 0));
+    st = ensure_partials(ctx, p, std::max<int64_t>(std::max<int64_t>(2 * (int64_t)grid, n_tiles), p->have_bins ? p->bins.tiles : 0));
     if (st != FL_OK) return st;
     a.row_ptr = p->row_ptr;
     a.col_idx = p->col_idx;
@@ -802,6 +814,13 @@ fl_status prepare_pr(fl_ctx *ctx, fl_plan *p, const Resolved &r, int lanes, PrAr
     a.k_slots = p->sl.k;
     a.y[0] = p->y[0];
     a.y[1] = p->y[1];
+    a.y[2] = p->y[2];
+    a.g = p->g;
+    a.lag = r.lag ? 1 : 0;
+    a.sweep = 0;
+    a.n_parts = grid;
+    a.part_stride = grid;
+    a.n_sinks = p->m;
     a.x[0] = p->x[0];
     a.x[1] = p->x[1];
     a.partials = p->partials;
@@ -1155,9 +1174,14 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
 
     // Launch the iteration kernel in chunks; a launch after convergence exits
     // at once.  The chunk length follows the observed residual decay so that
-    // few host round trips and few empty launches are needed.
+    // few host round trips and few empty launches are needed.  With the
+    // lagged step the sweeps alone are launched, and the step of iteration k
+    // runs in sweep k + 1 (k + 2 for the power iteration, whose residual is
+    // one sweep late as well): the sweep after the cap's last iteration does
+    // only that step, and sets the stop flag.
     int launches = 0;
     int chunk = 16;
+    const int64_t limit = r.lag ? (int64_t)r.max_iter + (exact ? 1 : 2) : INT64_MAX;
     double iterate_ms = 0.0, sweep_ms = 0.0;
     PrState *hs = ctx->h_state;
     int sampled = 0;
@@ -1172,6 +1196,7 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
         if (timed) FL_HIP(hipEventRecord(p->ev[5], s));
         for (int j = 0; j < chunk; ++j) {
             const bool sampled_here = profile_every > 0 && (launches + j) % profile_every == 0;
+            a.sweep = launches + j;
             if (sampled_here) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j], s));
             FL_HIP(fl::launch_pr_sweep(a, p->sl, lanes, grid, s));
             if (sampled_here) FL_HIP(hipEventRecord(ctx->sweep_ev[2 * j + 1], s));
@@ -1190,6 +1215,7 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
                     ++sampled;
                 }
         if (hs->done) break;
+        if (launches >= limit) return fail(ctx, FL_EHIP, "the iteration did not stop after %d sweeps", launches);
         const double rate = (hs->resid_prev > 0.0) ? hs->resid / hs->resid_prev : 1.0;
         if (exact) {
             chunk = 64;   // the sweeps end abruptly (exact fixed point): no decay to follow
@@ -1200,6 +1226,7 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
             chunk = 8;
         }
         chunk = std::min(chunk, std::max(1, r.max_iter - hs->k));
+        if (r.lag) chunk = (int)std::min<int64_t>(chunk, limit - launches);
     }
     if (timed) FL_HIP(hipEventRecord(p->ev[3], s));
     FL_HIP(fl::launch_pr_output(a, d_pagerank, s));
@@ -1536,9 +1563,15 @@ fl_status fl_tune(fl_ctx *ctx, fl_plan *p, const fl_params *prm, int32_t sweeps,
         if (st != FL_OK) return st;
         FL_HIP(hipMemsetAsync(p->state, 0, sizeof(PrState), s));
         FL_HIP(fl::launch_pr_init(a, init_grid, s));
+        // an iteration as fl_execute runs it: sweep and step kernel, or one
+        // sweep with the lagged step (the warm-up sweep 0 writes its g)
+        a.sweep = 0;
         FL_HIP(fl::launch_pr_iter(a, p->sp, p->sl, lanes, grid, s));  // warm-up sweep
         FL_HIP(hipEventRecord(p->ev[5], s));
-        for (int32_t q = 0; q < sweeps; ++q) FL_HIP(fl::launch_pr_iter(a, p->sp, p->sl, lanes, grid, s));
+        for (int32_t q = 0; q < sweeps; ++q) {
+            a.sweep = q + 1;
+            FL_HIP(fl::launch_pr_iter(a, p->sp, p->sl, lanes, grid, s));
+        }
         FL_HIP(hipEventRecord(p->ev[6], s));
         FL_HIP(hipStreamSynchronize(s));
         const double us = 1e3 * elapsed(p->ev[5], p->ev[6]) / sweeps;

@@ -112,6 +112,15 @@ struct PrState {
     double sink;         // sum of y_k over sinks
     double score_num;    // sum of ranks over L_p
     double score_den;    // sum of ranks over L
+    // Lagged step (PrArgs::lag): sweep j adds the teleport-and-sink term of
+    // r_{j-1}, gam[j & 1][0], and the residual of r_j against r_{j-1} uses
+    // gam[j & 1][1] as well (the term of r_{j-2}); the result is the iterate
+    // r = w + out_gamma in y buffer out_buf, whose entries sum to out_sigma.
+    double gam[2][2];
+    double out_gamma;
+    double out_sigma;
+    int32_t out_buf;
+    int32_t lag_pad;
 };
 
 // Row formats of the PageRank sweep.
@@ -158,7 +167,7 @@ struct PrArgs {
                             // then the byte offsets 4 (off[s] - off[0]) of the buffer-load sweep
     int32_t k_slots;
     int32_t k_pad;          // stride of off's two halves: k_slots rounded up to 64, plus 64
-    float *y[2];            // ping-pong iterate (node ids), slot k&1 holds y_k
+    float *y[3];            // iterate (node ids): y[k & 1] holds y_k; lagged step: y[j % 3] holds w_j
     float *x[2];            // y / out_deg (0 at sinks): node ids (CSR) or raw indices (slots)
     double *partials;       // 3 doubles per tile (slot sweep) or per workgroup (CSR sweep)
     PrState *st;
@@ -173,6 +182,23 @@ struct PrArgs {
     int32_t exact;          // 1: Jacobi sweeps u <- 1 + d P u to an exact fixed point (s = c = 1)
     const int32_t *bin_rows;  // binned sweep: node ids grouped by class
     BinTable bins;            // binned sweep: classes and tiles
+    // Lagged step (lag != 0): the sweeps run back to back with no step
+    // kernel.  Sweep j (the host passes j in `sweep`) writes one partial
+    // triple per workgroup, as three arrays of part_stride doubles, to
+    // buffer j & 1 of `partials`; its workgroup 0 first reduces the n_parts
+    // triples sweep j - 1 wrote into the state that sweep j + 1 reads.
+    // The stored iterate w_j leaves out the constant teleport-and-sink term
+    // gamma_{j-1} of r_j = w_j + gamma_{j-1}, which only the next step
+    // knows; g (node ids) holds the in-edge sums of the first sweep, whose
+    // x is r_0 / out_deg with r_0 = y0 = 1/N everywhere, so g / y0 is
+    // P^T D^-1 1 and gamma_{j-1} g / y0 is what the constant contributes to
+    // the next edge sums.
+    int32_t lag;
+    int32_t sweep;
+    int32_t n_parts;
+    int32_t part_stride;
+    int64_t n_sinks;
+    float *g;
 };
 
 // One member of a batch: an FFG with its own power iteration, run together
@@ -250,7 +276,7 @@ hipError_t launch_bin_rows(const int32_t *row_ptr, int32_t n, const int8_t *clas
 // One binned sweep restricted to the given table (the autotuner times one
 // class at a time this way), without the step kernel.
 hipError_t launch_pr_sweep_binned(const PrArgs &a, const BinTable &t, int grid, hipStream_t stream);
-hipError_t pr_binned_blocks_per_cu(int *blocks);
+hipError_t pr_binned_blocks_per_cu(int *blocks, bool lag = false);
 hipError_t launch_batch_sweep_binned(const BatchMember *members, const TileRef *tiles, const int32_t *range_dev,
                                      int grid, hipStream_t stream);
 hipError_t batch_sweep_binned_blocks_per_cu(int *blocks);

@@ -821,6 +821,16 @@ __device__ void finish_step(PrState *st, const double *__restrict__ partials, in
     double s1 = c0 == 1 ? r[0] : (c0 == 0 ? r[1] : r[2]);
     double s2 = c0 == 2 ? r[0] : (c0 == 1 ? r[1] : r[2]);
     block_sum3<B>(s0, s1, s2);
+    if (first && threadIdx.x == 0) {
+        // lagged step: r_0 = w_0 (no constant term), so sweep 0 adds nothing
+        // and sweep 1 adds gamma_0 = (d sink(r_0) + 1 - d) / N
+        st->gam[0][0] = st->gam[0][1] = 0.0;
+        st->gam[1][0] = exact ? 0.0 : (d * s2 + (1.0 - d)) / (double)n;
+        st->gam[1][1] = 0.0;
+        st->out_buf = 0;
+        st->out_gamma = 0.0;
+        st->out_sigma = s0;
+    }
     if (exact && threadIdx.x == 0) {
         // Jacobi sweeps y' = d P y + 1 (the sweep computes s d acc + c with
         // s = c = 1); a sweep that changes no value ends them, and s then
@@ -881,6 +891,164 @@ __global__ __launch_bounds__(kFinishBlock) void k_pr_finish(PrArgs a, int32_t co
     finish_step(a.st, a.partials, count, a.d, a.tol, a.max_iter, a.n, FIRST, a.exact != 0);
 }
 
+// ---------------------------------------------------------------------------
+// Lagged step.  With the plain power iteration, the step kernel between two
+// sweeps costs about a fifth of an iteration at the large workload, mostly
+// the fixed cost of a launch.  In the lagged form every sweep runs straight
+// after the previous one, and its workgroup 0 first does the step of the
+// sweep before.  A sweep therefore cannot know the constant term of its own
+// input r_j = w_j + gamma_{j-1}, gamma = (d sink(r) + 1 - d) / N being a
+// reduction over that input, nor the residual of r_j, which needs
+// gamma_{j-1} as well.  It stores w_{j+1} = d (P^T D^-1 w_j + gamma_{j-1}
+// P^T D^-1 1) without its constant, P^T D^-1 1 coming from the first
+// sweep's edge sums (PrArgs::g), and adds the residual of r_j against
+// r_{j-1} from the stored w_j and w_{j-1}.  The iterates are those of the
+// plain iteration in exact arithmetic; the stop is seen one sweep later.
+
+// Workgroup 0 of sweep j >= 1: reduce the partial triples of sweep j - 1
+// in a fixed order (thread t sums parts t, t + kBlock, ...; then a fixed
+// tree) and do its step.  Sweep j - 1 wrote sum w_j, the residual
+// |r_{j-1} - r_{j-2}| (zero for j = 1) and the sink part of sum w_j; for
+// the exact method, sum y_j, |y_j - y_{j-1}| and the sink part.
+__device__ void lag_step(const PrArgs &a) {
+    const int32_t j = a.sweep;
+    const int64_t stride = a.part_stride;
+    const double *__restrict__ p = a.partials + (int64_t)((j - 1) & 1) * 3 * stride;
+    constexpr int kU = 8;   // 24 loads in flight: one round covers 2048 workgroups
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+    for (int32_t i0 = 0; i0 < a.n_parts; i0 += kU * kBlock) {
+        double v[3][kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int32_t i = i0 + u * kBlock + (int32_t)threadIdx.x;
+            const bool ok = i < a.n_parts;
+            v[0][u] = ok ? p[i] : 0.0;
+            v[1][u] = ok ? p[stride + i] : 0.0;
+            v[2][u] = ok ? p[2 * stride + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            r0 += v[0][u];
+            r1 += v[1][u];
+            r2 += v[2][u];
+        }
+    }
+    block_sum3(r0, r1, r2);
+    if (threadIdx.x != 0) return;
+    PrState *st = a.st;
+    if (a.exact) {
+        // y_j is final once a sweep changed nothing
+        st->resid_prev = st->resid;
+        st->resid = r1;
+        st->k = j;
+        st->worked = j;
+        st->sigma = r0;
+        st->sink = r2;
+        if (r1 == 0.0)
+            st->done = 1;
+        else if (j >= a.max_iter)
+            st->done = 2;
+        if (st->done) {
+            st->out_buf = j % 3;
+            st->out_gamma = 0.0;
+            st->out_sigma = r0;
+        }
+        return;
+    }
+    const double ga = st->gam[j & 1][0], gb = st->gam[j & 1][1];   // gamma_{j-1}, gamma_{j-2}
+    const double n = (double)a.n;
+    const double sig = r0 + n * ga;                        // sum of r_j
+    const double sink = r2 + (double)a.n_sinks * ga;       // sink mass of r_j
+    if (j >= 2) {
+        st->resid_prev = st->resid;
+        st->resid = r1;
+        st->k = j - 1;
+        st->worked = j - 1;
+        if (r1 < a.tol)
+            st->done = 1;
+        else if (j - 1 >= a.max_iter)
+            st->done = 2;
+        if (st->done) {
+            // r_{j-1} = w_{j-1} + gamma_{j-2}, summed by the previous step
+            st->out_buf = (j - 1) % 3;
+            st->out_gamma = gb;
+            st->out_sigma = st->sigma;
+        }
+    }
+    st->gam[(j + 1) & 1][0] = (a.d * sink + (1.0 - a.d)) / n;   // gamma_j
+    st->gam[(j + 1) & 1][1] = ga;
+    st->sigma = sig;
+    st->sink = sink;
+}
+
+// One partial triple per workgroup (lagged step), to buffer sweep & 1.
+__device__ __forceinline__ void write_lag_partials(const PrArgs &a, double ps, double pr, double pk) {
+    block_sum3(ps, pr, pk);
+    if (threadIdx.x == 0) {
+        const int64_t stride = a.part_stride;
+        double *pp = a.partials + (int64_t)(a.sweep & 1) * 3 * stride + blockIdx.x;
+        pp[0] = ps;
+        pp[stride] = pr;
+        pp[2 * stride] = pk;
+    }
+}
+
+// What a lagged sweep needs besides its iterate: the constant terms
+// gamma_{j-1} (ga) and gamma_{j-2} (gb), ga / y0 (gs), and the mode.
+enum LagMode : int32_t { kLagFirst = 0, kLagNext = 1, kLagExact = 2 };
+struct LagTerms {
+    const float *y_prev;   // w_{j-1}
+    float *g;              // P^T D^-1 1 times y0 (written by the first sweep)
+    double ga, gb, gs, d;
+    int32_t mode;
+};
+
+__device__ __forceinline__ LagTerms lag_terms(const PrArgs &a) {
+    LagTerms t;
+    const int32_t j = a.sweep;
+    t.y_prev = a.y[(j + 2) % 3];
+    t.g = a.g;
+    t.d = a.d;
+    t.mode = a.exact ? kLagExact : (j == 0 ? kLagFirst : kLagNext);
+    const PrState *st = a.st;
+    t.ga = st->gam[j & 1][0];
+    t.gb = st->gam[j & 1][1];
+    const double y0 = (double)(float)(1.0 / (double)a.n);
+    t.gs = t.ga / y0;
+    return t;
+}
+
+// Whether a lagged sweep has node work: the sweep after the last iteration
+// the cap allows only does the step of the one before.
+__device__ __forceinline__ bool lag_has_tiles(const PrArgs &a) {
+    return a.sweep <= a.max_iter - (a.exact ? 1 : 0);
+}
+
+// The new value of node v in a lagged sweep from its edge sum acc, its terms
+// of the three partial sums, and (first sweep) its entry of g.  yin = w_j[v],
+// yprev = w_{j-1}[v] and gv = g[v] are loaded by the caller in every mode
+// (uninitialised in the modes that do not use them: not read here).
+__device__ __forceinline__ float lag_node(const LagTerms &t, int32_t v, float acc, float yin, float yprev, float gv,
+                                          int32_t deg, double &ps, double &pr, double &pk) {
+    double w;
+    if (t.mode == kLagExact)
+        w = t.d * (double)acc + 1.0;
+    else if (t.mode == kLagFirst)
+        w = t.d * (double)acc;
+    else
+        w = t.d * ((double)acc + t.gs * (double)gv);
+    const float yf = (float)w;
+    ps += (double)yf;
+    if (t.mode == kLagExact)
+        pr += fabs((double)yf - (double)yin);
+    else if (t.mode == kLagNext)
+        pr += fabs(((double)yin + t.ga) - ((double)yprev + t.gb));
+    else
+        t.g[v] = acc;
+    if (deg == 0) pk += (double)yf;
+    return yf;
+}
+
 // Initial iterate r = 1/N of one tile of kBlock nodes, with its partial sums.
 __device__ __forceinline__ void init_tile(int32_t tile, int32_t n, const int32_t *__restrict__ out_deg,
                                           const int32_t *__restrict__ xmap, float *y0v, float *x0v,
@@ -936,18 +1104,25 @@ __device__ __forceinline__ void pr_node_update(const PrArgs &a, int32_t v, int32
 
 // CSR sweep, L lanes per row: the lanes of a row read consecutive col_idx
 // entries (four rounds of loads in flight) and reduce with shuffles.
-template <int L>
+// LAG: the lagged step (see lag_step).
+template <int L, bool LAG>
 __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
     const PrState *st = a.st;
     if (st->done) return;
-    const int32_t k = st->k;
-    const float *__restrict__ y_in = a.y[k & 1];
+    if (LAG) {
+        if (blockIdx.x == 0 && a.sweep >= 1) lag_step(a);
+        if (!lag_has_tiles(a)) return;
+    }
+    const int32_t k = LAG ? a.sweep : st->k;
+    const float *__restrict__ y_in = a.y[LAG ? k % 3 : k & 1];
     const float *__restrict__ x_in = a.x[k & 1];
-    float *__restrict__ y_out = a.y[(k + 1) & 1];
+    float *__restrict__ y_out = a.y[LAG ? (k + 1) % 3 : (k + 1) & 1];
     float *__restrict__ x_out = a.x[(k + 1) & 1];
+    LagTerms lt{};
+    if (LAG) lt = lag_terms(a);
     const int32_t *__restrict__ row_ptr = a.row_ptr;
     const int32_t *__restrict__ col_idx = a.col_idx;
-    const double s = st->s, c = st->c;
+    const double s = LAG ? 1.0 : st->s, c = LAG ? 0.0 : st->c;
     const double sd = s * a.d;
     constexpr int kRows = kBlock / L;
     const int lane = threadIdx.x % L;
@@ -957,6 +1132,15 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
     for (int32_t t = w.first; t < w.end; t += w.step) {
         const int32_t v = t * kRows + sub;
         float acc = 0.0f;
+        // lagged step: the row's own values, loaded ahead of its gathers
+        int32_t deg = 0;
+        float yin = 0.0f, yprev = 0.0f, gv = 0.0f;
+        if (LAG && lane == 0 && v < a.n) {
+            deg = a.out_deg[v];
+            yin = y_in[v];
+            yprev = lt.y_prev[v];
+            gv = lt.g[v];
+        }
         if (v < a.n) {
             const int32_t e1 = row_ptr[v + 1];
             for (int32_t e = row_ptr[v] + lane; e < e1; e += 4 * L) {
@@ -972,9 +1156,20 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
         }
 #pragma unroll
         for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lane == 0 && v < a.n) pr_node_update(a, v, v, acc, sd, c, s, y_in, y_out, x_out, ps, pr, pk);
+        if (lane == 0 && v < a.n) {
+            if (LAG) {
+                const float yf = lag_node(lt, v, acc, yin, yprev, gv, deg, ps, pr, pk);
+                y_out[v] = yf;
+                x_out[v] = deg > 0 ? yf / (float)deg : 0.0f;
+            } else {
+                pr_node_update(a, v, v, acc, sd, c, s, y_in, y_out, x_out, ps, pr, pk);
+            }
+        }
     }
-    write_partials(a.partials, blockIdx.x, ps, pr, pk);
+    if (LAG)
+        write_lag_partials(a, ps, pr, pk);
+    else
+        write_partials(a.partials, blockIdx.x, ps, pr, pk);
 }
 
 
@@ -989,9 +1184,10 @@ struct BinSweep {
     const float *y_in, *x_in;
     float *y_out, *x_out;
     double s, c, sd;
+    LagTerms lt;   // lagged step only
 };
 
-template <int L>
+template <int L, bool LAG>
 __device__ __forceinline__ void binned_block(const BinSweep &q, int32_t first, int32_t count, double &ps,
                                              double &pr, double &pk) {
     const int lane = threadIdx.x % L;
@@ -999,6 +1195,15 @@ __device__ __forceinline__ void binned_block(const BinSweep &q, int32_t first, i
     const bool live = r < count;
     const int32_t v = live ? q.rows[r] : 0;
     float acc = 0.0f;
+    // lagged step: the row's own values, loaded ahead of its gathers
+    int32_t ldeg = 0;
+    float yin = 0.0f, yprev = 0.0f, gv = 0.0f;
+    if (LAG && lane == 0 && live) {
+        ldeg = q.out_deg[v];
+        yin = q.y_in[v];
+        yprev = q.lt.y_prev[v];
+        gv = q.lt.g[v];
+    }
     if (live) {
         const int32_t e1 = q.row_ptr[v + 1];
         for (int32_t e = q.row_ptr[v] + lane; e < e1; e += 4 * L) {
@@ -1015,19 +1220,26 @@ __device__ __forceinline__ void binned_block(const BinSweep &q, int32_t first, i
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0 && live) {
-        const float yf = (float)(q.sd * (double)acc + q.c);
-        const int32_t deg = q.out_deg[v];
-        q.y_out[v] = yf;
-        q.x_out[v] = deg > 0 ? yf / (float)deg : 0.0f;
-        ps += (double)yf;
-        pr += fabs((double)yf - q.s * (double)q.y_in[v]);
-        if (deg == 0) pk += (double)yf;
+        if (LAG) {
+            const float yf = lag_node(q.lt, v, acc, yin, yprev, gv, ldeg, ps, pr, pk);
+            q.y_out[v] = yf;
+            q.x_out[v] = ldeg > 0 ? yf / (float)ldeg : 0.0f;
+        } else {
+            const int32_t deg = q.out_deg[v];
+            const float yf = (float)(q.sd * (double)acc + q.c);
+            q.y_out[v] = yf;
+            q.x_out[v] = deg > 0 ? yf / (float)deg : 0.0f;
+            ps += (double)yf;
+            pr += fabs((double)yf - q.s * (double)q.y_in[v]);
+            if (deg == 0) pk += (double)yf;
+        }
     }
 }
 
-// Tile t (0 <= t < table.tiles) of a binned sweep: its class, then T blocks.
-// The table is read in place (kernel arguments or the member table) through
-// the scalar unit.
+// Tile t (0 <= t < table.tiles) of a binned sweep: its class, then T blocks,
+// their terms added to ps, pr, pk.  The table is read in place (kernel
+// arguments or the member table) through the scalar unit.
+template <bool LAG>
 __device__ __forceinline__ void binned_tile(const BinSweep &q0, const_ptr<BinTable> tb, int32_t t, double &ps,
                                             double &pr, double &pk) {
     int cl = 0;
@@ -1039,39 +1251,48 @@ __device__ __forceinline__ void binned_tile(const BinSweep &q0, const_ptr<BinTab
     BinSweep q = q0;
     q.rows = q0.rows + c->row_begin;
     const int32_t lt = t - c->tile_begin;
-    ps = pr = pk = 0.0;
     for (int b = 0; b < blocks; ++b) {
         const int32_t first = (lt * blocks + b) * (kBlock / lanes);
         switch (lanes) {
-            case 1: binned_block<1>(q, first, rows, ps, pr, pk); break;
-            case 2: binned_block<2>(q, first, rows, ps, pr, pk); break;
-            case 4: binned_block<4>(q, first, rows, ps, pr, pk); break;
-            case 8: binned_block<8>(q, first, rows, ps, pr, pk); break;
-            case 16: binned_block<16>(q, first, rows, ps, pr, pk); break;
-            case 32: binned_block<32>(q, first, rows, ps, pr, pk); break;
-            default: binned_block<64>(q, first, rows, ps, pr, pk); break;
+            case 1: binned_block<1, LAG>(q, first, rows, ps, pr, pk); break;
+            case 2: binned_block<2, LAG>(q, first, rows, ps, pr, pk); break;
+            case 4: binned_block<4, LAG>(q, first, rows, ps, pr, pk); break;
+            case 8: binned_block<8, LAG>(q, first, rows, ps, pr, pk); break;
+            case 16: binned_block<16, LAG>(q, first, rows, ps, pr, pk); break;
+            case 32: binned_block<32, LAG>(q, first, rows, ps, pr, pk); break;
+            default: binned_block<64, LAG>(q, first, rows, ps, pr, pk); break;
         }
     }
 }
 
 // The binned sweep over the tiles of a.bins (the plan's whole table, or a
-// part of it while the autotuner times one class).
+// part of it while the autotuner times one class).  LAG: the lagged step.
+template <bool LAG>
 __global__ __launch_bounds__(kBlock) void k_pr_iter_binned(PrArgs a) {
     const PrState *st = a.st;
     if (st->done) return;
-    const int32_t k = st->k;
+    if (LAG) {
+        if (blockIdx.x == 0 && a.sweep >= 1) lag_step(a);
+        if (!lag_has_tiles(a)) return;
+    }
+    const int32_t k = LAG ? a.sweep : st->k;
     BinSweep q;
     q.row_ptr = a.row_ptr;
     q.col_idx = a.col_idx;
     q.out_deg = a.out_deg;
     q.rows = a.bin_rows;
-    q.y_in = a.y[k & 1];
+    q.y_in = a.y[LAG ? k % 3 : k & 1];
     q.x_in = a.x[k & 1];
-    q.y_out = a.y[(k + 1) & 1];
+    q.y_out = a.y[LAG ? (k + 1) % 3 : (k + 1) & 1];
     q.x_out = a.x[(k + 1) & 1];
-    q.s = st->s;
-    q.c = st->c;
-    q.sd = q.s * a.d;
+    if (LAG) {
+        q.s = q.c = q.sd = 0.0;
+        q.lt = lag_terms(a);
+    } else {
+        q.s = st->s;
+        q.c = st->c;
+        q.sd = q.s * a.d;
+    }
     // Every class's tiles are dealt to the XCDs in eighths, XCD j taking the
     // j-th eighth of each class in turn: a class's rows ascend in node id,
     // so an XCD works in about the j-th eighth of the nodes whatever the
@@ -1079,17 +1300,23 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_binned(PrArgs a) {
     const const_ptr<BinTable> tb = &kernel_arg<PrArgs>()->bins;
     const int xcd = blockIdx.x % kXcds, nb = gridDim.x / kXcds, l = blockIdx.x / kXcds;
     const int nc = tb->n_classes;
+    double ws = 0.0, wr = 0.0, wk = 0.0;   // lagged step: the workgroup's sums
     for (int cl = 0; cl < nc; ++cl) {
         const int32_t t0 = tb->c[cl].tile_begin;
         const int32_t ct = (cl + 1 < nc ? tb->c[cl + 1].tile_begin : a.bins.tiles) - t0;
         const int32_t per = (ct + kXcds - 1) / kXcds;
         const int32_t lo = t0 + per * xcd, hi = t0 + min(per * (xcd + 1), ct);
         for (int32_t t = lo + l; t < hi; t += nb) {
-            double ps, pr, pk;
-            binned_tile(q, tb, t, ps, pr, pk);
-            write_partials(a.partials, t, ps, pr, pk);
+            if (LAG) {
+                binned_tile<true>(q, tb, t, ws, wr, wk);
+            } else {
+                double ps = 0.0, pr = 0.0, pk = 0.0;
+                binned_tile<false>(q, tb, t, ps, pr, pk);
+                write_partials(a.partials, t, ps, pr, pk);
+            }
         }
     }
+    if (LAG) write_lag_partials(a, ws, wr, wk);
 }
 
 // Binning of the rows: per node tile, the number of rows of each class;
@@ -1177,6 +1404,7 @@ struct SweepTile {
     double *partials;
     double s, c, sd;
     int32_t n, k_slots, k_pad, x_bytes;
+    LagTerms lt;   // lagged step only
 };
 
 // Slots per batch of the slot sweep.  All loads of a batch are issued before
@@ -1188,8 +1416,9 @@ struct SweepTile {
 constexpr int kSweepBatch = 48;
 
 // The node of lane lt (0 <= lt < kBlock) of the tile: its new value, and its
-// terms of the tile's three partial sums in ps, pr, pk (reduced by the caller).
-template <int W, bool BUF>
+// terms of the tile's three partial sums in ps, pr, pk (reduced by the
+// caller).  LAG (the lagged step): the terms are added to ps, pr, pk.
+template <int W, bool BUF, bool LAG = false>
 __device__ __forceinline__ void sweep_tile_sums(const SweepTile &q, int32_t tile, int lt, double &ps, double &pr,
                                                 double &pk) {
     // descriptor based at x_in + off[0] (<= x_in), so every slot's byte offset
@@ -1200,10 +1429,18 @@ __device__ __forceinline__ void sweep_tile_sums(const SweepTile &q, int32_t tile
     const int32_t v = tile * kBlock + lt;
     const bool active = v < q.n;
     Record<W> r;
-    float yin = 0.0f;
+    float yin = 0.0f, yprev = 0.0f, gv = 0.0f;
     if (active) {
         r = load_record<W>(q.rec, v);
+        // the node's own values are loaded with the record, ahead of the
+        // gathers, so that their latency hides behind them; in every mode,
+        // since loads under a branch on the mode make the compiler wait for
+        // them before the gathers (8 us more per sweep at the large workload)
         yin = q.y_in[v];
+        if (LAG) {
+            yprev = q.lt.y_prev[v];
+            gv = q.lt.g[v];
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < W; ++j) r.w[j] = 0ull;
@@ -1262,6 +1499,15 @@ __device__ __forceinline__ void sweep_tile_sums(const SweepTile &q, int32_t tile
 #pragma unroll
         for (int u = 0; u < kB; ++u) acc += val[u];
     }
+    if (LAG) {
+        if (active) {
+            const int32_t deg = r.out_deg();
+            const float yf = lag_node(q.lt, v, acc, yin, yprev, gv, deg, ps, pr, pk);
+            q.y_out[v] = yf;
+            q.x_out[i] = deg > 0 ? yf / (float)deg : 0.0f;
+        }
+        return;
+    }
     ps = pr = pk = 0.0;
     if (active) {
         const float yf = (float)(q.sd * (double)acc + q.c);
@@ -1280,28 +1526,62 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
     write_partials(q.partials, tile, ps, pr, pk);
 }
 
-template <int W, bool BUF>
+// LAG: the lagged step (see lag_step); the workgroup's terms make one triple,
+// summed per tile by the fixed tree and over its tiles in order by thread 0
+// in LDS, so that no FP64 sums stay live in registers across the gathers.
+template <int W, bool BUF, bool LAG>
 __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     const PrState *st = a.st;
     if (st->done) return;
-    const int32_t k = st->k;
+    if (LAG) {
+        if (blockIdx.x == 0 && a.sweep >= 1) lag_step(a);
+        if (!lag_has_tiles(a)) return;
+    }
+    const int32_t k = LAG ? a.sweep : st->k;
     SweepTile q;
     q.rec = a.rec;
     q.off = to_const(a.off);
-    q.y_in = a.y[k & 1];
+    q.y_in = a.y[LAG ? k % 3 : k & 1];
     q.x_in = a.x[k & 1];
-    q.y_out = a.y[(k + 1) & 1];
+    q.y_out = a.y[LAG ? (k + 1) % 3 : (k + 1) & 1];
     q.x_out = a.x[(k + 1) & 1];
     q.partials = a.partials;
-    q.s = st->s;
-    q.c = st->c;
-    q.sd = q.s * a.d;
+    if (LAG) {
+        q.s = q.c = q.sd = 0.0;
+        q.lt = lag_terms(a);
+    } else {
+        q.s = st->s;
+        q.c = st->c;
+        q.sd = q.s * a.d;
+    }
     q.n = a.n;
     q.k_slots = a.k_slots;
     q.k_pad = a.k_pad;
     q.x_bytes = a.x_bytes;
     const TileWalk w((a.n + kBlock - 1) / kBlock);
-    for (int32_t t = w.first; t < w.end; t += w.step) sweep_tile<W, BUF>(q, t);
+    if (LAG) {
+        __shared__ double sums[3];
+        if (threadIdx.x == 0) sums[0] = sums[1] = sums[2] = 0.0;
+        for (int32_t t = w.first; t < w.end; t += w.step) {
+            double ps = 0.0, pr = 0.0, pk = 0.0;
+            sweep_tile_sums<W, BUF, true>(q, t, (int)threadIdx.x, ps, pr, pk);
+            block_sum3(ps, pr, pk);
+            if (threadIdx.x == 0) {
+                sums[0] += ps;
+                sums[1] += pr;
+                sums[2] += pk;
+            }
+        }
+        if (threadIdx.x == 0) {
+            const int64_t stride = a.part_stride;
+            double *pp = a.partials + (int64_t)(a.sweep & 1) * 3 * stride + blockIdx.x;
+            pp[0] = sums[0];
+            pp[stride] = sums[1];
+            pp[2 * stride] = sums[2];
+        }
+    } else {
+        for (int32_t t = w.first; t < w.end; t += w.step) sweep_tile<W, BUF>(q, t);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1371,8 +1651,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_sweep_binned(const BatchMember
         q.s = st->s;
         q.c = st->c;
         q.sd = q.s * m->d;
-        double ps, pr, pk;
-        binned_tile(q, &m->bins, tile, ps, pr, pk);
+        double ps = 0.0, pr = 0.0, pk = 0.0;
+        binned_tile<false>(q, &m->bins, tile, ps, pr, pk);
         write_partials(m->partials, tile, ps, pr, pk);
     }
 }
@@ -1570,6 +1850,14 @@ __global__ void k_batch_states(const BatchMember *__restrict__ members, const in
 
 __global__ __launch_bounds__(kBlock) void k_pr_output(PrArgs a, double *__restrict__ pagerank) {
     const PrState *st = a.st;
+    if (a.lag) {
+        // r = w + gamma, scaled to sum 1
+        const float *__restrict__ y = a.y[st->out_buf];
+        const double g = st->out_gamma, s = 1.0 / st->out_sigma;
+        for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += gridDim.x * kBlock)
+            pagerank[v] = ((double)y[v] + g) * s;
+        return;
+    }
     const float *__restrict__ y = a.y[st->k & 1];
     const double s = st->s;
     for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += gridDim.x * kBlock)
@@ -1602,7 +1890,9 @@ __global__ __launch_bounds__(kBlock) void k_score(const double *__restrict__ pag
 // when the x vector's byte size leaves room for the out-of-range offset.
 template <int W>
 const void *slot_sweep_fn(const PrArgs &a) {
-    return a.x_bytes > 0 ? (const void *)k_pr_iter_slots<W, true> : (const void *)k_pr_iter_slots<W, false>;
+    if (a.lag)
+        return a.x_bytes > 0 ? (const void *)k_pr_iter_slots<W, true, true> : (const void *)k_pr_iter_slots<W, false, true>;
+    return a.x_bytes > 0 ? (const void *)k_pr_iter_slots<W, true, false> : (const void *)k_pr_iter_slots<W, false, false>;
 }
 
 const void *slot_sweep_kernel(const PrArgs &a, int words) {
@@ -1616,17 +1906,26 @@ const void *slot_sweep_kernel(const PrArgs &a, int words) {
     }
 }
 
-const void *csr_sweep_kernel(int lanes) {
+template <bool LAG>
+const void *csr_sweep_fn(int lanes) {
     switch (lanes) {
-        case 1: return (const void *)k_pr_iter_csr<1>;
-        case 2: return (const void *)k_pr_iter_csr<2>;
-        case 4: return (const void *)k_pr_iter_csr<4>;
-        case 8: return (const void *)k_pr_iter_csr<8>;
-        case 16: return (const void *)k_pr_iter_csr<16>;
-        case 32: return (const void *)k_pr_iter_csr<32>;
-        case 64: return (const void *)k_pr_iter_csr<64>;
+        case 1: return (const void *)k_pr_iter_csr<1, LAG>;
+        case 2: return (const void *)k_pr_iter_csr<2, LAG>;
+        case 4: return (const void *)k_pr_iter_csr<4, LAG>;
+        case 8: return (const void *)k_pr_iter_csr<8, LAG>;
+        case 16: return (const void *)k_pr_iter_csr<16, LAG>;
+        case 32: return (const void *)k_pr_iter_csr<32, LAG>;
+        case 64: return (const void *)k_pr_iter_csr<64, LAG>;
         default: return nullptr;
     }
+}
+
+const void *csr_sweep_kernel(const PrArgs &a, int lanes) {
+    return a.lag ? csr_sweep_fn<true>(lanes) : csr_sweep_fn<false>(lanes);
+}
+
+const void *binned_sweep_kernel(bool lag) {
+    return lag ? (const void *)k_pr_iter_binned<true> : (const void *)k_pr_iter_binned<false>;
 }
 
 }  // namespace
@@ -1836,8 +2135,8 @@ hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream) {
 hipError_t pr_iter_blocks_per_cu(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
                                  int *blocks) {
     (void)sp;
-    if (a.kind == kSweepBinned) return pr_binned_blocks_per_cu(blocks);
-    const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(lanes);
+    if (a.kind == kSweepBinned) return pr_binned_blocks_per_cu(blocks, a.lag != 0);
+    const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(a, lanes);
     if (!fn) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, 0);
 }
@@ -1846,12 +2145,12 @@ hipError_t launch_pr_sweep_binned(const PrArgs &a, const BinTable &t, int grid, 
     if (t.tiles <= 0) return hipSuccess;
     PrArgs b = a;
     b.bins = t;
-    hipLaunchKernelGGL(k_pr_iter_binned, dim3(grid), dim3(kBlock), 0, stream, b);
-    return hipGetLastError();
+    void *args[] = {(void *)&b};
+    return hipLaunchKernel(binned_sweep_kernel(a.lag != 0), dim3(grid), dim3(kBlock), args, 0, stream);
 }
 
-hipError_t pr_binned_blocks_per_cu(int *blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void *)k_pr_iter_binned, kBlock, 0);
+hipError_t pr_binned_blocks_per_cu(int *blocks, bool lag) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, binned_sweep_kernel(lag), kBlock, 0);
 }
 
 hipError_t launch_bin_rows(const int32_t *row_ptr, int32_t n, const int8_t *class_of_dev, int32_t *cnt,
@@ -1866,13 +2165,14 @@ hipError_t launch_bin_rows(const int32_t *row_ptr, int32_t n, const int8_t *clas
 
 hipError_t launch_pr_sweep(const PrArgs &a, const SlotTable &sl, int lanes, int grid, hipStream_t stream) {
     if (a.kind == kSweepBinned) return launch_pr_sweep_binned(a, a.bins, grid, stream);
-    const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(lanes);
+    const void *fn = a.kind == kSweepSlots ? slot_sweep_kernel(a, sl.words) : csr_sweep_kernel(a, lanes);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {(void *)&a};
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
 }
 
 hipError_t launch_pr_step(const PrArgs &a, int grid, hipStream_t stream) {
+    if (a.lag) return hipSuccess;   // the next sweep does the step
     // partial sums: one triple per tile (slot sweep, binned sweep) or per
     // workgroup (CSR sweep)
     const int32_t count = a.kind == kSweepSlots ? (a.n + kBlock - 1) / kBlock

@@ -45,12 +45,32 @@ def test_binding_prototypes_cover_the_header():
     assert set(_abi.PROTOTYPES) == declared_functions()
 
 
-def test_struct_layouts_match_header():
+def _c_layout(struct: str, fields) -> list:
+    """sizeof and field offsets of a struct of include/fl.h, as a C compiler
+    lays it out."""
+    import subprocess
+    import tempfile
+    body = [f'printf("%zu\\n", sizeof({struct}));']
+    body += [f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"fl.h\"\nint main(void) {\n"
+           + "\n".join(body) + "\nreturn 0;\n}\n")
+    with tempfile.TemporaryDirectory() as tmp:
+        c, exe = os.path.join(tmp, "l.c"), os.path.join(tmp, "l")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, c], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return [int(x) for x in out.split()]
+
+
+@pytest.mark.parametrize("name", ["fl_params", "fl_summary", "fl_timing", "fl_space"])
+def test_struct_layouts_match_header(name):
     from paper_2210_01465_amd import _abi
-    # fl_params: 3 doubles + 2 int32; fl_summary: 4 int64 + 6 int32 + 5 doubles
-    assert ctypes.sizeof(_abi.fl_params) == 32
-    assert ctypes.sizeof(_abi.fl_summary) == 4 * 8 + 6 * 4 + 5 * 8
-    assert ctypes.sizeof(_abi.fl_timing) == 4 * 8 + 2 * 4 + 8 + 2 * 4
+    cls = getattr(_abi, name)
+    fields = [f for f, _ in cls._fields_]
+    size, *offsets = _c_layout(name, fields)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offsets
 
 
 def test_null_context_is_rejected():

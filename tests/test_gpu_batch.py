@@ -1,8 +1,9 @@
 """GPU: batched and continuously batched analyses (fl_batch_*, fl_analyze_batch).
 
 A member's results must equal its plain slot-sweep run (fl_execute with
-FL_ROWS_SLOTS) bit for bit, whatever else shares the batch and whenever it
-joins; against the FP64 oracle the usual tolerances hold.
+FL_ROWS_SLOTS and FL_STEP_SEPARATE, the batch's order of sums) bit for bit,
+whatever else shares the batch and whenever it joins; against the FP64 oracle
+the usual tolerances hold.
 """
 from concurrent.futures import ThreadPoolExecutor
 
@@ -44,7 +45,7 @@ def plain(ctx, space, nb, d, p):
     from paper_2210_01465_amd import api
     fit = torch.from_numpy(space.fitness_raw).cuda()
     plan = api.plan_create(ctx, space.radix, fit, nb)
-    pr, mins, info = api.execute(plan, d, p, row_mapping=ROWS_SLOTS)
+    pr, mins, info = api.execute(plan, d, p, row_mapping=ROWS_SLOTS, separate_step=True)
     out = (pr.cpu().numpy(), mins.cpu().numpy(), info)
     plan.close()
     return out
@@ -275,7 +276,7 @@ def test_segmented_build_every_record_width(ctx):
         plan = api.plan_create(ctx, s.radix, fit, nbs[j])
         words.append(plan.sizes["mask_words"])
         lay = ROWS_SLOTS if plan.sizes["mask_words"] > 0 else 0
-        pr, mins, info = api.execute(plan, 0.85, 0.05, row_mapping=lay)
+        pr, mins, info = api.execute(plan, 0.85, 0.05, row_mapping=lay, separate_step=True)
         pr, mins = pr.cpu().numpy(), mins.cpu().numpy()
         plan.close()
         for res in runs:
@@ -313,7 +314,7 @@ def test_batch_rejects_bad_members(ctx):
         pass
     got = {t: (pr.cpu().numpy(), info) for t, pr, _, info in batch.collect()}
     assert sorted(got) == [0, 1] and got[1][1]["row_mapping"] == -2
-    ref, _, _ = api.execute(plan, 0.85, 0.05, row_mapping=-2)
+    ref, _, _ = api.execute(plan, 0.85, 0.05, row_mapping=-2, separate_step=True)
     assert np.array_equal(got[1][0], ref.cpu().numpy())
     batch.close()
     plan.close()
@@ -337,7 +338,7 @@ def test_one_plan_many_members(ctx):
     done = {}
     b1.step(5)
     b2.step(5)
-    mid_pr, _, mid_info = api.execute(plan, 0.85, 0.1, row_mapping=ROWS_SLOTS)  # between steps
+    mid_pr, _, mid_info = api.execute(plan, 0.85, 0.1, row_mapping=ROWS_SLOTS, separate_step=True)  # between steps
     mid_pr = mid_pr.cpu().numpy()
     for _ in range(200):
         r1, r2 = b1.step(8), b2.step(8)
@@ -478,7 +479,7 @@ def test_small_members_iterate_in_one_workgroup(ctx):
 def test_binned_members_equal_plain_binned_runs(ctx):
     """Members on the binned sweep (rows binned by in-degree, per-bucket lanes
     per row), mixed with slot-sweep members and joining mid-run: each result
-    equals fl_execute with FL_ROWS_BINNED bit for bit and matches the FP64
+    equals fl_execute with FL_ROWS_BINNED (and FL_STEP_SEPARATE) bit for bit and matches the FP64
     oracle."""
     import torch
     from paper_2210_01465_amd import api
@@ -507,7 +508,7 @@ def test_binned_members_equal_plain_binned_runs(ctx):
     for j, (s, pl, nb) in enumerate(zip(spaces, plans, nbs)):
         d = (0.8, 0.85, 0.9)[j % 3]
         lay = done[j][2]["row_mapping"]
-        pr, mins, info = api.execute(pl, d, 0.05, row_mapping=lay)
+        pr, mins, info = api.execute(pl, d, 0.05, row_mapping=lay, separate_step=True)
         assert np.array_equal(done[j][0], pr.cpu().numpy()), (s.name, lay)
         assert np.array_equal(done[j][1], mins.cpu().numpy())
         assert done[j][2]["iterations"] == info["iterations"]

@@ -79,11 +79,20 @@ def test_exact_agrees_with_power_iteration_and_layouts(ctx):
         for lay in (-1, 1, 8):
             pr, _, info = api.execute(plan, 0.85, 0.05, row_mapping=lay, exact=True)
             outs[lay] = (pr.cpu().numpy(), info["iterations"])
+        sep = {}
+        for lay in (-1, 1):
+            pr, _, info = api.execute(plan, 0.85, 0.05, row_mapping=lay, exact=True, separate_step=True)
+            sep[lay] = (pr.cpu().numpy(), info["iterations"])
     finally:
         plan.close()
     assert float(np.abs(outs[-1][0] - ref).sum()) <= 2e-5
-    # the slot sweep and the one-lane CSR sweep add in the same order
-    assert np.array_equal(outs[-1][0], outs[1][0]) and outs[-1][1] == outs[1][1]
+    # the slot sweep and the one-lane CSR sweep add in the same order; with a
+    # step kernel per sweep the final scaling sums in the same order too
+    assert np.array_equal(sep[-1][0], sep[1][0]) and sep[-1][1] == sep[1][1]
+    # the lagged step makes the same sweeps: only the scaling's rounding differs
+    for lay in (-1, 1):
+        assert outs[lay][1] == sep[lay][1]
+        assert float(np.abs(outs[lay][0] - sep[lay][0]).sum()) <= 1e-12
     assert float(np.abs(outs[8][0] - outs[-1][0]).sum()) <= 1e-5
 
 

@@ -140,10 +140,17 @@ def test_slot_layouts_agree_bit_for_bit(ctx):
                     continue
                 outs = {}
                 for lay in (ROWS_SLOTS, 1):
-                    pr, _, info = api.execute(plan, 0.85, 0.05, row_mapping=lay)
-                    outs[lay] = (pr.cpu().numpy(), info["iterations"])
-                assert outs[ROWS_SLOTS][1] == outs[1][1]
-                assert np.array_equal(outs[ROWS_SLOTS][0], outs[1][0]), (s.name, nb)
+                    for sep in (True, False):
+                        pr, _, info = api.execute(plan, 0.85, 0.05, row_mapping=lay, separate_step=sep)
+                        outs[lay, sep] = (pr.cpu().numpy(), info["iterations"])
+                # with a step kernel per sweep the order of every sum is the same
+                assert outs[ROWS_SLOTS, True][1] == outs[1, True][1]
+                assert np.array_equal(outs[ROWS_SLOTS, True][0], outs[1, True][0]), (s.name, nb)
+                # the lagged step sums per workgroup, whose count depends on
+                # the kernel: the same iterates up to rounding
+                for lay in (ROWS_SLOTS, 1):
+                    assert abs(outs[lay, False][1] - outs[lay, True][1]) <= 1
+                    assert float(np.abs(outs[lay, False][0] - outs[lay, True][0]).sum()) <= L1_TOL
             finally:
                 plan.close()
 
@@ -169,9 +176,10 @@ def test_slot_sweep_plain_loads(ctx):
     offsets, so the slot sweep takes its plain-load form.  The valid points
     form a 2^18-point sub-cube (bits 10..19 zero) with 10 % failures, so every
     parameter, the most significant included, has in-edges.  Checked against
-    the one-lane CSR sweep on the same plan (same order of addition: equal
-    bit for bit) and against the invariants of a probability vector with
-    teleport (sum 1, r >= (1 - d)/N)."""
+    the one-lane CSR sweep on the same plan (same order of addition with a
+    step kernel per sweep: equal bit for bit), the lagged step against that,
+    and against the invariants of a probability vector with teleport (sum 1,
+    r >= (1 - d)/N)."""
     import torch
     from paper_2210_01465_amd import api
     n_raw = 1 << 28
@@ -185,11 +193,15 @@ def test_slot_sweep_plain_loads(ctx):
     del f
     try:
         assert plan.sizes["mask_words"] == 2 and plan.n_valid == idx.size
-        pr_s, mins_s, info_s = api.execute(plan, 0.85, 0.05, row_mapping=ROWS_SLOTS)
-        pr_c, mins_c, info_c = api.execute(plan, 0.85, 0.05, row_mapping=1)
+        pr_s, mins_s, info_s = api.execute(plan, 0.85, 0.05, row_mapping=ROWS_SLOTS, separate_step=True)
+        pr_c, mins_c, info_c = api.execute(plan, 0.85, 0.05, row_mapping=1, separate_step=True)
         pr_s, pr_c = pr_s.cpu().numpy(), pr_c.cpu().numpy()
         assert info_s["iterations"] == info_c["iterations"] and info_s["status"] == 0
         assert np.array_equal(pr_s, pr_c)
+        pr_l, mins_l, info_l = api.execute(plan, 0.85, 0.05, row_mapping=ROWS_SLOTS)
+        assert abs(info_l["iterations"] - info_s["iterations"]) <= 1 and info_l["status"] == 0
+        assert float(np.abs(pr_l.cpu().numpy() - pr_s).sum()) <= L1_TOL
+        assert np.array_equal(mins_l.cpu().numpy(), mins_s.cpu().numpy())
         assert np.array_equal(mins_s.cpu().numpy(), mins_c.cpu().numpy())
         assert info_s["n_edges"] > 0 and abs(pr_s.sum() - 1.0) <= 1e-6
         assert pr_s.min() >= (1.0 - 0.85) / idx.size * (1.0 - 1e-5)
@@ -293,6 +305,14 @@ def test_error_paths(ctx):
             with pytest.raises(api.FLError) as e:
                 api.execute(plan, **args)
             assert e.value.status == _abi.FL_EINVAL, kw
+        # unknown flags and a non-zero reserved field
+        out = torch.empty(8, dtype=torch.float64, device="cuda")
+        mins = torch.empty(8, dtype=torch.int32, device="cuda")
+        for flags, reserved in ((2, 0), (-1, 0), (0, 1)):
+            prm = _abi.fl_params(0.85, 0.05, 0.0, 0, 0, flags, reserved)
+            rc = lib.fl_execute(ctx.handle, plan.handle, ctypes.byref(prm), ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(mins.data_ptr()), None)
+            assert rc == _abi.FL_EINVAL, (flags, reserved)
     finally:
         plan.close()
     wide = api.plan_create(ctx, (200,), torch.arange(1, 201, dtype=torch.float32, device="cuda"))

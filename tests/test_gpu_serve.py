@@ -1,5 +1,6 @@
 """GPU: the continuous-batching server.  Every request's result equals the
-same analysis run alone, whatever it shared the device with, and matches the
+same analysis run alone (with the batch's separate step), whatever it shared
+the device with, and matches the
 FP64 oracle (minima exactly, ranks within 1e-5 in L1, C_p within 1e-5)."""
 from concurrent.futures import ThreadPoolExecutor
 
@@ -33,7 +34,7 @@ def test_served_equals_alone():
     assert srv.stats["cache_hits"] > 0
     for r in reqs[:40]:
         plan = api.plan_create(ctx, r.radix, r.fitness, "hamming")
-        pr, mins, info = api.execute(plan, r.damping, r.p, row_mapping=-1)
+        pr, mins, info = api.execute(plan, r.damping, r.p, row_mapping=-1, separate_step=True)
         assert np.array_equal(done[r.rid].pagerank.cpu().numpy(), pr.cpu().numpy())
         assert done[r.rid].score == info["score"]
         plan.close()
