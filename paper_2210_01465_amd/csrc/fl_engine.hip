@@ -442,23 +442,25 @@ void build_begin(fl_ctx *ctx, Build &b, const fl_space *space, const float *fit,
         return build_fail(b, FL_EHIP, "hipEventCreate failed");
     }
 
-    const int64_t c_tiles = (n_raw + fl::kCompactTile - 1) / fl::kCompactTile;
+    // tiles of the segmented build's three passes, or of one space's two
+    const int64_t c_tiles = b.defer ? (n_raw + fl::kCompactTile - 1) / fl::kCompactTile
+                                    : (n_raw + fl::kSingleTile - 1) / fl::kSingleTile;
     b.remap = pool_alloc<int32_t>(ctx, n_raw);
     b.tile_cnt = pool_alloc<int32_t>(ctx, c_tiles);
     b.tile_bad = pool_alloc<int32_t>(ctx, c_tiles);
-    b.tile_off = pool_alloc<int32_t>(ctx, c_tiles);
     b.tile_min = pool_alloc<float>(ctx, c_tiles);
+    if (b.defer) b.tile_off = pool_alloc<int32_t>(ctx, c_tiles);
     if (!b.shared_sizes) b.d_sizes = pool_alloc<BuildSizes>(ctx, 1);
     p->valid_raw = pool_alloc<int32_t>(ctx, n_raw);
     p->fit_c = pool_alloc<float>(ctx, n_raw);
-    if (!b.remap || !b.tile_cnt || !b.tile_bad || !b.tile_off || !b.tile_min || !b.d_sizes || !p->valid_raw ||
-        !p->fit_c)
+    if (!b.remap || !b.tile_cnt || !b.tile_bad || (b.defer && !b.tile_off) || !b.tile_min || !b.d_sizes ||
+        !p->valid_raw || !p->fit_c)
         return build_fail(b, FL_ENOMEM, "device allocation failed");
     hipStream_t s = ctx->stream;
     hipError_t he = b.timed ? hipEventRecord(p->ev[0], s) : hipSuccess;
     if (he == hipSuccess && !b.defer)
-        he = fl::launch_compact(fit, sp.n_raw, b.tile_cnt, b.tile_min, b.tile_bad, b.tile_off, b.remap,
-                                p->valid_raw, p->fit_c, b.d_sizes, s);
+        he = fl::launch_compact_single(fit, sp.n_raw, b.tile_cnt, b.tile_min, b.tile_bad, b.remap, p->valid_raw,
+                                       p->fit_c, b.d_sizes, s);
     if (he == hipSuccess && !b.shared_sizes)
         he = hipMemcpyAsync(b.h_sizes, b.d_sizes, sizeof(BuildSizes), hipMemcpyDeviceToHost, s);
     if (he != hipSuccess) build_fail(b, FL_EHIP, "compaction: %s", hipGetErrorString(he));
@@ -1487,6 +1489,10 @@ fl_status tune_buckets(fl_ctx *ctx, fl_plan *p, const Resolved &r, int32_t sweep
     if (st == FL_OK) {
         a.partials = p->partials;
         a.bin_rows = rows;
+        // one bucket's rows at a time, with per-tile partial sums (sized
+        // above): the lagged step's per-workgroup buffers follow the plan's
+        // grid, not these launches'
+        a.lag = 0;
         hipError_t e = hipMemsetAsync(p->state, 0, sizeof(PrState), s);
         if (e == hipSuccess) e = fl::launch_pr_init(a, init_grid, s);
         const int64_t resident = (int64_t)std::max(per_cu, 1) * ctx->num_cus / fl::kXcds * fl::kXcds;

@@ -13,6 +13,11 @@ constexpr int kMaxWords = 5;                      // 64-bit words per node recor
 constexpr int kBlock = 256;                       // threads per workgroup (4 waves of 64)
 constexpr int kCompactItems = 8;                  // raw configurations per thread in compaction
 constexpr int kCompactTile = kBlock * kCompactItems;
+// single-pass compaction of one space: 16 per thread, 4096 per tile (about
+// 1 100 tiles at 4.7 M configurations, all resident at once with 32 KB of
+// LDS staging each)
+constexpr int kSingleItems = 16;
+constexpr int kSingleTile = kBlock * kSingleItems;
 constexpr int kXcds = 8;                          // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int kBatch = 16;                        // candidate slots whose loads are issued together
 constexpr int kMaxFinishGrid = 1024;              // workgroups of the batched step kernel (grid-stride)
@@ -235,10 +240,11 @@ struct TileRef {
 };
 
 // ---- launchers (fl_kernels.hip); all enqueue on `stream` ----
-hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, float *tile_min,
-                          int32_t *tile_bad, int32_t *tile_off, int32_t *remap,
-                          int32_t *valid_raw, float *fit_c, BuildSizes *sizes,
-                          hipStream_t stream);
+// Compaction of one space (two passes, no scan kernel): tile_cnt,
+// tile_min and tile_bad hold ceil(n_raw / kSingleTile) entries.
+hipError_t launch_compact_single(const float *fit, int32_t n_raw, int32_t *tile_cnt, float *tile_min,
+                                 int32_t *tile_bad, int32_t *remap, int32_t *valid_raw, float *fit_c,
+                                 BuildSizes *sizes, hipStream_t stream);
 // Segmented build stages (see SegBuild): `tiles` lists (space, tile) pairs,
 // `ids` the spaces of the one-workgroup-per-space scans.
 hipError_t launch_seg_compact(const SegBuild *segs, const SegTile *tiles, int32_t n_tiles, const int32_t *ids,

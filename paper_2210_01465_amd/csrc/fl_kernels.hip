@@ -234,13 +234,6 @@ __device__ __forceinline__ void compact_count(const float *__restrict__ fit, int
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact_count(const float *__restrict__ fit, int32_t n_raw,
-                                                          int32_t *__restrict__ tile_cnt,
-                                                          float *__restrict__ tile_min,
-                                                          int32_t *__restrict__ tile_bad) {
-    compact_count(fit, n_raw, blockIdx.x, tile_cnt, tile_min, tile_bad);
-}
-
 __device__ __forceinline__ void compact_scan(const int32_t *__restrict__ tile_cnt,
                                              const float *__restrict__ tile_min,
                                              const int32_t *__restrict__ tile_bad, int32_t n_tiles,
@@ -260,14 +253,6 @@ __device__ __forceinline__ void compact_scan(const int32_t *__restrict__ tile_cn
         sizes->f_opt = mn;
         sizes->n_plateau = 0;   // counted by the degree pass
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_compact_scan(const int32_t *__restrict__ tile_cnt,
-                                                         const float *__restrict__ tile_min,
-                                                         const int32_t *__restrict__ tile_bad,
-                                                         int32_t n_tiles, int32_t *__restrict__ tile_off,
-                                                         BuildSizes *__restrict__ sizes) {
-    compact_scan(tile_cnt, tile_min, tile_bad, n_tiles, tile_off, sizes);
 }
 
 __device__ __forceinline__ void compact_write(const float *__restrict__ fit, int32_t n_raw, int32_t tile,
@@ -300,12 +285,143 @@ __device__ __forceinline__ void compact_write(const float *__restrict__ fit, int
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact_write(const float *__restrict__ fit, int32_t n_raw,
-                                                          const int32_t *__restrict__ tile_off,
+// Compaction of one space in two passes without a scan kernel.  The first
+// pass counts each tile's valid points (and its minimum and bad values); in
+// the second, tile t sums the counts of tiles 0 .. t-1 itself (a few KB
+// from L2, one round of loads), so no tile waits for another, and writes
+// its part of the outputs: remap in place, the compacted node map and
+// fitness staged in LDS and stored coalesced.  The last tile also writes
+// the totals (n_valid, f_opt, the bad count).  Tiles of kSingleTile raw
+// configurations, 16 per thread, loaded as float4 when fit is 16-byte
+// aligned (VEC).
+//
+// A single pass with a decoupled look-back (Merrill and Garland 2016:
+// publish the tile's count, walk back over the predecessors' published
+// words to the first inclusive prefix) measured 50 us at the large workload
+// with a 64-wide walk and 39 us with a 256-wide one, against the 18-20 us
+// of these two passes: with every tile running at once, few prefixes are
+// out when the walks start, and each round is one device-scope load.
+
+template <bool VEC>
+__device__ __forceinline__ void load_tile_values(const float *__restrict__ fit, int32_t n_raw, int64_t base,
+                                                 int64_t step, float (&f)[kSingleItems]) {
+    // value j of the thread: raw index base + (j / 4) * step + j % 4
+#pragma unroll
+    for (int q = 0; q < kSingleItems / 4; ++q) {
+        const int64_t i = base + q * step;
+        if (VEC && i + 4 <= n_raw) {
+            const float4 a = *reinterpret_cast<const float4 *>(fit + i);
+            f[4 * q] = a.x;
+            f[4 * q + 1] = a.y;
+            f[4 * q + 2] = a.z;
+            f[4 * q + 3] = a.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f[4 * q + e] = i + e < n_raw ? fit[i + e] : NAN;
+        }
+    }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_compact_tiles(const float *__restrict__ fit, int32_t n_raw,
+                                                          int32_t *__restrict__ tile_cnt,
+                                                          float *__restrict__ tile_min,
+                                                          int32_t *__restrict__ tile_bad) {
+    // strided: thread t reads 4 consecutive values at base + 4t + 1024 q
+    float f[kSingleItems];
+    load_tile_values<VEC>(fit, n_raw, (int64_t)blockIdx.x * kSingleTile + 4 * threadIdx.x, 4 * kBlock, f);
+    int32_t cnt = 0, bad = 0;
+    float mn = INFINITY;
+#pragma unroll
+    for (int j = 0; j < kSingleItems; ++j) {
+        const bool v = valid_fitness(f[j]);
+        cnt += v;
+        bad += bad_fitness(f[j]);
+        if (v) mn = fminf(mn, f[j]);
+    }
+    cnt = block_sum(cnt);
+    bad = block_sum(bad);
+    mn = block_min(mn);
+    if (threadIdx.x == 0) {
+        tile_cnt[blockIdx.x] = cnt;
+        tile_bad[blockIdx.x] = bad;
+        tile_min[blockIdx.x] = mn;
+    }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_compact_place(const float *__restrict__ fit, int32_t n_raw,
+                                                          int32_t n_tiles, const int32_t *__restrict__ tile_cnt,
+                                                          const float *__restrict__ tile_min,
+                                                          const int32_t *__restrict__ tile_bad,
                                                           int32_t *__restrict__ remap,
                                                           int32_t *__restrict__ valid_raw,
-                                                          float *__restrict__ fit_c) {
-    compact_write(fit, n_raw, blockIdx.x, tile_off, remap, valid_raw, fit_c);
+                                                          float *__restrict__ fit_c,
+                                                          BuildSizes *__restrict__ sizes) {
+    __shared__ int32_t st_raw[kSingleTile];
+    __shared__ float st_fit[kSingleTile];
+    const int32_t tile = blockIdx.x;
+    const bool last = tile == n_tiles - 1;
+    // the tile's first output slot: the counts of the tiles before it (the
+    // last tile sums them all, and the bad counts and minima with them)
+    int32_t before = 0, bad = 0;
+    float mn = INFINITY;
+    const int32_t upto = last ? n_tiles : tile;
+    for (int32_t u = threadIdx.x; u < upto; u += kBlock) {
+        const int32_t c = tile_cnt[u];
+        if (u < tile) before += c;
+        if (last) {
+            bad += tile_bad[u];
+            mn = fminf(mn, tile_min[u]);
+        }
+    }
+    const int32_t excl = block_sum(before);
+    // blocked: thread t owns raw indices base .. base + 15
+    const int64_t base = (int64_t)tile * kSingleTile + (int64_t)threadIdx.x * kSingleItems;
+    float f[kSingleItems];
+    load_tile_values<VEC>(fit, n_raw, base, 4, f);
+    int32_t cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kSingleItems; ++j) cnt += valid_fitness(f[j]);
+    int32_t tot;
+    const int32_t local = block_excl_scan(cnt, &tot);
+    if (last) {
+        bad = block_sum(bad);
+        mn = block_min(mn);
+        if (threadIdx.x == 0) {
+            sizes->n_valid = excl + tot;
+            sizes->n_bad = bad;
+            sizes->f_opt = mn;
+            sizes->n_plateau = 0;   // counted by the degree pass
+        }
+    }
+    int32_t r[kSingleItems];
+    int32_t id = local;
+#pragma unroll
+    for (int j = 0; j < kSingleItems; ++j) {
+        if (valid_fitness(f[j])) {
+            r[j] = excl + id;
+            st_raw[id] = (int32_t)(base + j);
+            st_fit[id] = f[j];
+            ++id;
+        } else {
+            r[j] = -1;
+        }
+    }
+    if (base + kSingleItems <= n_raw) {
+#pragma unroll
+        for (int q = 0; q < kSingleItems / 4; ++q)
+            *reinterpret_cast<int4 *>(remap + base + 4 * q) = make_int4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kSingleItems; ++j)
+            if (base + j < n_raw) remap[base + j] = r[j];
+    }
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < tot; q += kBlock) {
+        valid_raw[excl + q] = st_raw[q];
+        fit_c[excl + q] = st_fit[q];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -384,6 +500,16 @@ __device__ __forceinline__ void degree_slots(const SP &sp, const SL &sl, int32_t
     const uint32_t i4 = 4u * i;
     int32_t dout = 0;
     bool tie = false;
+    // The comparisons work on the bits: by the time this pass runs every
+    // fitness is positive and finite, +inf or NaN (the build stops on any
+    // other), and positive finite floats order as their bit patterns, below
+    // +inf (0x7f800000) and the NaNs.  A neighbour c is worse (an in-edge)
+    // iff fv < c < +inf, i.e. (c - fv - 1) < (+inf - fv - 1) unsigned; better
+    // (an out-edge) iff 0 < c < fv, i.e. (c - 1) < (fv - 1) unsigned, which
+    // also drops the 0 of an absent slot.  Two VALU per test instead of two
+    // float compares and an AND.
+    const uint32_t fvb = __float_as_uint(fv);
+    const uint32_t in_lo = fvb + 1u, in_span = 0x7f800000u - in_lo, out_hi = fvb - 1u;
 #pragma unroll
     for (int b = 0; b < 2 * W; ++b) {
         if (32 * b >= sl.k) break;
@@ -406,11 +532,20 @@ __device__ __forceinline__ void degree_slots(const SP &sp, const SL &sl, int32_t
         uint32_t inb = 0u;
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
-            // a neighbour that is worse (in-edge; +inf marks an excluded one),
-            // or better (out-edge; 0 marks a slot the node does not have)
-            if ((fc[u] > fv) & (fc[u] < INFINITY)) inb |= 1u << u;
-            dout += (fc[u] < fv) & (fc[u] > 0.0f);
-            tie |= fc[u] == fv;   // a valid neighbour of equal fitness (0, NaN, inf never equal fv)
+            // a neighbour that is worse (in-edge; +inf and NaN mark excluded
+            // ones), or better (out-edge; 0 marks a slot the node does not have)
+            if (W == 1) {
+                // the same tests on floats: with one record word the compiler
+                // turns the integer form into a 256-register kernel that spills
+                if ((fc[u] > fv) & (fc[u] < INFINITY)) inb |= 1u << u;
+                dout += (fc[u] < fv) & (fc[u] > 0.0f);
+                tie |= fc[u] == fv;
+            } else {
+                const uint32_t cb = __float_as_uint(fc[u]);
+                if (cb - in_lo < in_span) inb |= 1u << u;
+                dout += cb - 1u < out_hi;
+                tie |= cb == fvb;   // a valid neighbour of equal fitness (0, NaN, inf never equal fv)
+            }
         }
         m[b >> 1] |= (b & 1) ? ((uint64_t)inb << 32) : (uint64_t)inb;
     }
@@ -520,12 +655,79 @@ __device__ __forceinline__ void degree_scan(const int64_t *__restrict__ tile_e, 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_degree_scan(const int64_t *__restrict__ tile_e,
-                                                        const int32_t *__restrict__ tile_m,
-                                                        int32_t n_tiles, int64_t *__restrict__ tile_eoff,
-                                                        int32_t *__restrict__ tile_moff,
-                                                        BuildSizes *__restrict__ sizes) {
-    degree_scan(tile_e, tile_m, n_tiles, tile_eoff, tile_moff, sizes);
+// Exclusive prefix sum of one value per thread over a workgroup of B
+// threads; *total receives the sum.
+template <int B, typename T>
+__device__ T block_excl_scan_b(T v, T *total) {
+    __shared__ T part[B / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) part[wid] = incl;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < B / 64; ++w) {
+        const T s = part[w];
+        off += (w < wid) ? s : T(0);
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+// The degree pass's tile scans (edges and sinks) in one 1024-thread
+// workgroup: each thread takes kScanItems consecutive tiles of both arrays,
+// so up to 8192 tiles (2 M nodes) need one round of loads; larger spaces loop
+// with a carry.  (The two-array, 256-thread scan_tiles took 14 us at the large
+// workload, six dependent rounds.)
+constexpr int kScanItems = 8;
+__global__ __launch_bounds__(kFinishBlock) void k_degree_scan(const int64_t *__restrict__ tile_e,
+                                                              const int32_t *__restrict__ tile_m,
+                                                              int32_t n_tiles, int64_t *__restrict__ tile_eoff,
+                                                              int32_t *__restrict__ tile_moff,
+                                                              BuildSizes *__restrict__ sizes) {
+    int64_t ce = 0;
+    int32_t cm = 0;
+    for (int32_t base = 0; base < n_tiles; base += kFinishBlock * kScanItems) {
+        const int32_t first = base + (int32_t)threadIdx.x * kScanItems;
+        int64_t e[kScanItems];
+        int32_t m[kScanItems];
+        int64_t se = 0;
+        int32_t sm = 0;
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            const bool in = first + j < n_tiles;
+            e[j] = in ? tile_e[first + j] : 0;
+            m[j] = in ? tile_m[first + j] : 0;
+            se += e[j];
+            sm += m[j];
+        }
+        int64_t te;
+        int32_t tm;
+        int64_t re = ce + block_excl_scan_b<kFinishBlock>(se, &te);
+        int32_t rm = cm + block_excl_scan_b<kFinishBlock>(sm, &tm);
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            if (first + j < n_tiles) {
+                tile_eoff[first + j] = re;
+                tile_moff[first + j] = rm;
+            }
+            re += e[j];
+            rm += m[j];
+        }
+        ce += te;
+        cm += tm;
+    }
+    if (threadIdx.x == 0) {
+        sizes->n_edges = ce;
+        sizes->n_minima = cm;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1070,6 +1272,41 @@ __global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
     const int32_t n_tiles = (a.n + kBlock - 1) / kBlock;
     for (int32_t t = blockIdx.x; t < n_tiles; t += gridDim.x)
         init_tile(t, a.n, a.out_deg, a.kind == kSweepSlots ? a.valid_raw : nullptr, a.y[0], a.x[0], a.partials);
+}
+
+// Lagged step: the initial iterate without partial sums and without a step
+// kernel.  Its sums are known: N y0 and M y0 over the M sinks, exact in FP64
+// (y0 = 1/N in FP32 has 24 significant bits), as the reduction of the
+// plain path gives them; workgroup 0 writes the state of the first step.
+__global__ __launch_bounds__(kBlock) void k_pr_init_lag(PrArgs a) {
+    const float y0 = (float)(1.0 / (double)a.n);
+    const int32_t *xmap = a.kind == kSweepSlots ? a.valid_raw : nullptr;
+    for (int32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += gridDim.x * kBlock) {
+        const int32_t deg = a.out_deg[v];
+        a.y[0][v] = y0;
+        a.x[0][xmap ? xmap[v] : v] = deg > 0 ? y0 / (float)deg : 0.0f;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        PrState *st = a.st;
+        const double y = (double)y0, n = (double)a.n;
+        const double s0 = n * y, s2 = (double)a.n_sinks * y;
+        st->sigma = s0;
+        st->sink = s2;
+        st->s = a.exact ? 1.0 : 1.0 / s0;
+        st->c = a.exact ? 1.0 : (a.d * s2 * st->s + (1.0 - a.d)) / n;
+        st->k = 0;
+        st->done = 0;
+        st->worked = 0;
+        st->resid = 0.0;
+        st->resid_prev = 0.0;
+        // sweep 0 adds nothing (r_0 = w_0), sweep 1 adds gamma_0
+        st->gam[0][0] = st->gam[0][1] = 0.0;
+        st->gam[1][0] = a.exact ? 0.0 : (a.d * s2 + (1.0 - a.d)) / n;
+        st->gam[1][1] = 0.0;
+        st->out_buf = 0;
+        st->out_gamma = 0.0;
+        st->out_sigma = s0;
+    }
 }
 
 // Tiles of the persistent grid.  XCD j = b % 8 owns the contiguous j-th
@@ -1933,17 +2170,21 @@ const void *binned_sweep_kernel(bool lag) {
 // ---------------------------------------------------------------------------
 // Launchers.
 
-hipError_t launch_compact(const float *fit, int32_t n_raw, int32_t *tile_cnt, float *tile_min,
-                          int32_t *tile_bad, int32_t *tile_off, int32_t *remap,
-                          int32_t *valid_raw, float *fit_c, BuildSizes *sizes,
-                          hipStream_t stream) {
-    const int32_t tiles = (n_raw + kCompactTile - 1) / kCompactTile;
-    hipLaunchKernelGGL(k_compact_count, dim3(tiles), dim3(kBlock), 0, stream, fit, n_raw, tile_cnt,
-                       tile_min, tile_bad);
-    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(kBlock), 0, stream, tile_cnt, tile_min,
-                       tile_bad, tiles, tile_off, sizes);
-    hipLaunchKernelGGL(k_compact_write, dim3(tiles), dim3(kBlock), 0, stream, fit, n_raw, tile_off,
-                       remap, valid_raw, fit_c);
+hipError_t launch_compact_single(const float *fit, int32_t n_raw, int32_t *tile_cnt, float *tile_min,
+                                 int32_t *tile_bad, int32_t *remap, int32_t *valid_raw, float *fit_c,
+                                 BuildSizes *sizes, hipStream_t stream) {
+    const int32_t tiles = (n_raw + kSingleTile - 1) / kSingleTile;
+    if (((uintptr_t)fit & 15u) == 0) {
+        hipLaunchKernelGGL(k_compact_tiles<true>, dim3(tiles), dim3(kBlock), 0, stream, fit, n_raw, tile_cnt, tile_min,
+                           tile_bad);
+        hipLaunchKernelGGL(k_compact_place<true>, dim3(tiles), dim3(kBlock), 0, stream, fit, n_raw, tiles, tile_cnt,
+                           tile_min, tile_bad, remap, valid_raw, fit_c, sizes);
+    } else {
+        hipLaunchKernelGGL(k_compact_tiles<false>, dim3(tiles), dim3(kBlock), 0, stream, fit, n_raw, tile_cnt,
+                           tile_min, tile_bad);
+        hipLaunchKernelGGL(k_compact_place<false>, dim3(tiles), dim3(kBlock), 0, stream, fit, n_raw, tiles, tile_cnt,
+                           tile_min, tile_bad, remap, valid_raw, fit_c, sizes);
+    }
     return hipGetLastError();
 }
 
@@ -2064,7 +2305,7 @@ hipError_t launch_degree(const SpaceDesc &sp, const SlotTable &sl, int adjacent,
             break;
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_degree_scan, dim3(1), dim3(kBlock), 0, stream, tile_e, tile_m, tiles,
+    hipLaunchKernelGGL(k_degree_scan, dim3(1), dim3(kFinishBlock), 0, stream, tile_e, tile_m, tiles,
                        tile_eoff, tile_moff, sizes);
     return hipGetLastError();
 }
@@ -2126,6 +2367,10 @@ hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, c
 }
 
 hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream) {
+    if (a.lag) {
+        hipLaunchKernelGGL(k_pr_init_lag, dim3(grid), dim3(kBlock), 0, stream, a);
+        return hipGetLastError();
+    }
     const int32_t n_tiles = (a.n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_pr_init, dim3(grid), dim3(kBlock), 0, stream, a);
     hipLaunchKernelGGL(k_pr_finish<true>, dim3(1), dim3(kFinishBlock), 0, stream, a, n_tiles);

@@ -22,7 +22,7 @@ def resources():
 def test_report_covers_the_kernels(resources):
     names = " ".join(resources)
     for k in ("k_pr_iter_slots", "k_pr_iter_csr", "k_batch_sweep", "k_degree_slots", "k_fill_slots",
-              "k_compact_write", "k_pr_finish"):
+              "k_compact_place", "k_seg_compact_write", "k_pr_finish"):
         assert k in names, k
     assert all("scratch" in r and "vgprs" in r for r in resources.values())
 
