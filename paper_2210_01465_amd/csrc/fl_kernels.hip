@@ -1763,9 +1763,10 @@ __device__ __forceinline__ void sweep_tile(const SweepTile &q, int32_t tile) {
     write_partials(q.partials, tile, ps, pr, pk);
 }
 
-// LAG: the lagged step (see lag_step); the workgroup's terms make one triple,
-// summed per tile by the fixed tree and over its tiles in order by thread 0
-// in LDS, so that no FP64 sums stay live in registers across the gathers.
+// LAG: the lagged step (see lag_step); the workgroup's terms make one
+// triple: each thread adds its nodes' terms over its tiles in LDS (so that no
+// FP64 sums stay live in registers across the gathers), then one fixed tree
+// reduces the threads' sums.
 template <int W, bool BUF, bool LAG>
 __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     const PrState *st = a.st;
@@ -1797,25 +1798,18 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
     q.x_bytes = a.x_bytes;
     const TileWalk w((a.n + kBlock - 1) / kBlock);
     if (LAG) {
-        __shared__ double sums[3];
-        if (threadIdx.x == 0) sums[0] = sums[1] = sums[2] = 0.0;
+        // each thread's running sums live in LDS between its tiles
+        __shared__ double sums[3][kBlock];
+        const int lt = (int)threadIdx.x;
+        sums[0][lt] = sums[1][lt] = sums[2][lt] = 0.0;
         for (int32_t t = w.first; t < w.end; t += w.step) {
             double ps = 0.0, pr = 0.0, pk = 0.0;
-            sweep_tile_sums<W, BUF, true>(q, t, (int)threadIdx.x, ps, pr, pk);
-            block_sum3(ps, pr, pk);
-            if (threadIdx.x == 0) {
-                sums[0] += ps;
-                sums[1] += pr;
-                sums[2] += pk;
-            }
+            sweep_tile_sums<W, BUF, true>(q, t, lt, ps, pr, pk);
+            sums[0][lt] += ps;
+            sums[1][lt] += pr;
+            sums[2][lt] += pk;
         }
-        if (threadIdx.x == 0) {
-            const int64_t stride = a.part_stride;
-            double *pp = a.partials + (int64_t)(a.sweep & 1) * 3 * stride + blockIdx.x;
-            pp[0] = sums[0];
-            pp[stride] = sums[1];
-            pp[2 * stride] = sums[2];
-        }
+        write_lag_partials(a, sums[0][lt], sums[1][lt], sums[2][lt]);
     } else {
         for (int32_t t = w.first; t < w.end; t += w.step) sweep_tile<W, BUF>(q, t);
     }
