@@ -1107,6 +1107,20 @@ __global__ __launch_bounds__(kFinishBlock) void k_pr_finish(PrArgs a, int32_t co
 // r_{j-1} from the stored w_j and w_{j-1}.  The iterates are those of the
 // plain iteration in exact arithmetic; the stop is seen one sweep later.
 
+// The stop flag of the lagged step.  Workgroup 0 sets it while the rest of
+// its sweep still runs; the other waves read it at device scope ahead of
+// each tile and stop sweeping once it is set (their results are not used
+// any more), so the sweep after the stop costs little more than its first
+// tiles.
+__device__ __forceinline__ void set_stop(PrState *st, int32_t v) {
+    __hip_atomic_store(&st->done, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t peek_stop(const PrState *st) {
+    return __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(const_cast<int32_t *>(&st->done), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 // Workgroup 0 of sweep j >= 1: reduce the partial triples of sweep j - 1
 // in a fixed order (thread t sums parts t, t + kBlock, ...; then a fixed
 // tree) and do its step.  Sweep j - 1 wrote sum w_j, the residual
@@ -1146,14 +1160,12 @@ __device__ void lag_step(const PrArgs &a) {
         st->worked = j;
         st->sigma = r0;
         st->sink = r2;
-        if (r1 == 0.0)
-            st->done = 1;
-        else if (j >= a.max_iter)
-            st->done = 2;
-        if (st->done) {
+        const int32_t stop = r1 == 0.0 ? 1 : (j >= a.max_iter ? 2 : 0);
+        if (stop) {
             st->out_buf = j % 3;
             st->out_gamma = 0.0;
             st->out_sigma = r0;
+            set_stop(st, stop);
         }
         return;
     }
@@ -1166,15 +1178,13 @@ __device__ void lag_step(const PrArgs &a) {
         st->resid = r1;
         st->k = j - 1;
         st->worked = j - 1;
-        if (r1 < a.tol)
-            st->done = 1;
-        else if (j - 1 >= a.max_iter)
-            st->done = 2;
-        if (st->done) {
+        const int32_t stop = r1 < a.tol ? 1 : (j - 1 >= a.max_iter ? 2 : 0);
+        if (stop) {
             // r_{j-1} = w_{j-1} + gamma_{j-2}, summed by the previous step
             st->out_buf = (j - 1) % 3;
             st->out_gamma = gb;
             st->out_sigma = st->sigma;
+            set_stop(st, stop);
         }
     }
     st->gam[(j + 1) & 1][0] = (a.d * sink + (1.0 - a.d)) / n;   // gamma_j
@@ -1367,6 +1377,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
     const TileWalk w((a.n + kRows - 1) / kRows);
     double ps = 0.0, pr = 0.0, pk = 0.0;
     for (int32_t t = w.first; t < w.end; t += w.step) {
+        const int32_t stop = LAG ? peek_stop(a.st) : 0;
         const int32_t v = t * kRows + sub;
         float acc = 0.0f;
         // lagged step: the row's own values, loaded ahead of its gathers
@@ -1402,6 +1413,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_csr(PrArgs a) {
                 pr_node_update(a, v, v, acc, sd, c, s, y_in, y_out, x_out, ps, pr, pk);
             }
         }
+        if (stop) break;   // lagged step, per wave: this loop has no barrier
     }
     if (LAG)
         write_lag_partials(a, ps, pr, pk);
@@ -1538,14 +1550,20 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_binned(PrArgs a) {
     const int xcd = blockIdx.x % kXcds, nb = gridDim.x / kXcds, l = blockIdx.x / kXcds;
     const int nc = tb->n_classes;
     double ws = 0.0, wr = 0.0, wk = 0.0;   // lagged step: the workgroup's sums
-    for (int cl = 0; cl < nc; ++cl) {
+    bool stopped = false;                  // lagged step: the stop flag was seen (per wave)
+    for (int cl = 0; cl < nc && !stopped; ++cl) {
         const int32_t t0 = tb->c[cl].tile_begin;
         const int32_t ct = (cl + 1 < nc ? tb->c[cl + 1].tile_begin : a.bins.tiles) - t0;
         const int32_t per = (ct + kXcds - 1) / kXcds;
         const int32_t lo = t0 + per * xcd, hi = t0 + min(per * (xcd + 1), ct);
         for (int32_t t = lo + l; t < hi; t += nb) {
             if (LAG) {
+                const int32_t stop = peek_stop(a.st);
                 binned_tile<true>(q, tb, t, ws, wr, wk);
+                if (stop) {   // per wave: no barrier in the tile loop
+                    stopped = true;
+                    break;
+                }
             } else {
                 double ps = 0.0, pr = 0.0, pk = 0.0;
                 binned_tile<false>(q, tb, t, ps, pr, pk);
@@ -1803,11 +1821,13 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter_slots(PrArgs a) {
         const int lt = (int)threadIdx.x;
         sums[0][lt] = sums[1][lt] = sums[2][lt] = 0.0;
         for (int32_t t = w.first; t < w.end; t += w.step) {
+            const int32_t stop = peek_stop(a.st);   // its latency hides behind the tile
             double ps = 0.0, pr = 0.0, pk = 0.0;
             sweep_tile_sums<W, BUF, true>(q, t, lt, ps, pr, pk);
             sums[0][lt] += ps;
             sums[1][lt] += pr;
             sums[2][lt] += pk;
+            if (stop) break;   // per wave: this loop has no barrier
         }
         write_lag_partials(a, sums[0][lt], sums[1][lt], sums[2][lt]);
     } else {
