@@ -27,6 +27,7 @@ cpu_baseline = the FP64 oracle on the same space at the same tolerance,
 from __future__ import annotations
 
 import argparse
+import collections
 import hashlib
 import json
 import os
@@ -38,6 +39,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FFG+PageRank edges/s (GTEPS) & % HBM peak at 1M configs; p50/p99 per-space latency"
 HBM_PEAK_GBS = 8000.0
+# the server runs analyses of graphs above this many edges alone on its
+# builder's stream, beside the batch (the 1.5 M-node space has 23 M)
+SERVING_ALONE_EDGES = 1 << 22
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pr_iter_slots_large_traffic.json")
 LOOP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_sweep_batched234_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2210_01465_amd", "csrc", "fl_kernels.hip")
@@ -555,25 +559,32 @@ def serving_stream(spaces, fits, large_space, large_fit, rate: float, seconds: f
     return reqs
 
 
-def serve_both(ctx, reqs, warm: float, cache: bool = True):
+def serve_both(ctx, reqs, warm: float, cache: bool = True, alone_edges: int | None = SERVING_ALONE_EDGES,
+               alone_when_idle: bool = True, plain: bool = True, sweeps_per_step: int = 16):
     """One request stream through the continuous-batching server (FFG builds
-    of cache misses on the builder thread's stream) and through the
-    one-at-a-time path, both with the same content-keyed plan cache (or
-    both without one).  Returns (served summary, plain summary, server
-    stats, served Done records)."""
+    of cache misses, and analyses of graphs above alone_edges edges, on the
+    builder thread's stream; requests that find it idle run alone at once)
+    and through the one-at-a-time path, both with the same content-keyed
+    plan cache (or both without one).  Returns (served summary, plain
+    summary or None, server stats, served Done records)."""
     import torch
     from paper_2210_01465_amd import serve
     free, _ = torch.cuda.mem_get_info()
     budget = int(free * 0.5)
-    backend = serve.GpuBackend(ctx, async_builds=True)
-    srv = serve.Server(backend, hbm_budget=budget, cache_budget=None if cache else 0)
+    backend = serve.GpuBackend(ctx, sweeps_per_step=sweeps_per_step, async_builds=True)
+    srv = serve.Server(backend, hbm_budget=budget, cache_budget=None if cache else 0,
+                       alone_when_idle=alone_when_idle, alone_edges=alone_edges)
     done = srv.run(reqs)
     torch.cuda.synchronize()
     served = serve.latency_summary(done, since=warm)
+    paths = collections.Counter(d.path for d in done)
     stats = {"ffg_builds": int(srv.stats["built"]), "cache_hits": int(srv.stats["cache_hits"]),
-             "build_waits": int(srv.stats["build_waits"]), "peak_bytes": int(srv.peak_bytes)}
+             "build_waits": int(srv.stats["build_waits"]), "peak_bytes": int(srv.peak_bytes),
+             "paths": {k: int(paths[k]) for k in ("batch", "alone", "builder")}}
     srv.close()
     backend.close()
+    if not plain:
+        return served, None, stats, done
     pb = serve.GpuBackend(ctx)
     plain = serve.latency_summary(serve.serve_plain(pb, reqs, cache_budget=budget // 2 if cache else 0),
                                   since=warm)

@@ -17,6 +17,13 @@ arrive over time.  The server
 * adds admitted requests to one running batch (fl_batch_*): members join and
   leave between steps of a few sweeps, so short analyses are not held behind
   long ones;
+* runs a request alone, at once, on the single-space path (lagged step, no
+  batch bookkeeping) when it finds the server idle: no batch member running
+  and no other request waiting to start.  Under light load most requests
+  take this path and see the single-space latency; as soon as requests
+  overlap they batch.  Optionally (``alone_edges``), analyses of graphs above
+  that many edges run alone on the builder's stream beside the batch, so
+  short requests never wait behind them;
 * records, per request, the latency from arrival to a host-visible result;
 * keeps Python's cyclic garbage collector from running inside the loop (a
   full collection over the live request and tensor objects stalls the loop
@@ -25,9 +32,10 @@ arrive over time.  The server
 
 The GPU work goes through a backend object (``build``, ``plan_bytes``,
 ``member_bytes``, ``add``, ``step``, ``collect``, ``release``, plus ``plain``
-for the one-at-a-time reference path; a backend with ``async_builds`` set
-also has ``submit_build`` / ``submit_plain`` / ``poll``), so the scheduling
-logic can be exercised with any backend.
+for the one-at-a-time reference path; optionally ``alone`` (the idle fast
+path) and ``edges``; a backend with ``async_builds`` set also has
+``submit_build`` / ``submit_plain`` / ``poll``), so the scheduling logic can
+be exercised with any backend.
 """
 from __future__ import annotations
 
@@ -62,6 +70,7 @@ class Done:
     pagerank: Any
     minima: Any
     info: dict
+    path: str = "batch"     # batch | alone (idle fast path) | builder (alone on its stream) | plain
 
     @property
     def latency(self) -> float:
@@ -86,7 +95,8 @@ class _Builder:
     take, and plan releases for that context, one job at a time.  The engine
     calls release the interpreter lock, so its kernels run while the serving
     loop steps the batch on the first context's stream.  Fitness tensors
-    handed to it must have no pending writes."""
+    handed to it must have no pending writes.  ``lock`` is held while a job
+    runs; the serving thread takes it to use the builder's context itself."""
 
     def __init__(self, api, device: int):
         import torch
@@ -96,6 +106,7 @@ class _Builder:
         self.ctx = api.Context(device, self.stream)
         self.jobs: "queue.Queue" = queue.Queue()
         self.done: "queue.Queue" = queue.Queue()
+        self.lock = threading.Lock()
         self.thread = threading.Thread(target=self._run, name="ffg-builder", daemon=True)
         self.thread.start()
 
@@ -109,6 +120,7 @@ class _Builder:
                     return
                 kind, a, b = job
                 try:
+                    self.lock.acquire()
                     if kind == "build":
                         plan = self.api.plan_create(self.ctx, a.radix, a.fitness, a.neighbourhood)
                         self.done.put(("build", a, (plan, _batchable(plan)), None))
@@ -118,6 +130,8 @@ class _Builder:
                         a.close()
                 except Exception as e:          # handed to the serving loop, which raises it
                     self.done.put((kind, a if kind == "build" else b, None, e))
+                finally:
+                    self.lock.release()
 
     def close(self):
         self.jobs.put(None)
@@ -192,6 +206,26 @@ class GpuBackend:
         pr, mins, info = self.api.execute(plan, req.damping, req.p)
         return pr, mins, info
 
+    def alone(self, plan, req: Request):
+        """Run one request alone at once on the calling thread (the
+        single-space path), or return None when the plan's context is busy:
+        a plan built by the builder runs on the builder's context and stream,
+        which the builder must not be using."""
+        b = self.builder
+        if b is None or plan.ctx is not b.ctx:
+            return self.plain(plan, req)
+        if not b.lock.acquire(blocking=False):
+            return None
+        try:
+            import torch
+            with torch.cuda.stream(b.stream):
+                return self.plain(plan, req)
+        finally:
+            b.lock.release()
+
+    def edges(self, plan) -> int:
+        return int(plan.sizes["n_edges"])
+
     def release(self, plan) -> None:
         if self.builder is not None and plan.ctx is self.builder.ctx:
             self.builder.jobs.put(("release", plan, None))   # its context belongs to the builder thread
@@ -218,13 +252,21 @@ class Server:
     released when the last of them finishes.  Memory accounting: every
     admitted request reserves 16 n_raw bytes for its own iterates until it
     joins (then its member bytes), and a build in flight reserves the
-    estimated footprint of its FFG until the plan's own size is known."""
+    estimated footprint of its FFG until the plan's own size is known.
+
+    alone_when_idle: use the backend's ``alone`` (if it has one) for a
+    request that finds the server idle.  alone_edges: with an async backend,
+    analyses of plans above this many edges run alone on the builder instead
+    of joining the batch (None: never)."""
 
     def __init__(self, backend, hbm_budget: int, cache_budget: int | None = None,
                  clock: Callable[[], float] | None = None,
-                 sleep: Callable[[float], None] | None = None, pause_gc: bool = True):
+                 sleep: Callable[[float], None] | None = None, pause_gc: bool = True,
+                 alone_when_idle: bool = True, alone_edges: int | None = None):
         self.backend = backend
         self.async_builds = bool(getattr(backend, "async_builds", False))
+        self.alone_when_idle = bool(alone_when_idle) and hasattr(backend, "alone")
+        self.alone_edges = alone_edges if self.async_builds else None
         self.pause_gc = pause_gc
         self.hbm_budget = int(hbm_budget)
         self.cache_budget = int(cache_budget if cache_budget is not None else hbm_budget // 2)
@@ -266,10 +308,11 @@ class Server:
             n_raw *= int(r)
         return 16 * n_raw
 
-    def _admit(self, req: Request) -> bool:
+    def _admit(self, req: Request, alone_ok: bool = False) -> bool:
         """Reserve memory for the request and start it: join the batch at
         once on a cached (or owned) plan, wait for a build of its space that
-        is in flight, or start that build.  False leaves it queued."""
+        is in flight, or start that build.  False leaves it queued.
+        alone_ok: no other request is starting with it."""
         key = req.key
         hit = self.cache.get(key)
         known = hit is not None or key in self.owned or key in self.building
@@ -284,10 +327,10 @@ class Server:
         if hit is not None:
             self.cache.move_to_end(key)
             self.stats["cache_hits"] += 1
-            self._start(req, key, hit[0], hit[2], it_bytes)
+            self._start(req, key, hit[0], hit[2], it_bytes, alone_ok)
         elif key in self.owned:
             self.stats["cache_hits"] += 1
-            self._start(req, key, self.owned[key][0], self.owned[key][2], it_bytes)
+            self._start(req, key, self.owned[key][0], self.owned[key][2], it_bytes, alone_ok)
         elif key in self.building:
             self.stats["build_waits"] += 1
             self.building[key].append(req)
@@ -300,7 +343,7 @@ class Server:
             self.stats["built"] += 1
             plan, batchable = self.backend.build(req)
             self._store(key, plan, batchable)
-            self._start(req, key, plan, batchable, it_bytes)
+            self._start(req, key, plan, batchable, it_bytes, alone_ok)
         self.peak_bytes = max(self.peak_bytes, self._held())
         return True
 
@@ -326,10 +369,14 @@ class Server:
         else:
             self.in_use[key] = self.in_use.get(key, 0) + delta
 
-    def _start(self, req: Request, key, plan, batchable, it_bytes: int) -> None:
-        """Run an admitted request on its plan: as a batch member, or alone
-        when the batched sweep cannot take the space."""
+    def _start(self, req: Request, key, plan, batchable, it_bytes: int, alone_ok: bool = False) -> None:
+        """Run an admitted request on its plan: alone at once when it finds
+        the server idle (alone_ok and no batch member running), alone on the
+        builder when the batched sweep cannot take the space (or the graph
+        is above alone_edges), else as a batch member."""
         self._use(key, +1)
+        if batchable and self.alone_edges is not None and self.backend.edges(plan) > self.alone_edges:
+            batchable = False
         if not batchable:
             if self.async_builds:
                 self.plain_inflight += 1
@@ -338,23 +385,31 @@ class Server:
             else:
                 pr, mins, info = self.backend.plain(plan, req)
                 self.reserved -= it_bytes
-                self._finish(req, pr, mins, info)
+                self._finish(req, pr, mins, info, "plain")
                 self._use(key, -1)
             return
+        if alone_ok and self.alone_when_idle and len(self.running) == self.plain_inflight:
+            res = self.backend.alone(plan, req)
+            if res is not None:
+                self.stats["alone"] += 1
+                self.reserved -= it_bytes
+                self._finish(req, *res, "alone")
+                self._use(key, -1)
+                return
         mbytes = self.backend.member_bytes(plan)
         self.reserved += mbytes - it_bytes
         self.peak_bytes = max(self.peak_bytes, self._held())
         self.backend.add(plan, req)
         self.running[req.rid] = (req, key, mbytes)
 
-    def _end(self, rid, pr, mins, info) -> None:
+    def _end(self, rid, pr, mins, info, path: str = "batch") -> None:
         req, key, nbytes = self.running.pop(rid)
         self.reserved -= nbytes
-        self._finish(req, pr, mins, info)
+        self._finish(req, pr, mins, info, path)
         self._use(key, -1)
 
-    def _finish(self, req: Request, pr, mins, info) -> None:
-        self.done.append(Done(req.rid, req.arrival, self.clock(), float(info["score"]), pr, mins, info))
+    def _finish(self, req: Request, pr, mins, info, path: str) -> None:
+        self.done.append(Done(req.rid, req.arrival, self.clock(), float(info["score"]), pr, mins, info, path))
 
     def _poll_builder(self) -> None:
         for kind, req, res in self.backend.poll():
@@ -364,12 +419,13 @@ class Server:
                 waiting = self.building.pop(key)
                 self.building_bytes.pop(key)
                 self._store(key, plan, batchable)
+                lone = len(waiting) == 1 and not self.queue
                 for r in waiting:
-                    self._start(r, key, plan, batchable, self._iterate_estimate(r))
+                    self._start(r, key, plan, batchable, self._iterate_estimate(r), lone)
                 self.peak_bytes = max(self.peak_bytes, self._held())
             else:
                 self.plain_inflight -= 1
-                self._end(req.rid, *res)
+                self._end(req.rid, *res, "builder")
 
     # -- main loop ----------------------------------------------------------
     def run(self, requests, start: float | None = None) -> list:
@@ -395,8 +451,9 @@ class Server:
             if self.async_builds:
                 self._poll_builder()
             still = []
+            lone = len(self.queue) == 1
             for req in self.queue:
-                if not self._admit(_shift(req, t0)):
+                if not self._admit(_shift(req, t0), lone):
                     still.append(req)
             self.queue = still
             members = len(self.running) - self.plain_inflight
@@ -471,7 +528,7 @@ def serve_plain(backend, requests, clock: Callable[[], float] | None = None,
         pr, mins, info = backend.plain(plan, req)
         if req.key not in cache:
             backend.release(plan)
-        done.append(Done(req.rid, req.arrival + t0, clock(), float(info["score"]), pr, mins, info))
+        done.append(Done(req.rid, req.arrival + t0, clock(), float(info["score"]), pr, mins, info, "plain"))
     for plan, _ in cache.values():
         backend.release(plan)
     return done

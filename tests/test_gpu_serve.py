@@ -1,7 +1,9 @@
 """GPU: the continuous-batching server.  Every request's result equals the
-same analysis run alone (with the batch's separate step), whatever it shared
-the device with, and matches the
-FP64 oracle (minima exactly, ranks within 1e-5 in L1, C_p within 1e-5)."""
+same analysis run alone (batch members: with the batch's separate step;
+requests that found the server idle: the lagged single-space path),
+whatever it shared the device with, and matches the FP64 oracle (minima
+exactly, ranks within 1e-5 in L1, C_p within 1e-5)."""
+import collections
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -32,10 +34,19 @@ def test_served_equals_alone():
     done = {d.rid: d for d in srv.run(reqs)}
     assert sorted(done) == [r.rid for r in reqs]
     assert srv.stats["cache_hits"] > 0
-    for r in reqs[:40]:
+    paths = collections.Counter(d.path for d in done.values())
+    print(f"[case] paths {dict(paths)}", flush=True)
+    assert paths["alone"] > 0 and paths["batch"] > 0
+    picked = [r for r in reqs if done[r.rid].path == "batch"][:25] + \
+        [r for r in reqs if done[r.rid].path == "alone"][:25]
+    for r in picked:
         plan = api.plan_create(ctx, r.radix, r.fitness, "hamming")
-        pr, mins, info = api.execute(plan, r.damping, r.p, row_mapping=-1, separate_step=True)
-        assert np.array_equal(done[r.rid].pagerank.cpu().numpy(), pr.cpu().numpy())
+        if done[r.rid].path == "batch":
+            pr, mins, info = api.execute(plan, r.damping, r.p, row_mapping=-1, separate_step=True)
+        else:
+            pr, mins, info = api.execute(plan, r.damping, r.p)
+        assert np.array_equal(done[r.rid].pagerank.cpu().numpy(), pr.cpu().numpy()), (r.rid, done[r.rid].path)
+        assert np.array_equal(done[r.rid].minima.cpu().numpy(), mins.cpu().numpy())
         assert done[r.rid].score == info["score"]
         plan.close()
     summ = serve.latency_summary(list(done.values()))
@@ -81,7 +92,7 @@ def test_served_results_match_oracle(large_reference):
         reqs.append(serve.Request(t, len(times) + k, ("large", "hamming"), large.radix, large_fit,
                                   "hamming", d, 0.05))
     reqs.sort()
-    # a space too wide for the batched sweep (398 candidate slots) runs alone on the builder
+    # a space with 398 candidate slots per configuration (binned rows in the batch)
     wide = synth.Space("wide", (200, 3), rng.lognormal(0.0, 0.5, 600).astype(np.float32))
     wide_fit = torch.from_numpy(wide.fitness_raw).cuda()
     spaces.append(wide)
@@ -90,11 +101,13 @@ def test_served_results_match_oracle(large_reference):
                                   "hamming", 0.85, 0.05))
     reqs.sort()
     print(f"[case] serve {len(reqs)} requests ({len(spaces)} spaces + 2 large) against the oracle, "
-          f"FFG builds on the builder thread", flush=True)
+          f"FFG builds and graphs above 4 M edges on the builder thread", flush=True)
     backend = serve.GpuBackend(ctx, sweeps_per_step=8, async_builds=True)
-    srv = serve.Server(backend, hbm_budget=16 << 30)
+    srv = serve.Server(backend, hbm_budget=16 << 30, alone_edges=1 << 22)
     done = {d.rid: d for d in srv.run(reqs)}
     assert sorted(done) == sorted(r.rid for r in reqs)
+    print(f"[case] paths {dict(collections.Counter(d.path for d in done.values()))}", flush=True)
+    assert all((done[r.rid].path == "builder") == (r.key[0] == "large") for r in reqs)
     assert srv.stats["built"] == len({r.key for r in reqs})
     keys = sorted({(r.key[0], r.damping) for r in reqs if r.key[0] != "large"}, key=str)
 

@@ -184,6 +184,32 @@ class FakeAsyncBackend(FakeBackend):
         return super().step()
 
 
+class FakeIdleBackend(FakeBackend):
+    """With the idle fast path: ``alone`` runs the request at once."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.n_alone = 0
+
+    def alone(self, g, req):
+        assert not self.members                   # only when no batch member runs
+        self.n_alone += 1
+        return self.plain(g, req)
+
+
+class FakeAsyncIdleBackend(FakeAsyncBackend):
+    """Async builds plus the fast path, which (as with the real builder's
+    lock) is refused while a builder job is in flight."""
+
+    def alone(self, g, req):
+        if self.jobs:
+            return None
+        return self.plain(g, req)
+
+    def edges(self, g):
+        return g.E
+
+
 def _check_against_plain(reqs, done):
     assert sorted(done) == sorted(r.rid for r in reqs)
     for r in reqs:
@@ -234,3 +260,46 @@ def test_plain_path_with_the_same_cache():
     fresh = {d.rid: d for d in serve.serve_plain(fb2, reqs, clock=fb2.clock, sleep=fb2.sleep)}
     assert fb2.n_builds == len(reqs) and fb2.live_plans == 0
     assert {r.rid: cached[r.rid].score for r in reqs} == {r.rid: fresh[r.rid].score for r in reqs}
+
+
+def test_idle_requests_run_alone_and_bursts_batch():
+    """A request that finds the server idle runs alone at once; requests
+    that overlap join the batch.  Every result equals its plain result."""
+    light = make_requests(40, seed=11, rate=100.0)
+    fb = FakeIdleBackend()
+    srv = serve.Server(fb, hbm_budget=1 << 30, clock=fb.clock, sleep=fb.sleep)
+    done = {d.rid: d for d in srv.run(light)}
+    _check_against_plain(light, done)
+    assert srv.stats["alone"] == fb.n_alone == sum(d.path == "alone" for d in done.values())
+    assert srv.stats["alone"] >= 30 and srv.reserved == 0
+    burst = make_requests(60, seed=12, rate=50000.0)
+    fb = FakeIdleBackend()
+    srv = serve.Server(fb, hbm_budget=1 << 30, clock=fb.clock, sleep=fb.sleep)
+    done = {d.rid: d for d in srv.run(burst)}
+    _check_against_plain(burst, done)
+    assert fb.added_while_running > 0 and sum(d.path == "batch" for d in done.values()) > 30
+    assert srv.reserved == 0
+    fb = FakeIdleBackend()
+    srv = serve.Server(fb, hbm_budget=1 << 30, clock=fb.clock, sleep=fb.sleep, alone_when_idle=False)
+    done = srv.run(light)
+    assert fb.n_alone == 0 and {d.path for d in done} == {"batch"}
+
+
+def test_long_graphs_run_on_the_builder():
+    """With alone_edges, graphs above that many edges run alone on the
+    builder (beside the batch); the fast path waits for an idle builder."""
+    reqs = make_requests(60, seed=13, rate=5000.0)
+    fb = FakeAsyncIdleBackend(build_cost=3e-4)
+    graphs = {r.key: oracle.build_graph(r.radix, r.fitness) for r in reqs}
+    cut = int(np.median([g.E for g in graphs.values()]))
+    srv = serve.Server(fb, hbm_budget=1 << 30, clock=fb.clock, sleep=fb.sleep, alone_edges=cut)
+    done = {d.rid: d for d in srv.run(reqs)}
+    _check_against_plain(reqs, done)
+    for r in reqs:
+        long = graphs[r.key].E > cut
+        assert (done[r.rid].path == "builder") == long, (r.rid, done[r.rid].path)
+    assert any(d.path == "builder" for d in done.values())
+    assert any(d.path == "batch" for d in done.values())
+    assert not srv.running and srv.plain_inflight == 0 and srv.reserved == 0
+    srv.close()
+    assert fb.live_plans == 0
