@@ -560,10 +560,13 @@ def serving_stream(spaces, fits, large_space, large_fit, rate: float, seconds: f
 
 
 def serve_both(ctx, reqs, warm: float, cache: bool = True, alone_edges: int | None = SERVING_ALONE_EDGES,
-               alone_when_idle: bool = True, plain: bool = True, sweeps_per_step: int = 16):
+               alone_when_idle: bool = True, plain: bool = True, sweeps_per_step: int = 16,
+               alone_on_builder: bool = True):
     """One request stream through the continuous-batching server (FFG builds
     of cache misses, and analyses of graphs above alone_edges edges, on the
-    builder thread's stream; requests that find it idle run alone at once)
+    builder thread's stream; requests that find it idle run alone at once,
+    and with alone_on_builder a request the builder can take at once runs
+    alone there instead of joining the batch)
     and through the one-at-a-time path, both with the same content-keyed
     plan cache (or both without one).  Returns (served summary, plain
     summary or None, server stats, served Done records)."""
@@ -573,7 +576,8 @@ def serve_both(ctx, reqs, warm: float, cache: bool = True, alone_edges: int | No
     budget = int(free * 0.5)
     backend = serve.GpuBackend(ctx, sweeps_per_step=sweeps_per_step, async_builds=True)
     srv = serve.Server(backend, hbm_budget=budget, cache_budget=None if cache else 0,
-                       alone_when_idle=alone_when_idle, alone_edges=alone_edges)
+                       alone_when_idle=alone_when_idle, alone_edges=alone_edges,
+                       alone_on_builder=alone_on_builder, switch_interval=1e-4)
     done = srv.run(reqs)
     torch.cuda.synchronize()
     served = serve.latency_summary(done, since=warm)

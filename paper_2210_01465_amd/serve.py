@@ -23,7 +23,9 @@ arrive over time.  The server
   take this path and see the single-space latency; as soon as requests
   overlap they batch.  Optionally (``alone_edges``), analyses of graphs above
   that many edges run alone on the builder's stream beside the batch, so
-  short requests never wait behind them;
+  short requests never wait behind them, and (``alone_on_builder``) a
+  request that cannot run alone at once runs alone on the builder if it is
+  idle;
 * records, per request, the latency from arrival to a host-visible result;
 * keeps Python's cyclic garbage collector from running inside the loop (a
   full collection over the live request and tensor objects stalls the loop
@@ -43,6 +45,7 @@ import collections
 import gc
 import heapq
 import queue
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -257,16 +260,24 @@ class Server:
     alone_when_idle: use the backend's ``alone`` (if it has one) for a
     request that finds the server idle.  alone_edges: with an async backend,
     analyses of plans above this many edges run alone on the builder instead
-    of joining the batch (None: never)."""
+    of joining the batch (None: never).  alone_on_builder: with an async
+    backend, a request that cannot run alone at once runs alone on the
+    builder when the builder is idle, instead of joining the batch.
+    switch_interval: the interpreter's thread switch interval while ``run``
+    serves (None: unchanged); a short one lets the builder thread take the
+    interpreter lock soon after its job is queued."""
 
     def __init__(self, backend, hbm_budget: int, cache_budget: int | None = None,
                  clock: Callable[[], float] | None = None,
                  sleep: Callable[[float], None] | None = None, pause_gc: bool = True,
-                 alone_when_idle: bool = True, alone_edges: int | None = None):
+                 alone_when_idle: bool = True, alone_edges: int | None = None,
+                 alone_on_builder: bool = False, switch_interval: float | None = None):
         self.backend = backend
         self.async_builds = bool(getattr(backend, "async_builds", False))
         self.alone_when_idle = bool(alone_when_idle) and hasattr(backend, "alone")
         self.alone_edges = alone_edges if self.async_builds else None
+        self.alone_on_builder = bool(alone_on_builder) and self.async_builds
+        self.switch_interval = switch_interval
         self.pause_gc = pause_gc
         self.hbm_budget = int(hbm_budget)
         self.cache_budget = int(cache_budget if cache_budget is not None else hbm_budget // 2)
@@ -396,6 +407,12 @@ class Server:
                 self._finish(req, *res, "alone")
                 self._use(key, -1)
                 return
+        if self.alone_on_builder and self.plain_inflight == 0 and not self.building:
+            self.stats["alone_builder"] += 1
+            self.plain_inflight += 1
+            self.running[req.rid] = (req, key, it_bytes)
+            self.backend.submit_plain(plan, req)
+            return
         mbytes = self.backend.member_bytes(plan)
         self.reserved += mbytes - it_bytes
         self.peak_bytes = max(self.peak_bytes, self._held())
@@ -434,9 +451,13 @@ class Server:
         paused = self.pause_gc and gc.isenabled()
         if paused:
             gc.disable()
+        interval = sys.getswitchinterval()
+        if self.switch_interval is not None:
+            sys.setswitchinterval(self.switch_interval)
         try:
             return self._loop(requests, start)
         finally:
+            sys.setswitchinterval(interval)
             if paused:
                 gc.enable()
 

@@ -303,3 +303,23 @@ def test_long_graphs_run_on_the_builder():
     assert not srv.running and srv.plain_inflight == 0 and srv.reserved == 0
     srv.close()
     assert fb.live_plans == 0
+
+
+def test_idle_builder_takes_lone_requests():
+    """With alone_on_builder, a request that cannot run alone at once (a
+    batch is running) runs alone on the builder when it is idle; the switch
+    interval is restored after the run."""
+    import sys
+    reqs = make_requests(60, seed=14, rate=8000.0)
+    fb = FakeAsyncIdleBackend(build_cost=1e-4)
+    before = sys.getswitchinterval()
+    srv = serve.Server(fb, hbm_budget=1 << 30, clock=fb.clock, sleep=fb.sleep, alone_on_builder=True,
+                       switch_interval=1e-4)
+    done = {d.rid: d for d in srv.run(reqs)}
+    assert sys.getswitchinterval() == before
+    _check_against_plain(reqs, done)
+    paths = {d.path for d in done.values()}
+    assert "builder" in paths and srv.stats["alone_builder"] > 0
+    assert not srv.running and srv.plain_inflight == 0 and srv.reserved == 0
+    srv.close()
+    assert fb.live_plans == 0
