@@ -455,15 +455,19 @@ def batched_sweep_rate(ctx, spaces, fits, damping, p, tol, sweeps_per_step: int 
             tm = batch.timing()
             batch.close()
         torch.cuda.synchronize()
-        alg = 0
+        alg = spmv = 0
         for j, pl in enumerate(plans):
             sz = pl.sizes
-            alg += infos[j]["iterations"] * ((20 + 8 * int(sz["mask_words"])) * int(sz["n_valid"])
-                                             + 4 * int(sz["n_edges"]))
+            it, n, e = infos[j]["iterations"], int(sz["n_valid"]), int(sz["n_edges"])
+            alg += it * ((20 + 8 * int(sz["mask_words"])) * n + 4 * e)
+            spmv += it * (20 * n + 8 * e)
         gbs = alg / (tm["sweep_ms"] * 1e-3) / 1e9
+        spmv_gbs = spmv / (tm["sweep_ms"] * 1e-3) / 1e9
         out = {"members": len(plans), "sweeps": tm["sweeps"], "device_ms": round(tm["sweep_ms"], 3),
                "alg_bytes": int(alg), "alg_formula": "sum over members of iterations x ((20 + 8 W) N + 4 E)",
                "gb_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+               "spmv_bytes": int(spmv), "spmv_formula": "sum over members of iterations x (20 N + 8 E)",
+               "spmv_gb_per_s": round(spmv_gbs, 1), "spmv_frac_of_peak": round(spmv_gbs / HBM_PEAK_GBS, 4),
                "graph_launches": tm["graph_launches"], "graph_captures": tm["graph_captures"], "traffic": None}
         rec = traffic_record(LOOP_TRAFFIC_FILE, "+".join(LOOP_KERNELS))
         if rec:        # DRAM bytes of the same loop, from rocprofv3 counters

@@ -233,12 +233,59 @@ T *pool_alloc(fl_ctx *ctx, int64_t count) {
     return static_cast<T *>(ctx->pool.alloc(bytes));
 }
 
+// Several device buffers carved from one pool block in 256-byte aligned
+// pieces, so that a build stage or a batch member costs one pool operation
+// (a batched build of a few hundred spaces made thousands, about 0.1 us of
+// host time each).  The first piece is the block's base: releasing it
+// returns the block, and the pool ignores the other pieces' pointers.
+class Carve {
+  public:
+    template <typename T>
+    Carve &add(T *&dst, int64_t count) {
+        if (n_ < kMax) piece_[n_++] = {reinterpret_cast<void **>(&dst), sizeof(T) * (size_t)std::max<int64_t>(count, 1)};
+        else overflow_ = true;
+        return *this;
+    }
+    // false (every destination null) when the block cannot be had
+    bool take(fl_ctx *ctx) {
+        size_t total = 0;
+        for (int j = 0; j < n_; ++j) total += round(piece_[j].bytes);
+        char *base = overflow_ ? nullptr : pool_alloc<char>(ctx, (int64_t)total);
+        size_t off = 0;
+        for (int j = 0; j < n_; ++j) {
+            *piece_[j].dst = base ? base + off : nullptr;
+            off += round(piece_[j].bytes);
+        }
+        return base != nullptr;
+    }
+
+  private:
+    static size_t round(size_t b) { return (b + 255) / 256 * 256; }
+    static constexpr int kMax = 8;
+    struct Piece {
+        void **dst;
+        size_t bytes;
+    };
+    Piece piece_[kMax] = {};
+    int n_ = 0;
+    bool overflow_ = false;
+};
+
 void release_plan_buffers(fl_plan *p) {
     DevicePool &pool = p->ctx->pool;
     void *bufs[] = {p->valid_raw, p->out_deg, p->row_ptr, p->col_idx, p->minima,  p->fit_c,
                     p->rec,       p->presence, p->y[0], p->y[1],      p->y[2],     p->x[0],
                     p->x[1],      p->g,       p->partials, p->state,  p->d_off,    p->bin_rows};
     for (void *b : bufs) pool.release(b);
+}
+
+// A plan's buffers back to the pool and its events destroyed; the caller has
+// synchronised the stream that last used them.
+void plan_free(fl_plan *p) {
+    release_plan_buffers(p);
+    if (p->have_events)
+        for (auto &e : p->ev) (void)hipEventDestroy(e);
+    delete p;
 }
 
 // Lanes per row for the iteration sweep: about half the mean in-degree, so a
@@ -445,14 +492,14 @@ void build_begin(fl_ctx *ctx, Build &b, const fl_space *space, const float *fit,
     // tiles of the segmented build's three passes, or of one space's two
     const int64_t c_tiles = b.defer ? (n_raw + fl::kCompactTile - 1) / fl::kCompactTile
                                     : (n_raw + fl::kSingleTile - 1) / fl::kSingleTile;
-    b.remap = pool_alloc<int32_t>(ctx, n_raw);
-    b.tile_cnt = pool_alloc<int32_t>(ctx, c_tiles);
-    b.tile_bad = pool_alloc<int32_t>(ctx, c_tiles);
-    b.tile_min = pool_alloc<float>(ctx, c_tiles);
-    if (b.defer) b.tile_off = pool_alloc<int32_t>(ctx, c_tiles);
-    if (!b.shared_sizes) b.d_sizes = pool_alloc<BuildSizes>(ctx, 1);
-    p->valid_raw = pool_alloc<int32_t>(ctx, n_raw);
-    p->fit_c = pool_alloc<float>(ctx, n_raw);
+    // scratch (based at remap) and plan buffers (based at valid_raw), one block each
+    Carve scratch;
+    scratch.add(b.remap, n_raw).add(b.tile_cnt, c_tiles).add(b.tile_bad, c_tiles).add(b.tile_min, c_tiles);
+    if (b.defer) scratch.add(b.tile_off, c_tiles);
+    if (!b.shared_sizes) scratch.add(b.d_sizes, 1);
+    scratch.take(ctx);
+    Carve own;
+    own.add(p->valid_raw, n_raw).add(p->fit_c, n_raw).take(ctx);
     if (!b.remap || !b.tile_cnt || !b.tile_bad || (b.defer && !b.tile_off) || !b.tile_min || !b.d_sizes ||
         !p->valid_raw || !p->fit_c)
         return build_fail(b, FL_ENOMEM, "device allocation failed");
@@ -477,19 +524,17 @@ void build_degree(fl_ctx *ctx, Build &b) {
     p->n = n;
     p->f_opt = b.h_sizes->f_opt;
     const int64_t n_tiles = (n + fl::kBlock - 1) / fl::kBlock;
-    b.in_deg = pool_alloc<int32_t>(ctx, n);
-    b.tile_e = pool_alloc<int64_t>(ctx, n_tiles);
-    b.tile_eoff = pool_alloc<int64_t>(ctx, n_tiles);
-    b.tile_m = pool_alloc<int32_t>(ctx, n_tiles);
-    b.tile_moff = pool_alloc<int32_t>(ctx, n_tiles);
-    p->out_deg = pool_alloc<int32_t>(ctx, n);
-    p->row_ptr = pool_alloc<int32_t>(ctx, (int64_t)n + 1);
-    p->minima = pool_alloc<int32_t>(ctx, n);
+    // scratch (based at in_deg) and plan buffers (based at out_deg), one block each
+    Carve scratch;
+    scratch.add(b.in_deg, n).add(b.tile_e, n_tiles).add(b.tile_eoff, n_tiles).add(b.tile_m, n_tiles);
+    scratch.add(b.tile_moff, n_tiles).take(ctx);
+    Carve own;
+    own.add(p->out_deg, n).add(p->row_ptr, (int64_t)n + 1).add(p->minima, n);
     if (p->sl.words > 0) {
-        p->rec = pool_alloc<uint64_t>(ctx, (int64_t)n * p->sl.words);
-        p->presence = pool_alloc<uint64_t>(ctx, ((int64_t)n + 63) / 64 * p->sl.words);
-        p->d_off = pool_alloc<int32_t>(ctx, 2 * k_pad_of(p->sl));
+        own.add(p->rec, (int64_t)n * p->sl.words).add(p->presence, ((int64_t)n + 63) / 64 * p->sl.words);
+        own.add(p->d_off, 2 * k_pad_of(p->sl));
     }
+    own.take(ctx);
     if (!b.in_deg || !b.tile_e || !b.tile_eoff || !b.tile_m || !b.tile_moff || !p->out_deg || !p->row_ptr ||
         !p->minima || (p->sl.words > 0 && (!p->rec || !p->presence || !p->d_off)))
         return build_fail(b, FL_ENOMEM, "device allocation failed");
@@ -930,12 +975,11 @@ void member_release(fl_ctx *ctx, fl_batch::Member &m) {
 }
 
 fl_status member_alloc(fl_ctx *ctx, const fl_plan *p, fl_batch::Member &m) {
-    for (int j = 0; j < 2; ++j) {
-        m.y[j] = pool_alloc<float>(ctx, p->n);
-        m.x[j] = pool_alloc<float>(ctx, m.binned ? p->n : (p->n_raw + 3) / 4 * 4);
-    }
-    m.partials = pool_alloc<double>(ctx, 3 * std::max<int64_t>(tiles_of(p), m.binned ? p->bins.tiles : 0));
-    m.state = pool_alloc<PrState>(ctx, 1);
+    // one block, based at y[0]
+    const int64_t nx = m.binned ? p->n : (p->n_raw + 3) / 4 * 4;
+    Carve c;
+    c.add(m.y[0], p->n).add(m.y[1], p->n).add(m.x[0], nx).add(m.x[1], nx);
+    c.add(m.partials, 3 * std::max<int64_t>(tiles_of(p), m.binned ? p->bins.tiles : 0)).add(m.state, 1).take(ctx);
     if (!m.y[0] || !m.y[1] || !m.x[0] || !m.x[1] || !m.partials || !m.state) {
         member_release(ctx, m);
         return fail(ctx, FL_ENOMEM, "device allocation failed");
@@ -1363,10 +1407,7 @@ fl_status fl_plan_destroy(fl_ctx *ctx, fl_plan *p) {
     if (p->ctx != ctx) return fail(ctx, FL_EINVAL, "plan belongs to another context");
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    release_plan_buffers(p);
-    if (p->have_events)
-        for (auto &e : p->ev) (void)hipEventDestroy(e);
-    delete p;
+    plan_free(p);
     return FL_OK;
 }
 
@@ -2331,8 +2372,10 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
         fl_batch_destroy(ctx, b);
         ctx->analyze_batch = nullptr;
     }
+    // one synchronisation for all the call's plans
+    (void)hipStreamSynchronize(s);
     for (auto &bd : builds)
-        if (bd.p) fl_plan_destroy(ctx, bd.p);
+        if (bd.p) plan_free(bd.p);
     ctx->err = msg;
     if (st != FL_OK) return st;
     for (int32_t j = 0; j < n_spaces; ++j)
