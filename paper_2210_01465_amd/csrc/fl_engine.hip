@@ -156,6 +156,7 @@ struct fl_ctx {
     fl_batch *analyze_batch = nullptr;  // kept by fl_analyze_batch between calls (empty between calls)
     // pinned tables of the segmented build (fl_analyze_batch), grown on demand
     fl::SegBuild *h_segs = nullptr;
+    BuildSizes *h_seg_sizes = nullptr;  // the spaces' sizes, copied back once per stage
     fl::SegTile *h_seg_tiles = nullptr;
     int32_t *h_seg_ids = nullptr;
     int32_t seg_cap = 0;
@@ -1019,12 +1020,15 @@ fl_status seg_tables_reserve(fl_ctx *ctx, int32_t segs, int64_t tiles) {
     if (segs > ctx->seg_cap) {
         (void)hipHostFree(ctx->h_segs);
         (void)hipHostFree(ctx->h_seg_ids);
+        (void)hipHostFree(ctx->h_seg_sizes);
         ctx->h_segs = nullptr;
         ctx->h_seg_ids = nullptr;
+        ctx->h_seg_sizes = nullptr;
         ctx->seg_cap = 0;
         const int32_t cap = std::max(segs, 64);
         if (hipHostMalloc((void **)&ctx->h_segs, sizeof(fl::SegBuild) * cap, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&ctx->h_seg_ids, sizeof(int32_t) * cap, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc((void **)&ctx->h_seg_ids, sizeof(int32_t) * cap, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->h_seg_sizes, sizeof(BuildSizes) * cap, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return FL_ENOMEM;
         }
@@ -1130,6 +1134,7 @@ fl_status fl_destroy(fl_ctx *ctx) {
     (void)hipHostFree(ctx->h_segs);
     (void)hipHostFree(ctx->h_seg_tiles);
     (void)hipHostFree(ctx->h_seg_ids);
+    (void)hipHostFree(ctx->h_seg_sizes);
     ctx->pool.release_all();
     for (hipEvent_t e : ctx->sweep_ev) (void)hipEventDestroy(e);
     (void)hipHostFree(ctx->h_sizes);
@@ -2124,15 +2129,13 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
     int32_t *d_ids = nullptr;
     fl::SegTile *d_tiles = nullptr;
     if (n_spaces > 0) {
-        if (hipHostMalloc((void **)&h_sizes, sizeof(BuildSizes) * n_spaces, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(ctx, FL_ENOMEM, "pinned allocation failed");
-        }
+        // pinned tables (the sizes among them) kept by the context between calls
+        if (seg_tables_reserve(ctx, n_spaces, 0) != FL_OK) return fail(ctx, FL_ENOMEM, "pinned allocation failed");
+        h_sizes = ctx->h_seg_sizes;
         d_sizes = pool_alloc<BuildSizes>(ctx, n_spaces);
         d_segs = pool_alloc<fl::SegBuild>(ctx, n_spaces);
         d_ids = pool_alloc<int32_t>(ctx, n_spaces);
-        if (!d_sizes || !d_segs || !d_ids || seg_tables_reserve(ctx, n_spaces, 0) != FL_OK) {
-            (void)hipHostFree(h_sizes);
+        if (!d_sizes || !d_segs || !d_ids) {
             ctx->pool.release(d_sizes);
             ctx->pool.release(d_segs);
             ctx->pool.release(d_ids);
@@ -2287,7 +2290,6 @@ fl_status fl_analyze_batch(fl_ctx *ctx, int32_t n_spaces, const fl_space *spaces
         if (he != hipSuccess && bd.status == FL_OK) build_fail(bd, FL_EHIP, "%s", hipGetErrorString(he));
         build_end(ctx, bd);
     }
-    (void)hipHostFree(h_sizes);
     ctx->pool.release(d_sizes);
     ctx->pool.release(d_segs);
     ctx->pool.release(d_ids);
