@@ -381,10 +381,11 @@ class Server:
             self.in_use[key] = self.in_use.get(key, 0) + delta
 
     def _start(self, req: Request, key, plan, batchable, it_bytes: int, alone_ok: bool = False) -> None:
-        """Run an admitted request on its plan: alone at once when it finds
-        the server idle (alone_ok and no batch member running), alone on the
-        builder when the batched sweep cannot take the space (or the graph
-        is above alone_edges), else as a batch member."""
+        """Run an admitted request on its plan: alone on the builder when the
+        batched sweep cannot take the space (or the graph is above
+        alone_edges); alone at once when it finds the server idle (alone_ok
+        and no batch member running); alone on the idle builder with
+        alone_on_builder; else as a batch member."""
         self._use(key, +1)
         if batchable and self.alone_edges is not None and self.backend.edges(plan) > self.alone_edges:
             batchable = False
