@@ -76,10 +76,7 @@ typedef struct {
  *   max_iter  iteration cap (0 => 1000); reaching it gives FL_ENOCONV.
  *   row_mapping  layout of the PageRank sweep: 0 = automatic (the layout
  *             fl_tune cached for the plan's shape class, else FL_ROWS_SLOTS
- *             where available, else FL_ROWS_BINNED; fl_execute runs a slot
- *             space of at most 1 024 nodes in one workgroup, all sweeps in
- *             one launch, with the ranks of FL_ROWS_SLOTS and
- *             FL_STEP_SEPARATE bit for bit);
+ *             where available, else FL_ROWS_BINNED);
  *             FL_ROWS_SLOTS = one node per lane over the in-edge slot
  *             records (needs at most 256 candidate slots per node);
  *             FL_ROWS_BINNED = the CSR with rows binned by in-degree into

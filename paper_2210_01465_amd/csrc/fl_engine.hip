@@ -1209,17 +1209,6 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
         const auto hit = ctx->tuned.find(shape_key(p));
         if (hit != ctx->tuned.end()) lanes = hit->second;
     }
-    // With the automatic layout a slot space whose tiles fit one round of the
-    // one-workgroup sweep (4 tiles, 1 024 nodes) runs all its sweeps in one
-    // launch instead of one per sweep, with a step after every sweep: the
-    // order of FL_STEP_SEPARATE.  Larger spaces sweep their tiles in
-    // parallel workgroups faster than one workgroup does in several rounds.
-    const bool small = !exact && prm->row_mapping == 0 && p->sl.words > 0 && x_bytes_of(p) > 0 &&
-                       tiles_of(p) <= fl::kFinishBlock / fl::kBlock;
-    if (small) {
-        lanes = FL_ROWS_SLOTS;
-        r.lag = false;
-    }
     FL_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     PrArgs a;
@@ -1248,13 +1237,7 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
     double iterate_ms = 0.0, sweep_ms = 0.0;
     PrState *hs = ctx->h_state;
     int sampled = 0;
-    if (small) {
-        if (timed) FL_HIP(hipEventRecord(p->ev[5], s));
-        FL_HIP(fl::launch_pr_small(a, p->sl.words, r.max_iter + 1, s));
-        if (timed) FL_HIP(hipEventRecord(p->ev[6], s));
-        launches = 1;
-    }
-    for (; !small;) {
+    for (;;) {
         if (profile_every > 0 && (int)ctx->sweep_ev.size() < 2 * chunk) {
             for (int j = (int)ctx->sweep_ev.size(); j < 2 * chunk; ++j) {
                 hipEvent_t e;
@@ -1305,7 +1288,6 @@ fl_status execute_impl(fl_ctx *ctx, fl_plan *p, const fl_params *prm, double *d_
     if (timed) FL_HIP(hipEventRecord(p->ev[4], s));
     FL_HIP(hipMemcpyAsync(hs, p->state, sizeof(PrState), hipMemcpyDeviceToHost, s));
     FL_HIP(hipStreamSynchronize(s));
-    if (small && timed) iterate_ms = elapsed(p->ev[5], p->ev[6]);
 
     p->timing.pagerank_ms = timed ? elapsed(p->ev[2], p->ev[3]) : 0.0;
     p->timing.score_ms = timed ? elapsed(p->ev[3], p->ev[4]) : 0.0;

@@ -265,11 +265,6 @@ hipError_t launch_fill(const SpaceDesc &sp, const SlotTable &sl, int adjacent, c
                        const int32_t *out_deg, const int64_t *tile_eoff, const int32_t *tile_moff,
                        int32_t *row_ptr, int32_t *col_idx, int32_t *minima, hipStream_t stream);
 hipError_t launch_pr_init(const PrArgs &a, int grid, hipStream_t stream);
-// A slot-layout space of at most kSmallTiles tiles (buffer-load form, plain
-// power iteration with a step per sweep) iterated to its end, or to
-// max_sweeps sweeps, in one workgroup; its state and first iterate as
-// launch_pr_init (lag = 0) leaves them.
-hipError_t launch_pr_small(const PrArgs &a, int words, int32_t max_sweeps, hipStream_t stream);
 hipError_t launch_pr_iter(const PrArgs &a, const SpaceDesc &sp, const SlotTable &sl, int lanes,
                           int grid, hipStream_t stream);
 // The two halves of launch_pr_iter: the sweep kernel, then the step kernel.

@@ -1945,89 +1945,76 @@ __global__ __launch_bounds__(kFinishBlock) void k_batch_finish(const BatchMember
 // the workgroup through LDS, so every wave takes the same branches.
 constexpr int kGroups = kFinishBlock / kBlock;
 
-// One member, all its sweeps (up to max_sweeps) inside the calling
-// workgroup of kFinishBlock threads.
 template <int W>
-__device__ __forceinline__ void small_member(const_ptr<BatchMember> m, int32_t max_sweeps) {
+__global__ __launch_bounds__(kFinishBlock) void k_batch_small(const BatchMember *__restrict__ members,
+                                                              const int32_t *__restrict__ member_ids,
+                                                              int32_t n_members, int32_t max_sweeps) {
     __shared__ double part[kGroups][3][kBlock / 64];
     __shared__ int32_t sh_done, sh_k;
     __shared__ double sh_s, sh_c;
     const int g = threadIdx.x / kBlock, lt = threadIdx.x % kBlock;
     const int lane = threadIdx.x & 63, wl = lt >> 6;
-    PrState *st = m->st;
-    for (int32_t sweep = 0; sweep < max_sweeps; ++sweep) {
-        if (threadIdx.x == 0) {
-            sh_done = st->done;
-            sh_k = st->k;
-            sh_s = st->s;
-            sh_c = st->c;
-        }
-        __syncthreads();
-        if (sh_done) break;               // uniform
-        const int32_t k = sh_k;
-        SweepTile q;
-        q.rec = m->rec;
-        q.off = to_const(m->off);
-        q.y_in = m->y[k & 1];
-        q.x_in = m->x[k & 1];
-        q.y_out = m->y[(k + 1) & 1];
-        q.x_out = m->x[(k + 1) & 1];
-        q.partials = m->partials;
-        q.s = sh_s;
-        q.c = sh_c;
-        q.sd = q.s * m->d;
-        q.n = m->n;
-        q.k_slots = m->k_slots;
-        q.k_pad = m->k_pad;
-        q.x_bytes = m->x_bytes;
-        const int32_t n_tiles = m->n_tiles;
-        for (int32_t t0 = 0; t0 < n_tiles; t0 += kGroups) {
-            const int32_t tile = t0 + g;      // a group past the last tile only joins the barriers
-            double ps = 0.0, pr = 0.0, pk = 0.0;
-            if (tile < n_tiles) sweep_tile_sums<W, true>(q, tile, lt, ps, pr, pk);
-            ps = wave_sum(ps);
-            pr = wave_sum(pr);
-            pk = wave_sum(pk);
-            if (lane == 0) {
-                part[g][0][wl] = ps;
-                part[g][1][wl] = pr;
-                part[g][2][wl] = pk;
+    for (int32_t j = blockIdx.x; j < n_members; j += gridDim.x) {
+        const_ptr<BatchMember> m = to_const(members) + member_ids[j];
+        PrState *st = m->st;
+        for (int32_t sweep = 0; sweep < max_sweeps; ++sweep) {
+            if (threadIdx.x == 0) {
+                sh_done = st->done;
+                sh_k = st->k;
+                sh_s = st->s;
+                sh_c = st->c;
             }
             __syncthreads();
-            if (lt == 0 && tile < n_tiles) {
-                double a = part[g][0][0], b = part[g][1][0], c = part[g][2][0];
-#pragma unroll
-                for (int w = 1; w < kBlock / 64; ++w) {
-                    a += part[g][0][w];
-                    b += part[g][1][w];
-                    c += part[g][2][w];
+            if (sh_done) break;               // uniform
+            const int32_t k = sh_k;
+            SweepTile q;
+            q.rec = m->rec;
+            q.off = to_const(m->off);
+            q.y_in = m->y[k & 1];
+            q.x_in = m->x[k & 1];
+            q.y_out = m->y[(k + 1) & 1];
+            q.x_out = m->x[(k + 1) & 1];
+            q.partials = m->partials;
+            q.s = sh_s;
+            q.c = sh_c;
+            q.sd = q.s * m->d;
+            q.n = m->n;
+            q.k_slots = m->k_slots;
+            q.k_pad = m->k_pad;
+            q.x_bytes = m->x_bytes;
+            const int32_t n_tiles = m->n_tiles;
+            for (int32_t t0 = 0; t0 < n_tiles; t0 += kGroups) {
+                const int32_t tile = t0 + g;      // a group past the last tile only joins the barriers
+                double ps = 0.0, pr = 0.0, pk = 0.0;
+                if (tile < n_tiles) sweep_tile_sums<W, true>(q, tile, lt, ps, pr, pk);
+                ps = wave_sum(ps);
+                pr = wave_sum(pr);
+                pk = wave_sum(pk);
+                if (lane == 0) {
+                    part[g][0][wl] = ps;
+                    part[g][1][wl] = pr;
+                    part[g][2][wl] = pk;
                 }
-                double *pp = m->partials + 3 * (int64_t)tile;
-                pp[0] = a;
-                pp[1] = b;
-                pp[2] = c;
+                __syncthreads();
+                if (lt == 0 && tile < n_tiles) {
+                    double a = part[g][0][0], b = part[g][1][0], c = part[g][2][0];
+#pragma unroll
+                    for (int w = 1; w < kBlock / 64; ++w) {
+                        a += part[g][0][w];
+                        b += part[g][1][w];
+                        c += part[g][2][w];
+                    }
+                    double *pp = m->partials + 3 * (int64_t)tile;
+                    pp[0] = a;
+                    pp[1] = b;
+                    pp[2] = c;
+                }
+                __syncthreads();                  // part is reused; the partials are visible
             }
-            __syncthreads();                  // part is reused; the partials are visible
+            finish_step(st, m->partials, n_tiles, m->d, m->tol, m->max_iter, m->n, false);
         }
-        finish_step(st, m->partials, n_tiles, m->d, m->tol, m->max_iter, m->n, false);
+        __syncthreads();                          // sh_* are rewritten for the next member
     }
-    __syncthreads();                              // sh_* are rewritten for the next member
-}
-
-template <int W>
-__global__ __launch_bounds__(kFinishBlock) void k_batch_small(const BatchMember *__restrict__ members,
-                                                              const int32_t *__restrict__ member_ids,
-                                                              int32_t n_members, int32_t max_sweeps) {
-    for (int32_t j = blockIdx.x; j < n_members; j += gridDim.x)
-        small_member<W>(to_const(members) + member_ids[j], max_sweeps);
-}
-
-// A single space of at most kSmallTiles tiles iterated to the end in one
-// workgroup (fl_execute): the descriptor is the kernel's first argument,
-// read in place in the kernel-argument segment.
-template <int W>
-__global__ __launch_bounds__(kFinishBlock) void k_pr_small([[maybe_unused]] BatchMember arg, int32_t max_sweeps) {
-    small_member<W>(kernel_arg<BatchMember>(), max_sweeps);
 }
 
 // Ranks r = y * s into the member's output for every listed tile.
@@ -2556,39 +2543,6 @@ hipError_t launch_batch_small(const BatchMember *members, const int32_t *member_
     if (n_members <= 0 || max_sweeps <= 0) return hipSuccess;
     void *args[] = {(void *)&members, (void *)&member_ids, (void *)&n_members, (void *)&max_sweeps};
     return hipLaunchKernel(fn, dim3(grid), dim3(kFinishBlock), args, 0, stream);
-}
-
-hipError_t launch_pr_small(const PrArgs &a, int words, int32_t max_sweeps, hipStream_t stream) {
-    const void *fn = nullptr;
-    switch (words) {
-        case 1: fn = (const void *)k_pr_small<1>; break;
-        case 2: fn = (const void *)k_pr_small<2>; break;
-        case 3: fn = (const void *)k_pr_small<3>; break;
-        case 4: fn = (const void *)k_pr_small<4>; break;
-        case 5: fn = (const void *)k_pr_small<5>; break;
-        default: return hipErrorInvalidValue;
-    }
-    if ((a.n + kBlock - 1) / kBlock > kSmallTiles || a.x_bytes <= 0 || a.lag || a.exact) return hipErrorInvalidValue;
-    BatchMember m{};
-    m.rec = a.rec;
-    m.off = a.off;
-    m.y[0] = a.y[0];
-    m.y[1] = a.y[1];
-    m.x[0] = a.x[0];
-    m.x[1] = a.x[1];
-    m.partials = a.partials;
-    m.st = a.st;
-    m.d = a.d;
-    m.tol = a.tol;
-    m.n = a.n;
-    m.k_slots = a.k_slots;
-    m.k_pad = a.k_pad;
-    m.words = words;
-    m.x_bytes = a.x_bytes;
-    m.n_tiles = (a.n + kBlock - 1) / kBlock;
-    m.max_iter = a.max_iter;
-    void *args[] = {(void *)&m, (void *)&max_sweeps};
-    return hipLaunchKernel(fn, dim3(1), dim3(kFinishBlock), args, 0, stream);
 }
 
 hipError_t launch_batch_finish(const BatchMember *members, const int32_t *member_ids, const int32_t *n_members_dev,

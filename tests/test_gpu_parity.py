@@ -352,42 +352,6 @@ def test_iteration_cap_reports_noconv(ctx):
     assert np.array_equal(mins, g.minima)
 
 
-def test_small_spaces_run_in_one_workgroup(ctx):
-    """With the automatic layout a slot space of at most 4 tiles (1 024
-    nodes) runs all its sweeps in one launch.  Its results equal, bit for bit, the run with
-    one sweep launch and one step kernel per iteration (FL_STEP_SEPARATE on
-    the slot layout), match the oracle, and max_iter still caps it."""
-    import torch
-    from paper_2210_01465_amd import api, _abi
-    cases = [synth.tiny(s) for s in range(4)]
-    cases += [s for s in (synth.fuzz_space(j, max_params=5, max_radix=6) for j in range(12))
-              if 0 < s.n_valid <= 1024]
-    n_small = 0
-    for s in cases:
-        for nb in ("hamming", "adjacent"):
-            say(f"one-workgroup path {s.name} radix={s.radix} {nb}")
-            plan = api.plan_create(ctx, s.radix, torch.from_numpy(s.fitness_raw).cuda(), nb)
-            try:
-                if int(plan.sizes["mask_words"]) == 0:
-                    continue
-                pr, mins, info = api.execute(plan, 0.85, 0.05)
-                assert api.plan_timing(plan)["launches"] == 1
-                ref, rmins, rinfo = api.execute(plan, 0.85, 0.05, row_mapping=ROWS_SLOTS, separate_step=True)
-                assert api.plan_timing(plan)["launches"] > 1
-                assert np.array_equal(pr.cpu().numpy(), ref.cpu().numpy())
-                assert np.array_equal(mins.cpu().numpy(), rmins.cpu().numpy())
-                assert info["score"] == rinfo["score"] and info["iterations"] == rinfo["iterations"]
-                g = oracle.build_graph(s.radix, s.fitness_raw, NB[nb])
-                r, _, _ = g.pagerank(0.85, 1e-13)
-                assert float(np.abs(pr.cpu().numpy() - r).sum()) <= L1_TOL
-                _, _, capped = api.execute(plan, 0.85, 0.05, max_iter=3, allow_noconv=True)
-                assert capped["status"] == _abi.FL_ENOCONV and capped["iterations"] == 3
-                n_small += 1
-            finally:
-                plan.close()
-    assert n_small >= 8
-
-
 def test_analyze_one_shot(ctx):
     import torch
     from paper_2210_01465_amd import api
