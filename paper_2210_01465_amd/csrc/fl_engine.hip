@@ -908,7 +908,6 @@ struct fl_batch {
     std::vector<Member> members;
     std::vector<int> free_slots;
     int capacity = 0;
-    int64_t member_tiles_total = 0;   // member_tiles summed over members
     fl::BatchMember *d_members = nullptr, *h_members = nullptr;
     fl::TileRef *d_tiles = nullptr, *h_tiles = nullptr;  // regions: init | sweep | output
     int64_t tile_cap = 0;
@@ -1785,7 +1784,9 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
     fl_batch::Member m;
     m.plan = p;
     m.binned = binned;
-    st = batch_reserve(b, (int)b->members.size() + 1, b->member_tiles_total + member_tiles(m));
+    int64_t tiles = 0;
+    for (const auto &q : b->members) tiles += member_tiles(q);
+    st = batch_reserve(b, (int)b->members.size() + 1, tiles + member_tiles(m));
     if (st != FL_OK) return st;
     st = member_alloc(ctx, p, m);
     if (st != FL_OK) return st;
@@ -1836,7 +1837,6 @@ fl_status fl_batch_add(fl_ctx *ctx, fl_batch *b, fl_plan *p, const fl_params *pr
         bm.bin_rows = p->bin_rows;
         bm.bins = p->bins;
     }
-    b->member_tiles_total += member_tiles(m);
     b->members.push_back(m);
     return FL_OK;
 }
@@ -2060,24 +2060,20 @@ fl_status fl_batch_collect(fl_ctx *ctx, fl_batch *b, int32_t max, int64_t *tags,
     ctx->err.clear();
     if (!b || b->ctx != ctx || !n_out || max < 0 || (max > 0 && (!tags || !out)))
         return fail(ctx, FL_EINVAL, "bad argument");
-    // one pass: finished members (up to max) leave, the others keep their order
     int32_t n = 0;
-    size_t keep = 0;
-    for (size_t q = 0; q < b->members.size(); ++q) {
+    for (size_t q = 0; q < b->members.size() && n < max;) {
         fl_batch::Member &m = b->members[q];
-        if (m.phase == 2 && n < max) {
-            tags[n] = m.tag;
-            out[n] = m.sum;
-            ++n;
-            member_release(ctx, m);   // the step that finished it synchronised the stream
-            b->free_slots.push_back(m.slot);
-            b->member_tiles_total -= member_tiles(m);
+        if (m.phase != 2) {
+            ++q;
             continue;
         }
-        if (keep != q) b->members[keep] = b->members[q];
-        ++keep;
+        tags[n] = m.tag;
+        out[n] = m.sum;
+        ++n;
+        member_release(ctx, m);   // the step that finished it synchronised the stream
+        b->free_slots.push_back(m.slot);
+        b->members.erase(b->members.begin() + (long)q);
     }
-    b->members.resize(keep);
     *n_out = n;
     return FL_OK;
 }
