@@ -1852,6 +1852,19 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
     fl::TileRef *t_init = b->h_tiles, *t_sweep = b->h_tiles + tc, *t_out = b->h_tiles + 2 * tc;
     int32_t *i_init = b->h_ids, *i_run = b->h_ids + b->capacity, *i_fin = b->h_ids + 2 * b->capacity;
 
+    // the lists below must fit the pinned tables (each region holds tile_cap
+    // tile references and capacity ids); checked before anything is written
+    {
+        int64_t t_join = 0, t_run = 0;
+        for (const auto &m : b->members) {
+            if (m.phase == 0) t_join += tiles_of(m.plan);
+            if (m.phase <= 1) t_run += std::max<int64_t>(tiles_of(m.plan), m.binned ? m.plan->bins.tiles : 0);
+        }
+        if (t_join > tc || t_run > tc || (int64_t)b->members.size() > b->capacity)
+            return fail(ctx, FL_EINVAL, "batch tables hold %lld tiles and %d members: %lld joining tiles, %lld "
+                        "running tiles, %zu members", (long long)tc, b->capacity, (long long)t_join,
+                        (long long)t_run, b->members.size());
+    }
     // host lists: joining members and their tiles, running members and
     // their tiles grouped by record width
     int32_t n_init = 0;
@@ -2025,6 +2038,7 @@ fl_status fl_batch_step(fl_ctx *ctx, fl_batch *b, int32_t sweeps, int32_t *n_run
         for (size_t q = 0; q < b->members.size(); ++q) {
             if (b->members[q].slot != i_run[j]) continue;
             fl_batch::Member &m = b->members[q];
+            if (nt_fin + tiles_of(m.plan) > tc) return fail(ctx, FL_EINVAL, "batch tables: output tiles overflow");
             i_fin[n_fin++] = m.slot;
             fin_index.push_back((int)q);
             for (int32_t t = 0; t < tiles_of(m.plan); ++t) t_out[nt_fin++] = {m.slot, t};
