@@ -723,10 +723,10 @@ def main():
                          "for the profiler's byte counters")
     ap.add_argument("--traffic-copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--traffic-command", default="")
-    ap.add_argument("--no-sweep-events", action="store_true",
-                    help="time the steps without sweep events (roofline then from chunk events)")
-    ap.add_argument("--sweep-event-every", type=int, default=8,
-                    help="bracket every n-th sweep launch with HIP events during the timed steps")
+    ap.add_argument("--sweep-event-every", type=int, default=0, metavar="N",
+                    help="bracket every N-th sweep launch of the timed steps with its own HIP events and "
+                         "take the roofline's launch time from those (0, the default: from the events "
+                         "around each chunk of back-to-back sweep launches)")
     args = ap.parse_args()
 
     if args.traffic_from:
@@ -797,7 +797,7 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    if not args.no_sweep_events:
+    if args.sweep_event_every > 0:
         api.profile(ctx, args.sweep_event_every)
     torch.cuda.synchronize()
     infos, timings = [], []
@@ -815,10 +815,15 @@ def main():
     N, E, M = info["n_valid"], info["n_edges"], info["n_minima"]
     edges = sum(i["n_edges"] * i["iterations"] for i in infos)
     gteps = edges / wall / 1e9
-    if args.no_sweep_events:        # chunk time over launches: includes the step kernels
-        avg_launch_s = sum(t["iterate_ms"] for t in timings) / 1e3 / sum(t["launches"] for t in timings)
-    else:                           # sweep kernels that did work, each between its own events
+    if args.sweep_event_every > 0:  # sweep kernels that did work, each between its own events
         avg_launch_s = sum(t["sweep_ms"] for t in timings) / 1e3 / sum(t["sweeps_timed"] for t in timings)
+    else:
+        # events around each chunk of back-to-back sweep launches (the lagged
+        # step launches no other kernel between them), over the sweeps that
+        # did work: iterations + 2 per analysis (the step, and with it the
+        # stop test, runs one sweep late, and one more sweep sees the stop)
+        avg_launch_s = (sum(t["iterate_ms"] for t in timings) / 1e3
+                        / sum(i["iterations"] + 2 for i in infos))
     # the PageRank SpMV's algorithmic bytes per iteration: y in, y out, x out,
     # out_deg, row_ptr (4 N each) and col_idx plus the x gathers (4 E each)
     bytes_per_launch = 20 * N + 8 * E
@@ -875,7 +880,10 @@ def main():
                          "achieved_trace": traffic_rec.get("dram_gb_per_s"),
                          "frac_trace": (round(traffic_rec["dram_gb_per_s"] / HBM_PEAK_GBS, 4)
                                         if traffic_rec.get("dram_gb_per_s") else None)},
-                     "timing": "chunk events / launches" if args.no_sweep_events
+                     "timing": ("HIP events on the engine's stream around each chunk of back-to-back sweep "
+                                "launches of the timed steps, over the sweeps that did work "
+                                f"({sum(i['iterations'] + 2 for i in infos)})")
+                               if args.sweep_event_every <= 0
                                else f"HIP events around every {args.sweep_event_every}th sweep launch "
                                     f"of the timed steps ({sum(t['sweeps_timed'] for t in timings)} "
                                     f"working launches)"},
